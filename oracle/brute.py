@@ -1,0 +1,46 @@
+"""Brute-force connectivity matrix in numpy -- TEST INFRASTRUCTURE ONLY.
+
+Second, independent CPU implementation of the FastCod pass-through matrix
+(Section 2 "Method", Alg. 2), for tiny inputs.  It forms, per streamline l,
+the dense 0/1 vectors h_l in {0,1}^N (ROI rows passed through) and
+g_l in {0,1}^M (target labels passed through) and sums their outer products:
+C = sum_l h_l g_l^T.  Voxels are looked up as roi[z, y, x] with 3-D indexing,
+never through a linear index, so a mistake in the C oracle's index formula
+cannot be repeated here.  All coordinate arithmetic stays in float32.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def brute_voxel(p, dims, scale: float = 1.0):
+    """(x, y, z) voxel of each point of p [K,3] and a mask of points inside the grid."""
+    p = np.asarray(p, dtype=np.float32).reshape(-1, 3)
+    with np.errstate(invalid="ignore", over="ignore"):
+        q = p * np.float32(scale)
+        f = np.floor(q + np.float32(0.5))
+        dims_f = np.asarray(dims, dtype=np.float64)
+        inside = np.all(f >= 0, axis=1) & np.all(f.astype(np.float64) < dims_f, axis=1)
+    v = np.zeros((p.shape[0], 3), dtype=np.int64)
+    v[inside] = f[inside].astype(np.int64)
+    return v, inside
+
+
+def brute_count(points, offsets, roi, lab, N: int, M: int, scale: float = 1.0) -> np.ndarray:
+    points = np.asarray(points, dtype=np.float32).reshape(-1, 3)
+    offsets = np.asarray(offsets, dtype=np.int64)
+    roi = np.asarray(roi, dtype=np.int32)
+    lab = np.asarray(lab, dtype=np.int32)
+    Z, Y, X = roi.shape
+    C = np.zeros((N, M), dtype=np.int64)
+    for s in range(offsets.shape[0] - 1):
+        v, inside = brute_voxel(points[offsets[s]:offsets[s + 1]], (X, Y, Z), scale)
+        v = v[inside]
+        r = roi[v[:, 2], v[:, 1], v[:, 0]]
+        m = lab[v[:, 2], v[:, 1], v[:, 0]]
+        h = np.zeros(N, dtype=np.int64)
+        g = np.zeros(M, dtype=np.int64)
+        h[r[(r >= 0) & (r < N)]] = 1
+        g[m[(m >= 0) & (m < M)]] = 1
+        C += np.outer(h, g)
+    return C

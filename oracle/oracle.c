@@ -1,0 +1,138 @@
+/*
+ * Connectivity-counting oracle -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, obviously correct CPU implementation of the pass-through
+ * connectivity matrix of FastCod (Bian, Shao, Zhuo, Gullapalli, Carass, Prince,
+ * "FastCod: Fast Brain Connectivity in Diffusion Imaging", SPIE Medical Imaging
+ * 2023).  Only the test suite, the package smoke check and the benchmark's CPU
+ * baseline may call it.  The product path (the HIP library) never links, loads
+ * or calls anything in this directory, and this file includes nothing from it.
+ *
+ * What is computed (Section 2 "Method", Alg. 2 with its passthrough and
+ * loc2region functions and the C update; the abstract and Section 1 state the
+ * reading used here: two regions are connected when one streamline passes
+ * through both, wherever it starts or ends):
+ *
+ *   A streamline l is an ordered list of 3-D points p^1..p^T (Section 2).
+ *   vox(p)  = ( floor(fl32(p_x + 0.5)), floor(fl32(p_y + 0.5)), floor(fl32(p_z + 0.5)) )
+ *             with voxel centres at integer coordinates; a point whose voxel lies
+ *             outside the X*Y*Z grid (or has a NaN/inf coordinate) touches nothing.
+ *   I_l     = { roi[vox(p)] : p in l, vox(p) in grid, 0 <= roi[vox(p)] < N }
+ *   M_l     = { lab[vox(p)] : p in l, vox(p) in grid, 0 <= lab[vox(p)] < M }
+ *   C[i][m] = #{ l : i in I_l and m in M_l }          (C is N x M, row i = voxel v_i)
+ *
+ * Volumes are stored [Z][Y][X] with x fastest: lin = x + X*(y + Y*z).
+ * With a coordinate scale s (the super-resolution transform of Section 3,
+ * "Super-resolving connectivity features"), every coordinate is first replaced
+ * by fl32(p * s); s = 1 leaves the points unchanged.
+ *
+ * Readings taken where the paper is silent (rounding, out-of-grid points,
+ * repeated visits, values outside [0,N) / [0,M)) are listed in the design notes
+ * of the repository; each one is exercised by a test.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fno-fast-math -shared -fPIC (no FMA
+ * contraction, so p*s and +0.5 are two separately rounded float operations).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* Linear voxel index of one point, or -1 when the point touches no voxel of the grid. */
+int64_t oracle_voxel(float px, float py, float pz, float scale, const int32_t dims[3])
+{
+    float p[3] = {px, py, pz};
+    int64_t v[3];
+    for (int k = 0; k < 3; ++k) {
+        float q = p[k] * scale;        /* fl32(p * s); exact when s == 1 */
+        float t = q + 0.5f;            /* fl32(q + 0.5), round to nearest even */
+        float f = floorf(t);
+        /* NaN fails both comparisons; the bound is compared in double so that
+           grid sizes above 2^24 are still exact. */
+        if (!(f >= 0.0f) || !((double)f < (double)dims[k]))
+            return -1;
+        v[k] = (int64_t)f;
+    }
+    return v[0] + (int64_t)dims[0] * (v[1] + (int64_t)dims[1] * v[2]);
+}
+
+static int cmp_i32(const void *a, const void *b)
+{
+    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
+}
+
+/* Sort and drop repeats; returns the number of distinct values. */
+static int64_t sort_unique(int32_t *v, int64_t n)
+{
+    if (n == 0)
+        return 0;
+    qsort(v, (size_t)n, sizeof(int32_t), cmp_i32);
+    int64_t k = 1;
+    for (int64_t j = 1; j < n; ++j)
+        if (v[j] != v[k - 1])
+            v[k++] = v[j];
+    return k;
+}
+
+/*
+ * Pass-through connectivity matrix.
+ *   points  [P][3] float32, streamline s = points[offsets[s] .. offsets[s+1])
+ *   offsets [S+1] int64, offsets[0] = 0, nondecreasing
+ *   roi, lab [Z][Y][X] int32 volumes, dims = {X, Y, Z}
+ *   C       [N][M] int64, overwritten
+ * Returns 0, or -1 on bad arguments / out of memory.
+ */
+int oracle_count(const float *points, const int64_t *offsets, int64_t S,
+                 const int32_t *roi, const int32_t *lab, const int32_t dims[3],
+                 int32_t N, int32_t M, float scale, int64_t *C)
+{
+    if (S < 0 || N < 1 || M < 1 || !C || !dims)
+        return -1;
+    memset(C, 0, sizeof(int64_t) * (size_t)N * (size_t)M);
+
+    int64_t cap = 0;
+    int32_t *I = NULL, *L = NULL;
+    for (int64_t s = 0; s < S; ++s) {
+        int64_t a = offsets[s], b = offsets[s + 1];
+        int64_t T = b - a;
+        if (T <= 0)
+            continue;                       /* an empty streamline touches nothing */
+        if (T > cap) {
+            free(I);
+            free(L);
+            cap = T;
+            I = (int32_t *)malloc(sizeof(int32_t) * (size_t)cap);
+            L = (int32_t *)malloc(sizeof(int32_t) * (size_t)cap);
+            if (!I || !L) {
+                free(I);
+                free(L);
+                return -1;
+            }
+        }
+        /* passthrough(l, V) and loc2region(p, R) for every point of l */
+        int64_t nI = 0, nL = 0;
+        for (int64_t j = a; j < b; ++j) {
+            const float *p = points + 3 * j;
+            int64_t lin = oracle_voxel(p[0], p[1], p[2], scale, dims);
+            if (lin < 0)
+                continue;
+            int32_t r = roi[lin];
+            int32_t m = lab[lin];
+            if (r >= 0 && r < N)
+                I[nI++] = r;
+            if (m >= 0 && m < M)
+                L[nL++] = m;
+        }
+        /* the sets I_l and M_l: each distinct value once */
+        nI = sort_unique(I, nI);
+        nL = sort_unique(L, nL);
+        /* C(i, m) += 1 for every i in I_l and m in M_l */
+        for (int64_t x = 0; x < nI; ++x)
+            for (int64_t y = 0; y < nL; ++y)
+                C[(int64_t)I[x] * M + L[y]] += 1;
+    }
+    free(I);
+    free(L);
+    return 0;
+}

@@ -1,0 +1,114 @@
+"""Planted mistakes in the oracle must be caught by its pins.
+
+Each mutant is a copy of oracle/oracle.c with one plausible mistake (a dropped term, a
+wrong bound, a transposed operand or index, a missing set operation), compiled with gcc
+into a temporary library.  The pin battery (golden toy case, rounding facts, closed-form
+lines, brute force, scale) must reject every mutant and accept the unmodified source.
+Mutants only ever write inside C's N*M entries, so none of them can corrupt memory.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import brute
+from paper_2302_09247_amd import synth
+from tests import _cases
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "oracle.c")
+
+MUTANTS = {
+    "no_half_offset": ("float t = q + 0.5f;", "float t = q;"),
+    "round_half_away": ("float f = floorf(t);", "float f = roundf(q);"),
+    "upper_bound_inclusive": ("!((double)f < (double)dims[k])", "!((double)f <= (double)dims[k])"),
+    "drops_voxel_zero": ("if (!(f >= 0.0f)", "if (!(f > 0.0f)"),
+    "transposed_volume_layout": ("return v[0] + (int64_t)dims[0] * (v[1] + (int64_t)dims[1] * v[2]);",
+                                 "return v[2] + (int64_t)dims[2] * (v[1] + (int64_t)dims[1] * v[0]);"),
+    "no_roi_dedupe": ("nI = sort_unique(I, nI);", "(void)0;"),
+    "no_label_dedupe": ("nL = sort_unique(L, nL);", "(void)0;"),
+    "transposed_C": ("C[(int64_t)I[x] * M + L[y]] += 1;", "C[(int64_t)L[y] * N + I[x]] += 1;"),
+    "skips_last_point": ("for (int64_t j = a; j < b; ++j) {", "for (int64_t j = a; j < b - 1; ++j) {"),
+    "endpoint_label_only": ("if (m >= 0 && m < M)\n                L[nL++] = m;",
+                            "if (m >= 0 && m < M && j == b - 1)\n                L[nL++] = m;"),
+    "drops_row_zero": ("if (r >= 0 && r < N)", "if (r > 0 && r < N)"),
+    "first_label_only": ("for (int64_t y = 0; y < nL; ++y)", "for (int64_t y = 0; y < nL && y < 1; ++y)"),
+    "ignores_scale": ("float q = p[k] * scale;", "float q = p[k];"),
+    "uses_x_bound_everywhere": ("!((double)f < (double)dims[k])", "!((double)f < (double)dims[0])"),
+}
+
+
+def _build(src_text, tmp_path, name):
+    c = tmp_path / f"{name}.c"
+    so = tmp_path / f"{name}.so"
+    c.write_text(src_text)
+    subprocess.check_call(["gcc", *oracle.CFLAGS, "-o", str(so), str(c), "-lm"])
+    lib = ctypes.CDLL(str(so))
+    lib.oracle_voxel.restype = ctypes.c_int64
+    lib.oracle_voxel.argtypes = [ctypes.c_float] * 4 + [ctypes.c_void_p]
+    lib.oracle_count.restype = ctypes.c_int
+    lib.oracle_count.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                 ctypes.c_float, ctypes.c_void_p]
+    return lib
+
+
+def _count(lib, points, offsets, roi, lab, N, M, scale=1.0):
+    p = np.ascontiguousarray(points, np.float32)
+    o = np.ascontiguousarray(offsets, np.int64)
+    r = np.ascontiguousarray(roi, np.int32)
+    lb = np.ascontiguousarray(lab, np.int32)
+    d = np.array(r.shape[::-1], np.int32)
+    C = np.zeros((N, M), np.int64)
+    ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)   # noqa: E731
+    assert lib.oracle_count(ptr(p), ptr(o), o.shape[0] - 1, ptr(r), ptr(lb), ptr(d), N, M,
+                            float(np.float32(scale)), ptr(C)) == 0
+    return C
+
+
+def _battery(lib):
+    """Names of the failed pins (empty = every pin passed)."""
+    failed = []
+    g = _cases.load_golden("toy_two_streamlines.json")
+    if not np.array_equal(_count(lib, g["points"], g["offsets"], g["roi"], g["lab"], g["N"], g["M"]), g["C"]):
+        failed.append("golden")
+    for value, X, exp in _cases.ROUNDING_PINS:
+        for axis in range(3):
+            dims = [3, 3, 3]
+            dims[axis] = X
+            p = [1.0, 1.0, 1.0]
+            p[axis] = value
+            v = [1, 1, 1]
+            v[axis] = exp
+            want = -1 if exp < 0 else v[0] + dims[0] * (v[1] + dims[1] * v[2])
+            d = np.array(dims, np.int32)
+            if lib.oracle_voxel(*[float(np.float32(c)) for c in p], 1.0, d.ctypes.data_as(ctypes.c_void_p)) != want:
+                failed.append(f"rounding {value}")
+    lab_of = lambda M: (lambda x, y, z: ((x + 2 * y + 3 * z) % (M + 1)) - 1)   # noqa: E731
+    for origin, step, T, dims, M in [((0.25, 2.0, 1.0), (0.5, 0.0, 0.0), 23, (13, 4, 3), 4),
+                                     ((0.125, 0.375, 0.0625), (0.25, 0.25, 0.25), 40, (11, 12, 13), 6)]:
+        pts, off, roi, lab, N, M, Cexp = _cases.line_case(origin, step, T, dims, M, lab_of(M))
+        if not np.array_equal(_count(lib, pts, off, roi, lab, N, M), Cexp):
+            failed.append(f"line {origin}")
+    for seed in range(4):
+        w = synth.random_small(seed, N=(None if seed % 2 else 6), bad_values=True)
+        args = (w.points.numpy(), w.offsets.numpy(), w.roi.numpy(), w.lab.numpy(), w.N, w.M)
+        for scale in (1.0, 1.7857143):
+            if not np.array_equal(_count(lib, *args, scale=scale), brute.brute_count(*args, scale=scale)):
+                failed.append(f"brute {seed} {scale}")
+    return failed
+
+
+def test_unmodified_oracle_passes_battery(tmp_path):
+    assert _battery(_build(open(SRC).read(), tmp_path, "orig")) == []
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) >= 1, f"mutation site for {name} not found in oracle.c"
+    failed = _battery(_build(src.replace(old, new, 1), tmp_path, name))
+    assert failed, f"planted mistake {name} was not caught by any pin"
