@@ -1,0 +1,142 @@
+/*
+ * fastcod.h -- C-ABI of libfastcod.so: pass-through connectivity counting on MI355X (gfx950).
+ *
+ * The operation (FastCod, Bian et al., SPIE Medical Imaging 2023; Section 2 "Method", Alg. 2:
+ * passthrough, loc2region and the update of C; the abstract and Section 1 define two regions as
+ * connected when a streamline passes through both, wherever it starts or ends):
+ *
+ *   A streamline l is an ordered list of points p^1..p^T in voxel coordinates (voxel centres at
+ *   integers).  Each point lies in voxel ( floor(fl32(x+0.5)), floor(fl32(y+0.5)), floor(fl32(z+0.5)) )
+ *   -- one IEEE binary32 add rounded to nearest even, then an exact floor; a point whose voxel is
+ *   outside the grid, or with a NaN/inf coordinate, touches nothing.
+ *   I_l = distinct ROI rows roi[v] in [0,N) over the voxels v of l,
+ *   M_l = distinct target labels lab[v] in [0,M) over the voxels v of l,
+ *   C[i][m] = number of streamlines l with i in I_l and m in M_l.
+ *   With a coordinate scale s (the super-resolution transform of Section 3, "Super-resolving
+ *   connectivity features"), every coordinate is first replaced by fl32(p*s).
+ *
+ * Conventions for every entry point:
+ *   - Pointers are DEVICE pointers unless marked HOST.  The caller owns every buffer it passes;
+ *     the library never frees caller memory.
+ *   - Volumes are int32 [Z][Y][X], x fastest: lin = x + X*(y + Y*z).  Values outside [0,N)
+ *     (ROI) or [0,M) (labels) mean "no ROI" / "no target" (-1 is the usual choice).
+ *   - Streamlines: points float32 [P][3] (x,y,z interleaved); offsets int64 [S+1] with
+ *     offsets[0] = 0, nondecreasing, offsets[S] = P; streamline s is points[offsets[s], offsets[s+1]).
+ *     Kernels clamp every offset into [0, offsets[S]], so malformed offsets give wrong counts but
+ *     never a read outside points[0, offsets[S]).  FASTCOD_VALIDATE checks them first.
+ *   - Argument errors are detected synchronously, before anything is enqueued, and return
+ *     FASTCOD_EINVAL.  HIP failures return FASTCOD_EHIP.  fastcod_last_error() gives the detail
+ *     (thread-local).  No C++ exception crosses this interface.
+ *   - Counting calls are asynchronous on `stream` (a hipStream_t; NULL = the null stream):
+ *     results are valid once the stream is synchronised.  Calls on one stream are serialised by
+ *     the stream; the library keeps a workspace per (device, stream) and grows it with hipMalloc
+ *     on first use (that growth synchronises the device).
+ *   - C is int32; one call adds at most S to any entry, and S <= INT32_MAX is enforced.
+ */
+#ifndef FASTCOD_H
+#define FASTCOD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define FASTCOD_OK 0
+#define FASTCOD_EINVAL (-1)    /* bad argument (null pointer, size out of range, overflow)        */
+#define FASTCOD_ERANGE (-2)    /* FASTCOD_VALIDATE / fastcod_validate found malformed input data   */
+#define FASTCOD_ENOMEM (-3)    /* device allocation failed, or a request exceeds a memory budget   */
+#define FASTCOD_EHIP (-4)      /* a HIP runtime call failed                                        */
+#define FASTCOD_EBUSY (-5)     /* the object is in use (e.g. server still has requests in flight)  */
+#define FASTCOD_ECANCELED (-6) /* the request was cancelled                                        */
+#define FASTCOD_ETIMEDOUT (-7) /* a wait ended before the request finished                         */
+
+/* fastcod_opts.flags */
+#define FASTCOD_ACCUMULATE 1u  /* add into C_out instead of overwriting it                         */
+#define FASTCOD_VALIDATE 2u    /* run fastcod_validate first (synchronous); ERANGE if it fails      */
+
+/* fastcod_opts.variant: which counting kernel runs (all give identical C). */
+#define FASTCOD_VARIANT_AUTO 0   /* the library's choice (the flat point-stream kernel)            */
+#define FASTCOD_VARIANT_WAVE 1   /* one wavefront per streamline, raster volume lookups            */
+#define FASTCOD_VARIANT_STREAM 2 /* flat point stream split at streamline starts, compact volume   */
+
+typedef struct fastcod_opts {
+    float scale;        /* coordinate scale s applied before voxelisation; 1.0f = none              */
+    int32_t upsample;   /* must be 1 (points are used as given)                                     */
+    uint32_t flags;     /* FASTCOD_ACCUMULATE | FASTCOD_VALIDATE                                    */
+    int32_t variant;    /* FASTCOD_VARIANT_*                                                        */
+    void *event_begin;  /* optional hipEvent_t, recorded on `stream` just before the counting kernel */
+    void *event_end;    /* optional hipEvent_t, recorded on `stream` just after it                  */
+} fastcod_opts;
+
+/* Default options: {1.0f, 1, 0, FASTCOD_VARIANT_AUTO, NULL, NULL}. */
+fastcod_opts fastcod_default_opts(void);
+
+/*
+ * Pass-through connectivity matrix (Section 2, Alg. 2), overwriting C_out.
+ *   points           [P][3] float32, device
+ *   offsets          [S+1] int64, device
+ *   n_streamlines    S, 0 <= S <= INT32_MAX
+ *   roi_index_vol    [Z][Y][X] int32, device; value in [0,N) = row of C
+ *   target_label_vol [Z][Y][X] int32, device; value in [0,M) = column of C
+ *   dims             HOST int32[3] = {X, Y, Z}, each >= 1, X*Y*Z < 2^31
+ *   N, M             >= 1, N*M < 2^31
+ *   C_out            [N][M] int32 row-major, device; overwritten
+ *   stream           hipStream_t (NULL = null stream)
+ * Returns FASTCOD_OK once all work is enqueued.
+ */
+int fastcod_count(const float *points, const int64_t *offsets, int64_t n_streamlines,
+                  const int32_t *roi_index_vol, const int32_t *target_label_vol,
+                  const int32_t dims[3], int32_t N, int32_t M, int32_t *C_out, void *stream);
+
+/* Same as fastcod_count with options (NULL opts = defaults). */
+int fastcod_count_ex(const float *points, const int64_t *offsets, int64_t n_streamlines,
+                     const int32_t *roi_index_vol, const int32_t *target_label_vol,
+                     const int32_t dims[3], int32_t N, int32_t M, int32_t *C_out,
+                     const fastcod_opts *opts, void *stream);
+
+/*
+ * Resident volume: the two label volumes of one grid, preprocessed once into a compact
+ * lookup structure (an occupancy bit per voxel in 16x8x8 bricks plus the packed (row, label)
+ * codes of occupied voxels) that stays in device memory.  Section 2's loc2region and
+ * passthrough then read a few MB instead of both volumes.  The source volumes may be freed
+ * after creation.  The handle is ready for use on any stream once `stream` has completed
+ * the build; counting calls made through it wait for that build automatically.
+ */
+typedef struct fastcod_volume fastcod_volume;
+
+int fastcod_volume_create(const int32_t *roi_index_vol, const int32_t *target_label_vol,
+                          const int32_t dims[3], int32_t N, int32_t M, void *stream,
+                          fastcod_volume **out);
+/* Device bytes held by the handle. */
+size_t fastcod_volume_bytes(const fastcod_volume *vol);
+/* Counting against a resident volume; arguments as fastcod_count_ex. */
+int fastcod_volume_count(const fastcod_volume *vol, const float *points, const int64_t *offsets,
+                         int64_t n_streamlines, int32_t *C_out, const fastcod_opts *opts,
+                         void *stream);
+/* Frees the handle (synchronises its device first). */
+int fastcod_volume_destroy(fastcod_volume *vol);
+
+/*
+ * Input check (synchronous): offsets[0] == 0 and nondecreasing, ROI values < N and label
+ * values < M wherever they are >= 0.  Returns FASTCOD_OK or FASTCOD_ERANGE (detail in
+ * fastcod_last_error).
+ */
+int fastcod_validate(const int64_t *offsets, int64_t n_streamlines, const int32_t *roi_index_vol,
+                     const int32_t *target_label_vol, const int32_t dims[3], int32_t N, int32_t M,
+                     void *stream);
+
+/* Static description of a status code. */
+const char *fastcod_strerror(int status);
+/* Detail of the last failing call on this thread ("" if none). */
+const char *fastcod_last_error(void);
+/* Frees every cached workspace (synchronises the devices that own them). */
+int fastcod_release(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FASTCOD_H */

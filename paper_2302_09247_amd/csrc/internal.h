@@ -1,0 +1,97 @@
+// Internal declarations shared by the kernels and the host side of libfastcod.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fc {
+
+constexpr int kWave = 64;
+constexpr int kWavesPerBlock = 4;               // 256-thread workgroups
+constexpr int kBlock = kWave * kWavesPerBlock;
+constexpr int kSetCap = 512;                    // LDS hash slots per wavefront (load <= 1/2)
+
+// Exclusive upper bounds of t = fl32(q + 0.5) per axis: the smallest float >= the grid size,
+// so that `t < bound` holds exactly when floor(t) < size, also for sizes above 2^24.
+struct Grid {
+    int32_t X, Y, Z;
+    float Xf, Yf, Zf;
+};
+
+// Raster lookup straight from the caller's volumes.
+struct RasterVol {
+    const int32_t *roi;
+    const int32_t *lab;
+    int32_t X, XY;
+    int32_t N, M;
+};
+
+// Compact lookup: occupancy bits in 16x8x8 super-bricks (one 128-byte line per super-brick,
+// 32 words of 32 voxels), per-word exclusive prefix counts, and one code per occupied voxel.
+struct CompactVol {
+    const uint32_t *mask;     // [W] occupancy words
+    const uint32_t *base;     // [W] occupied voxels before this word
+    const uint32_t *codes32;  // packed (row | label << rbits), if packed
+    const int2 *codes64;      // (row, label) pairs, if not packed
+    int32_t SBX, SBXY;        // super-bricks along x, and per z-slab
+    int32_t rbits;            // bits of the row field in a packed code
+    uint32_t rmask;           // (1 << rbits) - 1
+    int32_t N, M;
+    int32_t packed;
+};
+
+// Streamlines whose distinct (row, label) keys outgrow the per-wave LDS set are handed to a
+// fallback kernel through this queue of point indices (one point inside each such streamline).
+struct Overflow {
+    unsigned long long *count;
+    int64_t *list;
+    int64_t cap;
+};
+
+// Per-workgroup scratch of the fallback kernel; bit maps are all-zero between launches.
+struct FallbackScratch {
+    uint32_t *words;      // [blocks][stride]: N-bit map, M-bit map, M-entry label list
+    int64_t stride;
+    int32_t blocks;
+    int32_t nwordsN, nwordsM;
+};
+
+struct CountArgs {
+    const float *pts;
+    const int64_t *offsets;
+    int64_t S;
+    Grid g;
+    float scale;
+    int32_t *C;
+    int32_t M;
+    Overflow ovf;
+};
+
+// ---- launchers (kernels.hip); every launcher returns the hipError_t of its launch ----
+hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, int cus, hipStream_t st);
+hipError_t launch_fill_u64(unsigned long long *p, int64_t n, int cus, hipStream_t st);
+
+// compact volume build: mask must hold W words, tile_sums ceil(W / kScanTile) words
+constexpr int kScanTile = 2048;
+hipError_t launch_compact_build(const int32_t *roi, const int32_t *lab, Grid g, int32_t N, int32_t M,
+                                CompactVol cv, uint32_t *mask, uint32_t *base, void *codes,
+                                uint32_t *tile_sums, int64_t W, int cus, hipStream_t st);
+
+// point-balanced chunks: Q = max(kChunkPoints, ceil(P / kMaxChunks)) points, at most kMaxChunks
+constexpr int64_t kChunkPoints = 4096;
+constexpr int64_t kMaxChunks = int64_t(1) << 20;
+hipError_t launch_partition(const int64_t *offsets, int64_t S, int32_t *first /* [kMaxChunks+1] */, int cus,
+                            hipStream_t st);
+
+hipError_t launch_count_wave(const CountArgs &a, const RasterVol &rv, int blocks, hipStream_t st);
+hipError_t launch_count_stream(const CountArgs &a, const CompactVol &cv, const int32_t *first, int blocks,
+                               hipStream_t st);
+hipError_t launch_fallback_raster(const CountArgs &a, const RasterVol &rv, FallbackScratch fs,
+                                  hipStream_t st);
+hipError_t launch_fallback_compact(const CountArgs &a, const CompactVol &cv, FallbackScratch fs,
+                                   hipStream_t st);
+
+hipError_t launch_validate(const int64_t *offsets, int64_t S, const int32_t *roi, const int32_t *lab,
+                           int64_t nvox, int32_t N, int32_t M, int32_t *flags, int cus, hipStream_t st);
+
+}  // namespace fc

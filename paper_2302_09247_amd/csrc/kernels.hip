@@ -1,0 +1,686 @@
+// Device code of libfastcod.so (gfx950, wave64): pass-through connectivity counting.
+//
+// The operation is FastCod's Alg. 2 (Section 2, "Method"): for every streamline, the set of ROI
+// rows it passes through (passthrough) and the set of target labels it passes through
+// (loc2region applied to its points) are formed, and every (row, label) pair of the two sets adds
+// one to C.  The stages here:
+//   * compact volume build: one read of both volumes -> occupancy bits + packed codes;
+//   * partition: point-balanced chunks of whole streamlines (a binary search per chunk);
+//   * count kernels (wave-per-streamline over raster volumes, or flat point stream over the
+//     compact volume): voxelise each point, look it up, de-duplicate the hits of each streamline
+//     in a per-wavefront LDS hash set, and add its |I| x |M| pairs into C with global atomics;
+//   * fallback: streamlines with more distinct keys than the LDS set holds, one workgroup each,
+//     with global bit maps.
+// Integer counting is exact and atomics commute, so every variant gives the same C.
+#include "internal.h"
+
+namespace fc {
+
+constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+constexpr uint32_t kLabelTag = 0x80000000u;
+
+__device__ __forceinline__ int64_t clamp64(int64_t v, int64_t lo, int64_t hi) {
+    return v < lo ? lo : (v > hi ? hi : v);
+}
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+
+// number of set bits of m below this lane
+__device__ __forceinline__ int mbcnt(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ uint64_t lanes_between(int lo, int hi) {  // bits [lo, hi)
+    const uint64_t below_hi = hi >= 64 ? ~0ull : ((1ull << hi) - 1ull);
+    return below_hi & ~((1ull << lo) - 1ull);
+}
+
+__device__ __forceinline__ float load_stream(const float *p) { return __builtin_nontemporal_load(p); }
+
+// Voxel of one point: per axis t = fl32(fl32(p*s) + 0.5) and floor(t), inside iff 0 <= t < size.
+// (floor(t) >= 0 iff t >= 0, and floor(t) < size iff t < size; NaN fails both.)  __fmul_rn /
+// __fadd_rn are never contracted into an FMA.
+template <bool SCALED>
+__device__ __forceinline__ bool voxelise(float x, float y, float z, float s, const Grid &g, int &ix,
+                                         int &iy, int &iz) {
+    if (SCALED) {
+        x = __fmul_rn(x, s);
+        y = __fmul_rn(y, s);
+        z = __fmul_rn(z, s);
+    }
+    const float tx = __fadd_rn(x, 0.5f), ty = __fadd_rn(y, 0.5f), tz = __fadd_rn(z, 0.5f);
+    const bool in = (tx >= 0.0f) & (tx < g.Xf) & (ty >= 0.0f) & (ty < g.Yf) & (tz >= 0.0f) & (tz < g.Zf);
+    ix = in ? (int)tx : 0;  // truncation == floor for t >= 0
+    iy = in ? (int)ty : 0;
+    iz = in ? (int)tz : 0;
+    return in;
+}
+
+// ---------------------------------------------------------------------------------------------
+// volume lookups
+// ---------------------------------------------------------------------------------------------
+
+__device__ __forceinline__ void raster_get(const RasterVol &v, int ix, int iy, int iz, int &r, int &m) {
+    const int lin = ix + v.X * iy + v.XY * iz;
+    const int rv = v.roi[lin], mv = v.lab[lin];
+    r = (unsigned)rv < (unsigned)v.N ? rv : -1;
+    m = (unsigned)mv < (unsigned)v.M ? mv : -1;
+}
+
+__device__ __forceinline__ uint32_t compact_word(const CompactVol &c, int ix, int iy, int iz, uint32_t &bit) {
+    const uint32_t sb = (uint32_t)(ix >> 4) + (uint32_t)c.SBX * (uint32_t)(iy >> 3) +
+                        (uint32_t)c.SBXY * (uint32_t)(iz >> 3);
+    const uint32_t b = (uint32_t)(ix & 15) | ((uint32_t)(iy & 7) << 4) | ((uint32_t)(iz & 7) << 7);
+    bit = b & 31u;
+    return (sb << 5) | (b >> 5);
+}
+
+__device__ __forceinline__ void compact_decode(const CompactVol &c, uint32_t word, uint32_t bit, uint32_t mw,
+                                               int &r, int &m) {
+    const uint32_t rank = c.base[word] + __popc(mw & ((1u << bit) - 1u));
+    if (c.packed) {
+        const uint32_t code = c.codes32[rank];
+        const uint32_t rv = code & c.rmask, mv = code >> c.rbits;
+        r = rv < (uint32_t)c.N ? (int)rv : -1;
+        m = mv < (uint32_t)c.M ? (int)mv : -1;
+    } else {
+        const int2 code = c.codes64[rank];
+        r = code.x;
+        m = code.y;
+    }
+}
+
+__device__ __forceinline__ void compact_get(const CompactVol &c, int ix, int iy, int iz, int &r, int &m) {
+    uint32_t bit;
+    const uint32_t w = compact_word(c, ix, iy, iz, bit);
+    const uint32_t mw = c.mask[w];
+    r = -1;
+    m = -1;
+    if ((mw >> bit) & 1u) compact_decode(c, w, bit, mw, r, m);
+}
+
+struct RasterLookup {
+    RasterVol v;
+    __device__ void get(int ix, int iy, int iz, int &r, int &m) const { raster_get(v, ix, iy, iz, r, m); }
+};
+struct CompactLookup {
+    CompactVol v;
+    __device__ void get(int ix, int iy, int iz, int &r, int &m) const { compact_get(v, ix, iy, iz, r, m); }
+};
+
+// ---------------------------------------------------------------------------------------------
+// per-wavefront set of the open streamline's distinct keys (LDS, open addressing)
+//   key = row for ROI hits, label | kLabelTag for target hits (rows and labels are < 2^31 - 1)
+//   slots[0 .. nI) hold the table slots of rows, slots[CAP/2 - nM .. CAP/2) those of labels;
+//   nI + nM <= CAP/2 keeps the table at most half full, so probing always ends.
+// ---------------------------------------------------------------------------------------------
+
+template <int CAP>
+struct WaveSet {
+    static constexpr int kLog2 = __builtin_ctz(CAP);
+    static constexpr int kHalf = CAP / 2;
+    uint32_t *tab;
+    uint32_t *slots;
+    int nI, nM;
+    bool skip;  // the open streamline overflowed: its hits are ignored until it closes
+
+    __device__ void init(uint32_t *t, uint32_t *s) {
+        tab = t;
+        slots = s;
+        nI = nM = 0;
+        skip = false;
+        for (int k = lane_id(); k < CAP; k += kWave) tab[k] = kEmpty;
+    }
+
+    // Insert the keys of the lanes in `cand`; returns the lanes whose key was not yet present.
+    __device__ uint64_t insert(uint64_t cand, uint32_t key, uint32_t &slot) {
+        const int lane = lane_id();
+        bool active = (cand >> lane) & 1ull;
+        bool fresh = false;
+        uint32_t h = (key * 0x9E3779B1u) >> (32 - kLog2);
+        while (__ballot(active)) {
+            if (active) {
+                const uint32_t old = atomicCAS(&tab[h], kEmpty, key);
+                if (old == kEmpty) {
+                    fresh = true;
+                    slot = h;
+                    active = false;
+                } else if (old == key) {
+                    active = false;
+                } else {
+                    h = (h + 1u) & (CAP - 1);
+                }
+            }
+        }
+        return __ballot(fresh);
+    }
+
+    // Adds the candidate rows / labels; false when the set could outgrow its capacity.
+    __device__ bool add(uint64_t candR, int r, uint64_t candM, int m) {
+        if (nI + nM + __popcll(candR) + __popcll(candM) > kHalf) return false;
+        const int lane = lane_id();
+        uint32_t slotR = 0, slotM = 0;
+        const uint64_t newR = candR ? insert(candR, (uint32_t)r, slotR) : 0ull;
+        const uint64_t newM = candM ? insert(candM, (uint32_t)m | kLabelTag, slotM) : 0ull;
+        if ((newR >> lane) & 1ull) slots[nI + mbcnt(newR)] = slotR;
+        if ((newM >> lane) & 1ull) slots[kHalf - 1 - (nM + mbcnt(newM))] = slotM;
+        nI += __popcll(newR);
+        nM += __popcll(newM);
+        return true;
+    }
+
+    __device__ void clear_entries() {
+        for (int k = lane_id(); k < nI; k += kWave) tab[slots[k]] = kEmpty;
+        for (int k = lane_id(); k < nM; k += kWave) tab[slots[kHalf - 1 - k]] = kEmpty;
+        nI = nM = 0;
+    }
+
+    // The streamline ends: C(i, m) += 1 for all its rows i and labels m, then reset.
+    __device__ void close(int32_t *__restrict__ C, int32_t M) {
+        if (!skip && nI > 0 && nM > 0) {
+            for (int b = 0; b < nI; b += kWave) {
+                const int k = b + lane_id();
+                const bool ok = k < nI;
+                const uint32_t i = ok ? tab[slots[k]] : 0u;
+                int32_t *row = C + (int64_t)i * M;
+                for (int j = 0; j < nM; ++j) {
+                    const uint32_t mk = __builtin_amdgcn_readfirstlane(tab[slots[kHalf - 1 - j]]) & ~kLabelTag;
+                    if (ok) atomicAdd(row + mk, 1);
+                }
+            }
+        }
+        clear_entries();
+        skip = false;
+    }
+};
+
+__device__ __forceinline__ void push_overflow(const Overflow &o, int64_t point_index) {
+    if (lane_id() == 0) {
+        const unsigned long long k = atomicAdd(o.count, 1ull);
+        if ((int64_t)k < o.cap) o.list[k] = point_index;
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// fills
+// ---------------------------------------------------------------------------------------------
+
+__global__ void k_fill_i32(int32_t *__restrict__ p, int64_t n, int32_t v) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+__global__ void k_fill_u64(unsigned long long *__restrict__ p, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0ull;
+}
+
+static int fill_blocks(int64_t n, int cus) {
+    int64_t b = (n + kBlock - 1) / kBlock;
+    const int64_t cap = (int64_t)cus * 16;
+    if (b > cap) b = cap;
+    return (int)(b < 1 ? 1 : b);
+}
+
+hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, int cus, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    k_fill_i32<<<fill_blocks(n, cus), kBlock, 0, st>>>(p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(unsigned long long *p, int64_t n, int cus, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    k_fill_u64<<<fill_blocks(n, cus), kBlock, 0, st>>>(p, n);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------------
+// compact volume build
+// ---------------------------------------------------------------------------------------------
+
+// one thread per voxel (coalesced reads of both volumes); occupied voxels set their bit
+__global__ void k_compact_mark(const int32_t *__restrict__ roi, const int32_t *__restrict__ lab, Grid g,
+                               int32_t N, int32_t M, int32_t SBX, int32_t SBXY, uint32_t *__restrict__ mask) {
+    const int64_t nvox = (int64_t)g.X * g.Y * g.Z;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t lin = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; lin < nvox; lin += stride) {
+        const int32_t r = roi[lin], m = lab[lin];
+        if ((unsigned)r < (unsigned)N || (unsigned)m < (unsigned)M) {
+            const int x = (int)(lin % g.X);
+            const int64_t t = lin / g.X;
+            const int y = (int)(t % g.Y);
+            const int z = (int)(t / g.Y);
+            const uint32_t sb = (uint32_t)(x >> 4) + (uint32_t)SBX * (uint32_t)(y >> 3) + (uint32_t)SBXY * (uint32_t)(z >> 3);
+            const uint32_t b = (uint32_t)(x & 15) | ((uint32_t)(y & 7) << 4) | ((uint32_t)(z & 7) << 7);
+            atomicOr(&mask[(sb << 5) | (b >> 5)], 1u << (b & 31u));
+        }
+    }
+}
+
+// inclusive scan of one value per thread over a 256-thread block; returns the block total in `total`
+__device__ uint32_t block_scan_incl(uint32_t v, uint32_t *lds4, uint32_t &total) {
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t u = __shfl_up(v, d);
+        if (lane >= d) v += u;
+    }
+    if (lane == kWave - 1) lds4[w] = v;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int k = 0; k < w; ++k) before += lds4[k];
+    total = lds4[0] + lds4[1] + lds4[2] + lds4[3];
+    __syncthreads();
+    return v + before;
+}
+
+constexpr int kWordsPerThread = kScanTile / kBlock;  // 8
+
+__global__ void k_compact_tile_sums(const uint32_t *__restrict__ mask, int64_t W, uint32_t *__restrict__ tile_sums) {
+    __shared__ uint32_t lds4[4];
+    const int64_t w0 = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kWordsPerThread;
+    uint32_t s = 0;
+    for (int k = 0; k < kWordsPerThread; ++k)
+        if (w0 + k < W) s += __popc(mask[w0 + k]);
+    uint32_t total;
+    block_scan_incl(s, lds4, total);
+    if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
+}
+
+// one block: exclusive scan of the tile sums in place
+__global__ void k_compact_scan_tiles(uint32_t *__restrict__ tile_sums, int64_t ntiles) {
+    __shared__ uint32_t lds4[4];
+    uint32_t carry = 0;
+    for (int64_t a = 0; a < ntiles; a += kBlock) {
+        const int64_t i = a + threadIdx.x;
+        const uint32_t v = i < ntiles ? tile_sums[i] : 0u;
+        uint32_t total;
+        const uint32_t incl = block_scan_incl(v, lds4, total);
+        if (i < ntiles) tile_sums[i] = carry + incl - v;
+        carry += total;
+    }
+}
+
+template <bool PACKED>
+__global__ void k_compact_codes(const uint32_t *__restrict__ mask, const uint32_t *__restrict__ tile_base, int64_t W,
+                                const int32_t *__restrict__ roi, const int32_t *__restrict__ lab, Grid g, CompactVol cv,
+                                int32_t SBY, uint32_t *__restrict__ base, void *__restrict__ codes) {
+    __shared__ uint32_t lds4[4];
+    const int64_t w0 = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kWordsPerThread;
+    uint32_t words[kWordsPerThread];
+    uint32_t s = 0;
+    for (int k = 0; k < kWordsPerThread; ++k) {
+        words[k] = (w0 + k < W) ? mask[w0 + k] : 0u;
+        s += __popc(words[k]);
+    }
+    uint32_t total;
+    uint32_t run = tile_base[blockIdx.x] + block_scan_incl(s, lds4, total) - s;
+    for (int k = 0; k < kWordsPerThread; ++k) {
+        const int64_t w = w0 + k;
+        if (w >= W) break;
+        base[w] = run;
+        uint32_t bits = words[k];
+        const uint32_t sb = (uint32_t)(w >> 5), wl = (uint32_t)(w & 31);
+        const int sbx = (int)(sb % (uint32_t)cv.SBX);
+        const int sby = (int)((sb / (uint32_t)cv.SBX) % (uint32_t)SBY);
+        const int sbz = (int)(sb / (uint32_t)cv.SBXY);
+        while (bits) {
+            const uint32_t j = __builtin_ctz(bits);
+            bits &= bits - 1u;
+            const uint32_t b = (wl << 5) | j;
+            const int x = sbx * 16 + (int)(b & 15u), y = sby * 8 + (int)((b >> 4) & 7u), z = sbz * 8 + (int)(b >> 7);
+            const int64_t lin = (int64_t)x + (int64_t)g.X * ((int64_t)y + (int64_t)g.Y * z);
+            const int32_t r = roi[lin], m = lab[lin];
+            const bool rv = (unsigned)r < (unsigned)cv.N, mv = (unsigned)m < (unsigned)cv.M;
+            if (PACKED) {
+                const uint32_t rf = rv ? (uint32_t)r : cv.rmask;
+                const uint32_t mf = mv ? (uint32_t)m : (0xFFFFFFFFu >> cv.rbits);
+                static_cast<uint32_t *>(codes)[run] = rf | (mf << cv.rbits);
+            } else {
+                static_cast<int2 *>(codes)[run] = make_int2(rv ? r : -1, mv ? m : -1);
+            }
+            ++run;
+        }
+    }
+}
+
+hipError_t launch_compact_build(const int32_t *roi, const int32_t *lab, Grid g, int32_t N, int32_t M, CompactVol cv,
+                                uint32_t *mask, uint32_t *base, void *codes, uint32_t *tile_sums, int64_t W, int cus,
+                                hipStream_t st) {
+    const int64_t ntiles = (W + kScanTile - 1) / kScanTile;
+    const int32_t SBY = cv.SBXY / cv.SBX;
+    k_fill_i32<<<fill_blocks(W, cus), kBlock, 0, st>>>(reinterpret_cast<int32_t *>(mask), W, 0);
+    const int64_t nvox = (int64_t)g.X * g.Y * g.Z;
+    k_compact_mark<<<fill_blocks(nvox, cus * 2), kBlock, 0, st>>>(roi, lab, g, N, M, cv.SBX, cv.SBXY, mask);
+    k_compact_tile_sums<<<(unsigned)ntiles, kBlock, 0, st>>>(mask, W, tile_sums);
+    k_compact_scan_tiles<<<1, kBlock, 0, st>>>(tile_sums, ntiles);
+    if (cv.packed)
+        k_compact_codes<true><<<(unsigned)ntiles, kBlock, 0, st>>>(mask, tile_sums, W, roi, lab, g, cv, SBY, base, codes);
+    else
+        k_compact_codes<false><<<(unsigned)ntiles, kBlock, 0, st>>>(mask, tile_sums, W, roi, lab, g, cv, SBY, base, codes);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------------
+// partition: first[c] = first streamline starting at or after point c*Q (first[nchunks] = S)
+// ---------------------------------------------------------------------------------------------
+
+// Chunk size from the point count P = offsets[S] (read on the device, so launches stay
+// asynchronous): Q = max(kChunkPoints, ceil(P / kMaxChunks)), nchunks = ceil(P / Q) <= kMaxChunks.
+__device__ __forceinline__ void chunking(const int64_t *offsets, int64_t S, int64_t &P, int64_t &Q, int64_t &nchunks) {
+    P = offsets[S];
+    if (P < 0) P = 0;
+    Q = (P + kMaxChunks - 1) / kMaxChunks;
+    if (Q < kChunkPoints) Q = kChunkPoints;
+    nchunks = (P + Q - 1) / Q;
+}
+
+__global__ void k_partition(const int64_t *__restrict__ offsets, int64_t S, int32_t *__restrict__ first) {
+    int64_t P, Q, nchunks;
+    chunking(offsets, S, P, Q, nchunks);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c <= nchunks; c += stride) {
+        if (c == nchunks) {
+            first[c] = (int32_t)S;
+            continue;
+        }
+        const int64_t target = c * Q;
+        int64_t lo = 0, hi = S;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (offsets[mid] < target) lo = mid + 1;
+            else hi = mid;
+        }
+        first[c] = (int32_t)lo;
+    }
+}
+
+hipError_t launch_partition(const int64_t *offsets, int64_t S, int32_t *first, int cus, hipStream_t st) {
+    k_partition<<<fill_blocks(kMaxChunks + 1, cus), kBlock, 0, st>>>(offsets, S, first);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------------
+// count, variant 1: one wavefront per streamline, raster lookups
+// ---------------------------------------------------------------------------------------------
+
+template <bool SCALED>
+__global__ void __launch_bounds__(kBlock) k_count_wave(CountArgs a, RasterVol rv) {
+    __shared__ uint32_t s_tab[kWavesPerBlock * kSetCap];
+    __shared__ uint32_t s_slots[kWavesPerBlock * (kSetCap / 2)];
+    const int lane = lane_id(), wv = threadIdx.x >> 6;
+    WaveSet<kSetCap> set;
+    set.init(s_tab + wv * kSetCap, s_slots + wv * (kSetCap / 2));
+    const int64_t Ptot = a.offsets[a.S] > 0 ? a.offsets[a.S] : 0;
+    const int64_t nw = (int64_t)gridDim.x * kWavesPerBlock;
+    for (int64_t s = (int64_t)blockIdx.x * kWavesPerBlock + wv; s < a.S; s += nw) {
+        const int64_t b0 = clamp64(a.offsets[s], 0, Ptot);
+        const int64_t b1 = clamp64(a.offsets[s + 1], b0, Ptot);
+        int last_r = -1, last_m = -1;
+        for (int64_t w0 = b0; w0 < b1; w0 += kWave) {
+            const int64_t p = w0 + lane;
+            int r = -1, m = -1;
+            if (p < b1) {
+                const float x = load_stream(a.pts + 3 * p), y = load_stream(a.pts + 3 * p + 1),
+                            z = load_stream(a.pts + 3 * p + 2);
+                int ix, iy, iz;
+                if (voxelise<SCALED>(x, y, z, a.scale, a.g, ix, iy, iz)) raster_get(rv, ix, iy, iz, r, m);
+            }
+            // drop a hit equal to the previous point's (same voxel row/label), then the LDS set
+            int rp = __shfl_up(r, 1), mp = __shfl_up(m, 1);
+            if (lane == 0) {
+                rp = last_r;
+                mp = last_m;
+            }
+            const uint64_t candR = __ballot(r >= 0 && r != rp);
+            const uint64_t candM = __ballot(m >= 0 && m != mp);
+            last_r = __shfl(r, kWave - 1);
+            last_m = __shfl(m, kWave - 1);
+            if ((candR | candM) == 0ull || set.skip) continue;
+            if (!set.add(candR, r, candM, m)) {
+                push_overflow(a.ovf, b0);
+                set.clear_entries();
+                set.skip = true;
+            }
+        }
+        set.close(a.C, a.M);
+    }
+}
+
+hipError_t launch_count_wave(const CountArgs &a, const RasterVol &rv, int blocks, hipStream_t st) {
+    if (a.scale != 1.0f) k_count_wave<true><<<blocks, kBlock, 0, st>>>(a, rv);
+    else k_count_wave<false><<<blocks, kBlock, 0, st>>>(a, rv);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------------
+// count, variant 2: flat point stream over point-balanced chunks of whole streamlines
+// ---------------------------------------------------------------------------------------------
+//
+// Chunk c owns the streamlines that start in [c*Q, (c+1)*Q).  A wavefront walks its chunk in
+// 64-point windows regardless of streamline boundaries; the starts that fall inside a window
+// come from a block of 64 offsets held one per lane.  Most points touch neither volume: the
+// occupancy bit (a 2-3 MB structure that stays in L2) filters them, and only flagged lanes fetch
+// a code.  Segments of a window (lane ranges between starts) are folded into the open
+// streamline's LDS set in order; each start closes the open streamline.
+
+template <bool SCALED>
+__global__ void __launch_bounds__(kBlock) k_count_stream(CountArgs a, CompactVol cv, const int32_t *__restrict__ first) {
+    __shared__ uint32_t s_tab[kWavesPerBlock * kSetCap];
+    __shared__ uint32_t s_slots[kWavesPerBlock * (kSetCap / 2)];
+    const int lane = lane_id(), wv = threadIdx.x >> 6;
+    WaveSet<kSetCap> set;
+    set.init(s_tab + wv * kSetCap, s_slots + wv * (kSetCap / 2));
+    const int64_t S = a.S;
+    int64_t Ptot, Q, nchunks;
+    chunking(a.offsets, S, Ptot, Q, nchunks);
+    const int64_t nw = (int64_t)gridDim.x * kWavesPerBlock;
+    for (int64_t c = (int64_t)blockIdx.x * kWavesPerBlock + wv; c < nchunks; c += nw) {
+        const int64_t s0 = clamp64(first[c], 0, S);
+        const int64_t s1 = clamp64(first[c + 1], s0, S);
+        if (s0 >= s1) continue;
+        const int64_t P0 = clamp64(a.offsets[s0], 0, Ptot);
+        const int64_t P1 = clamp64(a.offsets[s1], P0, Ptot);
+        // starts of streamlines s0+1 .. s1-1, 64 at a time (P1 = "no more starts")
+        int64_t vb = s0 + 1;
+        int64_t voff = (vb + lane < s1) ? clamp64(a.offsets[vb + lane], P0, P1) : P1;
+        int k0 = 0;
+        int last_r = -1, last_m = -1;
+        for (int64_t w0 = P0; w0 < P1; w0 += kWave) {
+            const int64_t wend = (w0 + kWave < P1) ? w0 + kWave : P1;
+            const int64_t p = w0 + lane;
+            bool flag = false;
+            uint32_t word = 0, bit = 0, mw = 0;
+            if (p < wend) {
+                const float x = load_stream(a.pts + 3 * p), y = load_stream(a.pts + 3 * p + 1),
+                            z = load_stream(a.pts + 3 * p + 2);
+                int ix, iy, iz;
+                if (voxelise<SCALED>(x, y, z, a.scale, a.g, ix, iy, iz)) {
+                    word = compact_word(cv, ix, iy, iz, bit);
+                    mw = cv.mask[word];
+                    flag = (mw >> bit) & 1u;
+                }
+            }
+            // streamline starts inside this window -> bit q of `starts` for lane q
+            uint64_t starts = 0;
+            for (;;) {
+                const uint64_t inwin = __ballot(lane >= k0 && voff < wend);
+                if (inwin) {
+                    int64_t qv = voff - w0;
+                    qv = qv < 0 ? 0 : (qv > kWave - 1 ? kWave - 1 : qv);
+                    uint64_t it = inwin;
+                    while (it) {
+                        const int k = __builtin_ctzll(it);
+                        it &= it - 1ull;
+                        starts |= 1ull << __builtin_amdgcn_readlane((int)qv, k);
+                    }
+                    k0 += __popcll(inwin);
+                }
+                if (k0 < kWave) break;
+                vb += kWave;
+                voff = (vb + lane < s1) ? clamp64(a.offsets[vb + lane], P0, P1) : P1;
+                k0 = 0;
+            }
+            const uint64_t F = __ballot(flag);
+            if (F == 0ull) {
+                if (starts && (set.nI | set.nM | (int)set.skip)) set.close(a.C, a.M);
+                last_r = last_m = -1;
+                continue;
+            }
+            int r = -1, m = -1;
+            if (flag) compact_decode(cv, word, bit, mw, r, m);
+            int rp = __shfl_up(r, 1), mp = __shfl_up(m, 1);
+            if (lane == 0) {
+                rp = last_r;
+                mp = last_m;
+            }
+            if ((starts >> lane) & 1ull) rp = mp = -1;  // first point of a streamline
+            const uint64_t candR = __ballot(r >= 0 && r != rp);
+            const uint64_t candM = __ballot(m >= 0 && m != mp);
+            last_r = __shfl(r, kWave - 1);
+            last_m = __shfl(m, kWave - 1);
+            int pos = 0;
+            uint64_t st = starts;
+            for (;;) {
+                const int end = st ? __builtin_ctzll(st) : kWave;
+                const uint64_t seg = lanes_between(pos, end);
+                const uint64_t cR = candR & seg, cM = candM & seg;
+                if ((cR | cM) && !set.skip) {
+                    if (!set.add(cR, r, cM, m)) {
+                        push_overflow(a.ovf, w0 + pos);
+                        set.clear_entries();
+                        set.skip = true;
+                    }
+                }
+                if (!st) break;
+                set.close(a.C, a.M);
+                pos = end;
+                st &= st - 1ull;
+            }
+        }
+        set.close(a.C, a.M);
+    }
+}
+
+hipError_t launch_count_stream(const CountArgs &a, const CompactVol &cv, const int32_t *first, int blocks,
+                               hipStream_t st) {
+    if (a.scale != 1.0f) k_count_stream<true><<<blocks, kBlock, 0, st>>>(a, cv, first);
+    else k_count_stream<false><<<blocks, kBlock, 0, st>>>(a, cv, first);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------------
+// fallback for overflowed streamlines: one workgroup per queued streamline, global bit maps
+// ---------------------------------------------------------------------------------------------
+
+template <typename Lookup, bool SCALED>
+__global__ void __launch_bounds__(kBlock) k_fallback(CountArgs a, Lookup lk, FallbackScratch fs) {
+    __shared__ int s_nlab;
+    const int64_t S = a.S;
+    const int64_t Ptot = a.offsets[S] > 0 ? a.offsets[S] : 0;
+    uint32_t *bmN = fs.words + (int64_t)blockIdx.x * fs.stride;
+    uint32_t *bmM = bmN + fs.nwordsN;
+    uint32_t *labels = bmM + fs.nwordsM;
+    const int64_t nq = (int64_t)*a.ovf.count;
+    const int64_t nq_c = nq < a.ovf.cap ? nq : a.ovf.cap;
+    for (int64_t q = blockIdx.x; q < nq_c; q += gridDim.x) {
+        const int64_t p = a.ovf.list[q];
+        // streamline containing point p: last s with offsets[s] <= p
+        int64_t lo = 0, hi = S;  // answer in [0, S-1]
+        while (hi - lo > 1) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (a.offsets[mid] <= p) lo = mid;
+            else hi = mid;
+        }
+        const int64_t b0 = clamp64(a.offsets[lo], 0, Ptot);
+        const int64_t b1 = clamp64(a.offsets[lo + 1], b0, Ptot);
+        if (threadIdx.x == 0) s_nlab = 0;
+        __syncthreads();
+        // distinct labels
+        for (int64_t j = b0 + threadIdx.x; j < b1; j += blockDim.x) {
+            int ix, iy, iz, r, m;
+            if (!voxelise<SCALED>(a.pts[3 * j], a.pts[3 * j + 1], a.pts[3 * j + 2], a.scale, a.g, ix, iy, iz)) continue;
+            lk.get(ix, iy, iz, r, m);
+            if (m >= 0) {
+                const uint32_t bitm = 1u << (m & 31);
+                if (!(atomicOr(&bmM[m >> 5], bitm) & bitm)) {
+                    const int k = atomicAdd(&s_nlab, 1);
+                    atomicExch(&labels[k], (uint32_t)m);
+                }
+            }
+        }
+        __syncthreads();
+        const int nlab = s_nlab;
+        // distinct rows: the first claimant of each row adds its pairs
+        if (nlab > 0) {
+            for (int64_t j = b0 + threadIdx.x; j < b1; j += blockDim.x) {
+                int ix, iy, iz, r, m;
+                if (!voxelise<SCALED>(a.pts[3 * j], a.pts[3 * j + 1], a.pts[3 * j + 2], a.scale, a.g, ix, iy, iz)) continue;
+                lk.get(ix, iy, iz, r, m);
+                if (r >= 0) {
+                    const uint32_t bitr = 1u << (r & 31);
+                    if (!(atomicOr(&bmN[r >> 5], bitr) & bitr)) {
+                        int32_t *row = a.C + (int64_t)r * a.M;
+                        for (int k = 0; k < nlab; ++k)
+                            atomicAdd(row + __hip_atomic_load(&labels[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), 1);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // restore the all-zero scratch (bit maps and label list)
+        for (int64_t j = b0 + threadIdx.x; j < b1; j += blockDim.x) {
+            int ix, iy, iz, r, m;
+            if (!voxelise<SCALED>(a.pts[3 * j], a.pts[3 * j + 1], a.pts[3 * j + 2], a.scale, a.g, ix, iy, iz)) continue;
+            lk.get(ix, iy, iz, r, m);
+            if (r >= 0) atomicExch(&bmN[r >> 5], 0u);
+            if (m >= 0) atomicExch(&bmM[m >> 5], 0u);
+        }
+        for (int k = threadIdx.x; k < nlab; k += blockDim.x) atomicExch(&labels[k], 0u);
+        __syncthreads();
+    }
+}
+
+template <typename Lookup>
+static hipError_t launch_fallback(const CountArgs &a, const Lookup &lk, FallbackScratch fs, hipStream_t st) {
+    if (a.scale != 1.0f) k_fallback<Lookup, true><<<fs.blocks, kBlock, 0, st>>>(a, lk, fs);
+    else k_fallback<Lookup, false><<<fs.blocks, kBlock, 0, st>>>(a, lk, fs);
+    return hipGetLastError();
+}
+
+hipError_t launch_fallback_raster(const CountArgs &a, const RasterVol &rv, FallbackScratch fs, hipStream_t st) {
+    return launch_fallback(a, RasterLookup{rv}, fs, st);
+}
+
+hipError_t launch_fallback_compact(const CountArgs &a, const CompactVol &cv, FallbackScratch fs, hipStream_t st) {
+    return launch_fallback(a, CompactLookup{cv}, fs, st);
+}
+
+// ---------------------------------------------------------------------------------------------
+// validation
+// ---------------------------------------------------------------------------------------------
+
+__global__ void k_validate(const int64_t *__restrict__ offsets, int64_t S, const int32_t *__restrict__ roi,
+                           const int32_t *__restrict__ lab, int64_t nvox, int32_t N, int32_t M, int32_t *flags) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int f = 0;
+    if (t0 == 0 && offsets[0] != 0) f |= 1;
+    for (int64_t s = t0; s < S; s += stride)
+        if (offsets[s + 1] < offsets[s]) f |= 1;
+    for (int64_t v = t0; v < nvox; v += stride) {
+        if (roi[v] >= N) f |= 2;
+        if (lab[v] >= M) f |= 4;
+    }
+    if (f) atomicOr(flags, f);
+}
+
+hipError_t launch_validate(const int64_t *offsets, int64_t S, const int32_t *roi, const int32_t *lab, int64_t nvox,
+                           int32_t N, int32_t M, int32_t *flags, int cus, hipStream_t st) {
+    k_fill_i32<<<1, kWave, 0, st>>>(flags, 1, 0);
+    const int64_t n = S > nvox ? S : nvox;
+    k_validate<<<fill_blocks(n, cus), kBlock, 0, st>>>(offsets, S, roi, lab, nvox, N, M, flags);
+    return hipGetLastError();
+}
+
+}  // namespace fc

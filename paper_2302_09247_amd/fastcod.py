@@ -1,0 +1,216 @@
+"""Thin ctypes binding of libfastcod.so (C-ABI in include/fastcod.h).
+
+Argument marshalling only: every step of the counting runs in the library's HIP kernels.
+PyTorch provides device memory and the current HIP stream.  When the library is missing,
+every call raises -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfastcod.so")
+
+OK, EINVAL, ERANGE, ENOMEM, EHIP, EBUSY, ECANCELED, ETIMEDOUT = 0, -1, -2, -3, -4, -5, -6, -7
+ACCUMULATE, VALIDATE = 1, 2
+VARIANT_AUTO, VARIANT_WAVE, VARIANT_STREAM = 0, 1, 2
+
+# every symbol include/fastcod.h declares
+EXPORTS = (
+    "fastcod_default_opts", "fastcod_count", "fastcod_count_ex", "fastcod_volume_create",
+    "fastcod_volume_bytes", "fastcod_volume_count", "fastcod_volume_destroy", "fastcod_validate",
+    "fastcod_strerror", "fastcod_last_error", "fastcod_release",
+)
+
+
+class FastcodError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"fastcod status {status}: {msg}")
+        self.status = status
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("scale", ctypes.c_float), ("upsample", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("variant", ctypes.c_int32), ("event_begin", ctypes.c_void_p), ("event_end", ctypes.c_void_p)]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+
+
+def load(path: str = LIB_PATH):
+    """Loads the library (once); raises when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FastcodError(EINVAL, f"{path} is not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    i32, i64, u32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+    lib.fastcod_default_opts.restype = Opts
+    lib.fastcod_count.argtypes = [_vp, _vp, i64, _vp, _vp, _vp, i32, i32, _vp, _vp]
+    lib.fastcod_count_ex.argtypes = [_vp, _vp, i64, _vp, _vp, _vp, i32, i32, _vp, ctypes.POINTER(Opts), _vp]
+    lib.fastcod_volume_create.argtypes = [_vp, _vp, _vp, i32, i32, _vp, ctypes.POINTER(_vp)]
+    lib.fastcod_volume_bytes.argtypes = [_vp]
+    lib.fastcod_volume_bytes.restype = ctypes.c_size_t
+    lib.fastcod_volume_count.argtypes = [_vp, _vp, _vp, i64, _vp, ctypes.POINTER(Opts), _vp]
+    lib.fastcod_volume_destroy.argtypes = [_vp]
+    lib.fastcod_validate.argtypes = [_vp, i64, _vp, _vp, _vp, i32, i32, _vp]
+    lib.fastcod_strerror.argtypes = [ctypes.c_int]
+    lib.fastcod_strerror.restype = ctypes.c_char_p
+    lib.fastcod_last_error.restype = ctypes.c_char_p
+    for name in ("fastcod_count", "fastcod_count_ex", "fastcod_volume_create", "fastcod_volume_count",
+                 "fastcod_volume_destroy", "fastcod_validate", "fastcod_release"):
+        getattr(lib, name).restype = ctypes.c_int
+    del u32
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != OK:
+        lib = load()
+        raise FastcodError(rc, f"{lib.fastcod_strerror(rc).decode()}: {lib.fastcod_last_error().decode()}")
+
+
+_dummy = {}
+
+
+def _points_ptr(points: torch.Tensor) -> int:
+    """Device address of the points; an empty point array gets a valid (never read) address."""
+    if points.numel() > 0:
+        return points.data_ptr()
+    d = _dummy.get(points.device)
+    if d is None:
+        d = _dummy[points.device] = torch.zeros(4, dtype=torch.float32, device=points.device)
+    return d.data_ptr()
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _dev(t: torch.Tensor, dtype, name: str, shape=None) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape[1:]) != shape:
+        raise ValueError(f"{name} has shape {tuple(t.shape)}")
+    return t
+
+
+def make_opts(scale: float = 1.0, upsample: int = 1, accumulate: bool = False, validate: bool = False,
+              variant: int = VARIANT_AUTO, events: Optional[Tuple[int, int]] = None) -> Opts:
+    o = load().fastcod_default_opts()
+    o.scale = float(scale)
+    o.upsample = int(upsample)
+    o.flags = (ACCUMULATE if accumulate else 0) | (VALIDATE if validate else 0)
+    o.variant = int(variant)
+    if events is not None:
+        o.event_begin, o.event_end = events
+    return o
+
+
+def count(points: torch.Tensor, offsets: torch.Tensor, roi: torch.Tensor, lab: torch.Tensor, N: int, M: int, *,
+          scale: float = 1.0, upsample: int = 1, accumulate: bool = False, validate: bool = False,
+          variant: int = VARIANT_AUTO, out: Optional[torch.Tensor] = None, stream=None,
+          events: Optional[Tuple[int, int]] = None) -> torch.Tensor:
+    """C[N, M] (int32, on the points' device) of the pass-through definition (fastcod_count_ex).
+
+    points [P,3] float32, offsets [S+1] int64, roi/lab [Z,Y,X] int32, all on one HIP device.
+    Asynchronous on ``stream`` (default: the current torch stream)."""
+    lib = load()
+    _dev(points, torch.float32, "points", (3,))
+    _dev(offsets, torch.int64, "offsets")
+    _dev(roi, torch.int32, "roi")
+    _dev(lab, torch.int32, "lab")
+    if roi.dim() != 3 or roi.shape != lab.shape:
+        raise ValueError("roi and lab must be [Z,Y,X] volumes of one shape")
+    if out is None:
+        out = (torch.empty if not accumulate else torch.zeros)((N, M), dtype=torch.int32, device=points.device)
+    _dev(out, torch.int32, "out")
+    if tuple(out.shape) != (N, M):
+        raise ValueError("out must be [N, M]")
+    dims = (ctypes.c_int32 * 3)(int(roi.shape[2]), int(roi.shape[1]), int(roi.shape[0]))
+    o = make_opts(scale, upsample, accumulate, validate, variant, events)
+    S = int(offsets.shape[0]) - 1
+    with torch.cuda.device(points.device):
+        _check(lib.fastcod_count_ex(_points_ptr(points), offsets.data_ptr(), S, roi.data_ptr(), lab.data_ptr(),
+                                    dims, int(N), int(M), out.data_ptr(), ctypes.byref(o), _stream_ptr(stream)))
+    return out
+
+
+class Volume:
+    """Resident compact volume (fastcod_volume_*): built once, counted against many times."""
+
+    def __init__(self, roi: torch.Tensor, lab: torch.Tensor, N: int, M: int, stream=None):
+        lib = load()
+        _dev(roi, torch.int32, "roi")
+        _dev(lab, torch.int32, "lab")
+        if roi.dim() != 3 or roi.shape != lab.shape:
+            raise ValueError("roi and lab must be [Z,Y,X] volumes of one shape")
+        self.N, self.M = int(N), int(M)
+        self.dims = (int(roi.shape[2]), int(roi.shape[1]), int(roi.shape[0]))
+        self.device = roi.device
+        h = _vp()
+        with torch.cuda.device(roi.device):
+            _check(lib.fastcod_volume_create(roi.data_ptr(), lab.data_ptr(), (ctypes.c_int32 * 3)(*self.dims),
+                                             self.N, self.M, _stream_ptr(stream), ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self) -> int:
+        return self._h.value
+
+    @property
+    def nbytes(self) -> int:
+        return int(load().fastcod_volume_bytes(self._h))
+
+    def count(self, points: torch.Tensor, offsets: torch.Tensor, *, scale: float = 1.0, accumulate: bool = False,
+              out: Optional[torch.Tensor] = None, stream=None, events=None) -> torch.Tensor:
+        lib = load()
+        _dev(points, torch.float32, "points", (3,))
+        _dev(offsets, torch.int64, "offsets")
+        if out is None:
+            out = (torch.empty if not accumulate else torch.zeros)((self.N, self.M), dtype=torch.int32,
+                                                                  device=points.device)
+        _dev(out, torch.int32, "out")
+        o = make_opts(scale, 1, accumulate, False, VARIANT_STREAM, events)
+        with torch.cuda.device(points.device):
+            _check(lib.fastcod_volume_count(self._h, _points_ptr(points), offsets.data_ptr(),
+                                            int(offsets.shape[0]) - 1, out.data_ptr(), ctypes.byref(o),
+                                            _stream_ptr(stream)))
+        return out
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            _check(load().fastcod_volume_destroy(self._h))
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def validate(offsets: torch.Tensor, roi: torch.Tensor, lab: torch.Tensor, N: int, M: int, stream=None) -> None:
+    """Raises FastcodError(ERANGE) when offsets are malformed or volume values exceed N / M."""
+    lib = load()
+    dims = (ctypes.c_int32 * 3)(int(roi.shape[2]), int(roi.shape[1]), int(roi.shape[0]))
+    with torch.cuda.device(roi.device):
+        _check(lib.fastcod_validate(offsets.data_ptr(), int(offsets.shape[0]) - 1, roi.data_ptr(), lab.data_ptr(),
+                                    dims, int(N), int(M), _stream_ptr(stream)))
+
+
+def release() -> None:
+    _check(load().fastcod_release())

@@ -1,0 +1,79 @@
+"""Host-side checks of the C-ABI library that need no GPU: it loads, exports every symbol the
+header declares, and rejects bad arguments synchronously before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2302_09247_amd import fastcod
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fastcod.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fastcod_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(fastcod.LIB_PATH):
+        pytest.fail("libfastcod.so is not built; run __graft_entry__.build()")
+    return fastcod.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(fastcod.EXPORTS)
+
+
+def test_strerror_and_default_opts(lib):
+    assert lib.fastcod_strerror(0) == b"ok"
+    assert lib.fastcod_strerror(-1) == b"invalid argument"
+    assert lib.fastcod_strerror(12345) == b"unknown status"
+    o = lib.fastcod_default_opts()
+    assert (o.scale, o.upsample, o.flags, o.variant) == (1.0, 1, 0, 0)
+
+
+def _count(lib, dims=(4, 4, 4), N=3, M=2, S=1, pts=1, off=1, roi=1, lab=1, C=1, opts=None):
+    d = (ctypes.c_int32 * 3)(*dims) if dims is not None else None
+    return lib.fastcod_count_ex(pts, off, S, roi, lab, d, N, M, C,
+                                ctypes.byref(opts) if opts is not None else None, None)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(dims=None), dict(dims=(0, 4, 4)), dict(dims=(2 ** 11, 2 ** 10, 2 ** 10)), dict(N=0), dict(M=0),
+    dict(N=2 ** 16, M=2 ** 15), dict(S=-1), dict(S=2 ** 31), dict(pts=None), dict(off=None), dict(roi=None),
+    dict(lab=None), dict(C=None),
+])
+def test_bad_arguments_are_rejected_synchronously(lib, kw):
+    args = dict(pts=1, off=1, roi=1, lab=1, C=1)
+    args.update(kw)
+    for k in ("pts", "off", "roi", "lab", "C"):
+        if args[k] == 1:
+            args[k] = 16          # never dereferenced: the call fails in its argument checks
+    assert _count(lib, **args) == fastcod.EINVAL
+    assert lib.fastcod_last_error() != b""
+
+
+@pytest.mark.parametrize("field,value", [("upsample", 2), ("scale", 0.0), ("scale", float("nan")),
+                                         ("scale", float("inf")), ("variant", 7)])
+def test_bad_options_are_rejected(lib, field, value):
+    o = lib.fastcod_default_opts()
+    setattr(o, field, value)
+    assert _count(lib, pts=16, off=16, roi=16, lab=16, C=16, opts=o) == fastcod.EINVAL
+
+
+def test_volume_create_rejects_bad_args(lib):
+    h = ctypes.c_void_p()
+    d = (ctypes.c_int32 * 3)(4, 4, 4)
+    assert lib.fastcod_volume_create(None, 16, d, 3, 2, None, ctypes.byref(h)) == fastcod.EINVAL
+    assert lib.fastcod_volume_create(16, 16, d, 3, 2, None, None) == fastcod.EINVAL
+    assert lib.fastcod_volume_count(None, 16, 16, 1, 16, None, None) == fastcod.EINVAL
+    assert lib.fastcod_volume_destroy(None) == fastcod.OK

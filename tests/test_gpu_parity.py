@@ -1,0 +1,283 @@
+"""GPU parity: the HIP path (through the C-ABI) against the CPU oracle, bit-exact.
+
+C is an integer count with a unique value (no rounding-order freedom), so the bar is exact
+equality of every element.  Every kernel variant must agree.  Sizes: small cases that span many
+64-point windows and ragged tails, the 64^3 case in full, the 1.25 mm and 0.7 mm subjects in full
+(the 0.7 mm one in the launch configuration the benchmark times), the super-resolution job,
+overflow of the per-wavefront set, and the degenerate inputs.
+"""
+import ctypes
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2302_09247_amd import synth
+from tests import _cases
+
+pytestmark = pytest.mark.gpu
+
+VARIANTS = [0, 1, 2]
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _gpu(w):
+    return w.to("cuda")
+
+
+def _run(fc, w, variant=0, scale=None, **kw):
+    C = fc.count(w.points, w.offsets, w.roi, w.lab, w.N, w.M, scale=(w.scale if scale is None else scale),
+                 variant=variant, **kw)
+    torch.cuda.synchronize()
+    return C.cpu().numpy().astype(np.int64)
+
+
+def _np_workload(points, offsets, roi, lab, N, M, scale=1.0, name="case"):
+    return synth.Workload(name, torch.from_numpy(np.ascontiguousarray(points, np.float32)),
+                          torch.from_numpy(np.ascontiguousarray(offsets, np.int64)),
+                          torch.from_numpy(np.ascontiguousarray(roi, np.int32)),
+                          torch.from_numpy(np.ascontiguousarray(lab, np.int32)), int(N), int(M), scale)
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_golden_toy(fc, variant):
+    g = _cases.load_golden("toy_two_streamlines.json")
+    w = _gpu(_np_workload(g["points"], g["offsets"], g["roi"], g["lab"], g["N"], g["M"]))
+    np.testing.assert_array_equal(_run(fc, w, variant), g["C"])
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_closed_form_lines(fc, variant):
+    lab_of = lambda M: (lambda x, y, z: ((x + 2 * y + 3 * z) % (M + 1)) - 1)   # noqa: E731
+    for origin, step, T, dims, M in [((0.25, 2.0, 1.0), (0.5, 0.0, 0.0), 23, (13, 4, 3), 4),
+                                     ((1.0, -0.25, 2.0), (0.0, 0.5, 0.0), 17, (3, 9, 4), 3),
+                                     ((1.0, 2.0, -0.75), (0.0, 0.0, 0.5), 21, (3, 4, 10), 5),
+                                     ((0.125, 0.375, 0.0625), (0.25, 0.25, 0.25), 140, (40, 41, 42), 6),
+                                     ((-3.0, 1.0, 1.0), (0.75, 0.125, 0.0), 30, (12, 6, 3), 3)]:
+        pts, off, roi, lab, N, M, Cexp = _cases.line_case(origin, step, T, dims, M, lab_of(M))
+        w = _gpu(_np_workload(pts, off, roi, lab, N, M))
+        np.testing.assert_array_equal(_run(fc, w, variant), Cexp)
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_rounding_pins(fc, variant):
+    # one single-point streamline per (pin, axis); identity ROI rows, one label on every voxel
+    X = 64
+    pins = [(v, e) for (v, XX, e) in _cases.ROUNDING_PINS if XX == X]
+    dims = (X, 3, 3)
+    for axis in range(3):
+        d = [3, 3, 3]
+        d[axis] = X
+        roi = np.arange(X * 9, dtype=np.int32).reshape(d[2], d[1], d[0])
+        lab = np.zeros_like(roi)
+        pts = np.ones((len(pins), 3), dtype=np.float32)
+        pts[:, axis] = np.array([v for v, _ in pins], dtype=np.float32)
+        off = np.arange(len(pins) + 1, dtype=np.int64)
+        w = _gpu(_np_workload(pts, off, roi, lab, X * 9, 1))
+        C = _run(fc, w, variant)
+        exp = np.zeros((X * 9, 1), np.int64)
+        for _, e in pins:
+            if e >= 0:
+                v = [1, 1, 1]
+                v[axis] = e
+                exp[v[0] + d[0] * (v[1] + d[1] * v[2]), 0] += 1
+        np.testing.assert_array_equal(C, exp)
+    del dims
+
+
+def test_huge_axis_rounding(fc):
+    # 2^24 - 1 + 0.5 ties to 2^24 on a grid of 2^25 voxels along x (raster lookups: the grid is
+    # too thin for the compact volume, which the stream variant reports as EINVAL)
+    X = 2 ** 25
+    roi = torch.arange(X, dtype=torch.int32, device="cuda").reshape(1, 1, X)
+    lab = torch.zeros_like(roi)
+    # 16777215 + 0.5 ties to 2^24 (even); 33554430 is exact; 33554431.5 rounds to 2^25 = X (outside)
+    pts = torch.tensor([[16777215.0, 0.0, 0.0], [33554430.0, 0.2, -0.3], [33554431.5, 0.0, 0.0]],
+                       dtype=torch.float32, device="cuda")
+    off = torch.arange(4, dtype=torch.int64, device="cuda")
+    C = fc.count(pts, off, roi, lab, X, 1)
+    torch.cuda.synchronize()
+    nz = torch.nonzero(C[:, 0]).flatten().cpu().tolist()
+    assert nz == [16777216, 33554430]
+    with pytest.raises(fc.FastcodError):
+        fc.count(pts, off, roi, lab, X, 1, variant=2)
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_random_small(fc, seed):
+    w = synth.random_small(seed, N=(None if seed % 3 else 6), bad_values=(seed % 2 == 0),
+                           dims=[(12, 10, 9), (7, 16, 5), (33, 3, 18), (70, 9, 11)][seed % 4],
+                           S=120, max_len=300)
+    g = _gpu(w)
+    for scale in (1.0, 1.7857143):
+        exp = oracle.count(w.points, w.offsets, w.roi, w.lab, w.N, w.M, scale=scale)
+        for v in VARIANTS:
+            np.testing.assert_array_equal(_run(fc, g, v, scale=scale), exp, err_msg=f"variant {v} scale {scale}")
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_tiny64_full(fc, variant):
+    w = synth.make_tiny64(seed=1, S=10_000, device="cuda")
+    exp = oracle.count(w.points, w.offsets, w.roi, w.lab, w.N, w.M)
+    np.testing.assert_array_equal(_run(fc, w, variant), exp)
+
+
+def _overflow_case():
+    # long straight walks through an identity-ROI grid: hundreds of distinct rows per streamline
+    rng = np.random.default_rng(7)
+    dims = (300, 40, 30)
+    X, Y, Z = dims
+    roi = np.arange(X * Y * Z, dtype=np.int32).reshape(Z, Y, X)
+    lab = rng.integers(-1, 40, size=(Z, Y, X)).astype(np.int32)
+    parts, off = [], [0]
+    for s in range(300):
+        T = int(rng.integers(1, 1500))
+        o = np.array([rng.uniform(0, X), rng.uniform(0, Y), rng.uniform(0, Z)])
+        d = rng.normal(size=3)
+        d[0] = abs(d[0]) * 4
+        d /= np.linalg.norm(d)
+        t = np.arange(T)[:, None] * 0.5
+        parts.append((o + t * d).astype(np.float32))
+        off.append(off[-1] + T)
+    return _np_workload(np.concatenate(parts), np.array(off), roi, lab, X * Y * Z, 40, name="overflow")
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_set_overflow_fallback(fc, variant):
+    w = _overflow_case()
+    exp = oracle.count(w.points, w.offsets, w.roi, w.lab, w.N, w.M)
+    np.testing.assert_array_equal(_run(fc, _gpu(w), variant), exp)
+
+
+def test_degenerate_inputs(fc):
+    w = synth.random_small(3)
+    g = _gpu(w)
+    for v in VARIANTS:
+        # no streamlines
+        C = fc.count(torch.zeros((0, 3), dtype=torch.float32, device="cuda"),
+                     torch.zeros(1, dtype=torch.int64, device="cuda"), g.roi, g.lab, w.N, w.M, variant=v)
+        # only empty streamlines
+        C2 = fc.count(torch.zeros((0, 3), dtype=torch.float32, device="cuda"),
+                      torch.zeros(9, dtype=torch.int64, device="cuda"), g.roi, g.lab, w.N, w.M, variant=v)
+        # every point outside the grid / NaN
+        pts = torch.tensor([[-5.0, 1, 1], [float("nan"), 1, 1], [1e30, 0, 0]], dtype=torch.float32, device="cuda")
+        C3 = fc.count(pts, torch.tensor([0, 1, 3], dtype=torch.int64, device="cuda"), g.roi, g.lab, w.N, w.M,
+                      variant=v)
+        torch.cuda.synchronize()
+        assert not C.any() and not C2.any() and not C3.any()
+
+
+def test_accumulate_streams_and_chunked_resume(fc):
+    w = synth.make_tiny64(seed=4, S=4000, device="cuda")
+    exp = oracle.count(w.points, w.offsets, w.roi, w.lab, w.N, w.M)
+    # resume: split the streamline list and accumulate the parts into one C, on two streams
+    off = w.offsets
+    cut = 1234
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    C = torch.zeros((w.N, w.M), dtype=torch.int32, device="cuda")
+    with torch.cuda.stream(s1):
+        fc.count(w.points, off[:cut + 1].contiguous(), w.roi, w.lab, w.N, w.M, accumulate=True, out=C, stream=s1)
+    s2.wait_stream(s1)
+    with torch.cuda.stream(s2):
+        pts2 = w.points[int(off[cut]):].contiguous()
+        off2 = (off[cut:] - off[cut]).contiguous()
+        fc.count(pts2, off2, w.roi, w.lab, w.N, w.M, accumulate=True, out=C, stream=s2)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(C.cpu().numpy(), exp)
+    # overwrite mode ignores old contents
+    C.fill_(123)
+    fc.count(w.points, w.offsets, w.roi, w.lab, w.N, w.M, out=C)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(C.cpu().numpy(), exp)
+
+
+def test_resident_volume_handle(fc):
+    w = synth.make_tiny64(seed=8, S=3000, device="cuda")
+    exp = oracle.count(w.points, w.offsets, w.roi, w.lab, w.N, w.M)
+    roi, lab = w.roi.clone(), w.lab.clone()
+    vol = fc.Volume(roi, lab, w.N, w.M)
+    torch.cuda.synchronize()
+    del roi, lab                     # the handle keeps no reference to the source volumes
+    torch.cuda.empty_cache()
+    assert vol.nbytes > 0
+    for _ in range(2):
+        C = vol.count(w.points, w.offsets)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(C.cpu().numpy(), exp)
+    vol.close()
+
+
+def test_validate(fc):
+    w = _gpu(synth.random_small(5))
+    fc.validate(w.offsets, w.roi, w.lab, w.N, w.M)
+    bad = w.offsets.clone()
+    bad[3] = bad[4] + 5
+    with pytest.raises(fc.FastcodError) as e:
+        fc.validate(bad, w.roi, w.lab, w.N, w.M)
+    assert e.value.status == fc.ERANGE
+    with pytest.raises(fc.FastcodError):
+        fc.count(w.points, bad, w.roi, w.lab, w.N, w.M, validate=True)
+    roi = w.roi.clone()
+    roi.view(-1)[0] = w.N + 3
+    with pytest.raises(fc.FastcodError):
+        fc.validate(w.offsets, roi, w.lab, w.N, w.M)
+    # malformed offsets without validation: wrong counts are allowed, a crash is not
+    for v in VARIANTS:
+        fc.count(w.points, bad, w.roi, w.lab, w.N, w.M, variant=v)
+    torch.cuda.synchronize()
+
+
+def test_binding_rejects_bad_tensors(fc):
+    w = _gpu(synth.random_small(2))
+    with pytest.raises(TypeError):
+        fc.count(w.points.cpu(), w.offsets, w.roi, w.lab, w.N, w.M)
+    with pytest.raises(TypeError):
+        fc.count(w.points.double(), w.offsets, w.roi, w.lab, w.N, w.M)
+    with pytest.raises(fc.FastcodError):
+        fc.count(w.points, w.offsets, w.roi, w.lab, w.N, w.M, upsample=2)
+
+
+# ---- full-size subjects -------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def vols07():
+    return synth.volumes_07mm()
+
+
+def _full_parity(fc, w, variants, workers=16):
+    _say(f"[parity] {w.name}: S={w.S} P={w.P} N={w.N} M={w.M} scale={w.scale}")
+    exp = oracle.count_chunked(w.points.cpu(), w.offsets.cpu(), w.roi.cpu(), w.lab.cpu(), w.N, w.M,
+                               scale=w.scale, streamlines_per_chunk=1 << 15, workers=workers)
+    _say(f"[parity] {w.name}: oracle done, total pairs {int(exp.sum())}")
+    for v in variants:
+        got = _run(fc, w, v)
+        np.testing.assert_array_equal(got, exp, err_msg=f"variant {v}")
+        _say(f"[parity] {w.name}: variant {v} bit-exact")
+
+
+def test_125mm_full(fc):
+    w = synth.make_125mm(device="cuda")
+    _full_parity(fc, w, VARIANTS)
+
+
+def test_sr_job_full(fc, vols07):
+    w = synth.make_sr(S=200_000, device="cuda", vols_hi=vols07)
+    _full_parity(fc, w, VARIANTS)
+
+
+def test_07mm_full_bench_configuration(fc, vols07):
+    w = synth.make_07mm(device="cuda", vols=vols07)
+    _full_parity(fc, w, [0])
+    # the resident-volume path gives the same matrix
+    exp = _run(fc, w, 0)
+    vol = fc.Volume(w.roi, w.lab, w.N, w.M)
+    got = vol.count(w.points, w.offsets)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(got.cpu().numpy(), exp)
+    vol.close()
