@@ -69,9 +69,12 @@ typedef struct fastcod_opts {
     int32_t variant;    /* FASTCOD_VARIANT_*                                                        */
     void *event_begin;  /* optional hipEvent_t, recorded on `stream` just before the counting kernel */
     void *event_end;    /* optional hipEvent_t, recorded on `stream` just after it                  */
+    int32_t batch;      /* flat-stream schedule: 64-point windows per pipelined batch, 2/4/8; 0 = 4 */
+    int32_t blocks_per_cu; /* flat-stream schedule: resident workgroups per CU, 0 = occupancy limit */
+    int32_t depth;      /* flat-stream schedule: point batches in flight per wavefront, 1/2; 0 = 1   */
 } fastcod_opts;
 
-/* Default options: {1.0f, 1, 0, FASTCOD_VARIANT_AUTO, NULL, NULL}. */
+/* Default options: {1.0f, 1, 0, FASTCOD_VARIANT_AUTO, NULL, NULL, 0, 0, 0}. */
 fastcod_opts fastcod_default_opts(void);
 
 /*

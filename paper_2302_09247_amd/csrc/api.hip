@@ -8,7 +8,7 @@
 #include <string>
 #include <utility>
 
-#include "../../include/fastcod.h"
+#include "fastcod.h"
 #include "internal.h"
 
 namespace {
@@ -123,7 +123,7 @@ struct CompactLayout {
     int64_t nvox;
     bool packed;
     int32_t rbits;
-    size_t off_mask, off_base, off_tiles, off_codes, bytes;
+    size_t off_mb, off_tiles, off_codes, bytes;
 };
 
 bool compact_layout(const int32_t dims[3], int32_t N, int32_t M, CompactLayout &L) {
@@ -140,9 +140,8 @@ bool compact_layout(const int32_t dims[3], int32_t N, int32_t M, CompactLayout &
     L.packed = rb + lb <= 32;
     L.rbits = rb;
     auto align = [](size_t v) { return (v + 255) & ~size_t(255); };
-    L.off_mask = 0;
-    L.off_base = align(L.off_mask + 4 * (size_t)L.W);
-    L.off_tiles = align(L.off_base + 4 * (size_t)L.W);
+    L.off_mb = 0;
+    L.off_tiles = align(L.off_mb + 8 * (size_t)L.W);
     L.off_codes = align(L.off_tiles + 4 * (size_t)L.ntiles);
     L.bytes = L.off_codes + (L.packed ? 4 : 8) * (size_t)L.nvox;   // at most every voxel occupied
     return true;
@@ -151,8 +150,7 @@ bool compact_layout(const int32_t dims[3], int32_t N, int32_t M, CompactLayout &
 fc::CompactVol compact_view(void *buf, const CompactLayout &L, int32_t N, int32_t M) {
     char *b = static_cast<char *>(buf);
     fc::CompactVol cv;
-    cv.mask = reinterpret_cast<const uint32_t *>(b + L.off_mask);
-    cv.base = reinterpret_cast<const uint32_t *>(b + L.off_base);
+    cv.mb = reinterpret_cast<const uint2 *>(b + L.off_mb);
     cv.codes32 = reinterpret_cast<const uint32_t *>(b + L.off_codes);
     cv.codes64 = reinterpret_cast<const int2 *>(b + L.off_codes);
     cv.SBX = L.SBX;
@@ -162,6 +160,8 @@ fc::CompactVol compact_view(void *buf, const CompactLayout &L, int32_t N, int32_
     cv.N = N;
     cv.M = M;
     cv.packed = L.packed ? 1 : 0;
+    cv.W = L.W;
+    cv.ncodes = L.nvox;
     return cv;
 }
 
@@ -194,10 +194,14 @@ int check_stream_args(const float *points, const int64_t *offsets, int64_t S, in
     if (o.upsample != 1) return fail(FASTCOD_EINVAL, "upsample must be 1");
     if (!(o.scale == o.scale) || o.scale <= 0.0f || isinf(o.scale)) return fail(FASTCOD_EINVAL, "scale must be finite and > 0");
     if (o.variant < FASTCOD_VARIANT_AUTO || o.variant > FASTCOD_VARIANT_STREAM) return fail(FASTCOD_EINVAL, "unknown variant");
+    if (o.batch != 0 && o.batch != 2 && o.batch != 4 && o.batch != 8) return fail(FASTCOD_EINVAL, "batch must be 0, 2, 4 or 8");
+    if (o.blocks_per_cu < 0) return fail(FASTCOD_EINVAL, "blocks_per_cu must be >= 0");
+    if (o.depth != 0 && o.depth != 1 && o.depth != 2) return fail(FASTCOD_EINVAL, "depth must be 0, 1 or 2");
     return FASTCOD_OK;
 }
 
 constexpr int kBlocksPerCU = 8;            // resident 256-thread workgroups per CU (count kernels)
+constexpr int kRangesPerWave = 4;          // flat-stream point ranges per wavefront, handed out dynamically
 
 int fallback_scratch(Workspace &ws, int32_t N, int32_t M, fc::FallbackScratch &fs) {
     fs.nwordsN = (N + 31) / 32;
@@ -254,17 +258,24 @@ int enqueue_count(Workspace &ws, int dev, const float *points, const int64_t *of
     a.ovf.count = static_cast<unsigned long long *>(ws.ovf.p);
     a.ovf.list = reinterpret_cast<int64_t *>(static_cast<char *>(ws.ovf.p) + 256);
     a.ovf.cap = S;
+    a.ovf.work = static_cast<unsigned long long *>(ws.ovf.p) + 1;
     fc::FallbackScratch fs;
     int rc = fallback_scratch(ws, N, M, fs);
     if (rc) return rc;
-    FC_HIP(fc::launch_fill_u64(a.ovf.count, 1, cus, st));
+    FC_HIP(fc::launch_fill_u64(a.ovf.count, 2, cus, st));   // overflow count and range counter
     const int64_t resident = (int64_t)cus * kBlocksPerCU;
     if (cv) {
-        FC_HIP(ws.first.ensure(4 * (size_t)(fc::kMaxChunks + 1), false));
+        const int batch = o.batch == 2 || o.batch == 8 ? o.batch : 4;
+        const int depth = o.depth == 2 ? 2 : 1;
+        int per_cu = fc::count_stream_blocks_per_cu(o.scale != 1.0f, cv->packed != 0, batch, depth);
+        if (o.blocks_per_cu > 0 && o.blocks_per_cu < per_cu) per_cu = o.blocks_per_cu;
+        const int64_t blocks = (int64_t)cus * per_cu;
+        const int64_t nparts = blocks * fc::kWavesPerBlock * kRangesPerWave;
+        FC_HIP(ws.first.ensure(4 * (size_t)(nparts + 1), false));
         int32_t *first = static_cast<int32_t *>(ws.first.p);
-        FC_HIP(fc::launch_partition(offsets, S, first, cus, st));
+        FC_HIP(fc::launch_partition(offsets, S, nparts, first, cus, st));
         if (o.event_begin) FC_HIP(hipEventRecord((hipEvent_t)o.event_begin, st));
-        FC_HIP(fc::launch_count_stream(a, *cv, first, (int)resident, st));
+        FC_HIP(fc::launch_count_stream(a, *cv, first, nparts, (int)blocks, batch, depth, st));
         if (o.event_end) FC_HIP(hipEventRecord((hipEvent_t)o.event_end, st));
         FC_HIP(fc::launch_fallback_compact(a, *cv, fs, st));
     } else {
@@ -300,6 +311,9 @@ fastcod_opts fastcod_default_opts(void) {
     o.variant = FASTCOD_VARIANT_AUTO;
     o.event_begin = nullptr;
     o.event_end = nullptr;
+    o.batch = 0;
+    o.blocks_per_cu = 0;
+    o.depth = 0;
     return o;
 }
 
@@ -349,8 +363,7 @@ int fastcod_count_ex(const float *points, const int64_t *offsets, int64_t S, con
     FC_HIP(ws.compact.ensure(L.bytes, false));
     fc::CompactVol cv = compact_view(ws.compact.p, L, N, M);
     char *b = static_cast<char *>(ws.compact.p);
-    FC_HIP(fc::launch_compact_build(roi, lab, g, N, M, cv, reinterpret_cast<uint32_t *>(b + L.off_mask),
-                                    reinterpret_cast<uint32_t *>(b + L.off_base), b + L.off_codes,
+    FC_HIP(fc::launch_compact_build(roi, lab, g, N, M, cv, reinterpret_cast<uint32_t *>(b + L.off_mb), b + L.off_codes,
                                     reinterpret_cast<uint32_t *>(b + L.off_tiles), L.W, cu_count(dev), st));
     return enqueue_count(ws, dev, points, offsets, S, g, N, M, nullptr, &cv, C, o, st);
 }
@@ -390,8 +403,7 @@ int fastcod_volume_create(const int32_t *roi, const int32_t *lab, const int32_t 
     {
         Workspace &ws = *workspace_for(dev, st);
         std::lock_guard<std::mutex> lock(ws.mu);
-        e = fc::launch_compact_build(roi, lab, g, N, M, cv, reinterpret_cast<uint32_t *>(b + L.off_mask),
-                                     reinterpret_cast<uint32_t *>(b + L.off_base), b + L.off_codes,
+        e = fc::launch_compact_build(roi, lab, g, N, M, cv, reinterpret_cast<uint32_t *>(b + L.off_mb), b + L.off_codes,
                                      reinterpret_cast<uint32_t *>(b + L.off_tiles), L.W, cu_count(dev), st);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&v->ready, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventRecord(v->ready, st);

@@ -26,11 +26,11 @@ struct RasterVol {
     int32_t N, M;
 };
 
-// Compact lookup: occupancy bits in 16x8x8 super-bricks (one 128-byte line per super-brick,
-// 32 words of 32 voxels), per-word exclusive prefix counts, and one code per occupied voxel.
+// Compact lookup: occupancy bits in 16x8x8 super-bricks (32 words of 32 voxels each), every
+// occupancy word paired with the number of occupied voxels before it (its rank base), and one
+// code per occupied voxel in that order.
 struct CompactVol {
-    const uint32_t *mask;     // [W] occupancy words
-    const uint32_t *base;     // [W] occupied voxels before this word
+    const uint2 *mb;          // [W] {occupancy word, rank base}
     const uint32_t *codes32;  // packed (row | label << rbits), if packed
     const int2 *codes64;      // (row, label) pairs, if not packed
     int32_t SBX, SBXY;        // super-bricks along x, and per z-slab
@@ -38,6 +38,8 @@ struct CompactVol {
     uint32_t rmask;           // (1 << rbits) - 1
     int32_t N, M;
     int32_t packed;
+    int64_t W;                // occupancy words
+    int64_t ncodes;           // capacity of the code array (bounds of every code read)
 };
 
 // Streamlines whose distinct (row, label) keys outgrow the per-wave LDS set are handed to a
@@ -46,6 +48,7 @@ struct Overflow {
     unsigned long long *count;
     int64_t *list;
     int64_t cap;
+    unsigned long long *work;   // next point range to hand out (flat-stream kernel); zeroed per launch
 };
 
 // Per-workgroup scratch of the fallback kernel; bit maps are all-zero between launches.
@@ -71,21 +74,23 @@ struct CountArgs {
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, int cus, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long *p, int64_t n, int cus, hipStream_t st);
 
-// compact volume build: mask must hold W words, tile_sums ceil(W / kScanTile) words
+// compact volume build: mb holds W {word, base} pairs, tile_sums ceil(W / kScanTile) words
 constexpr int kScanTile = 2048;
 hipError_t launch_compact_build(const int32_t *roi, const int32_t *lab, Grid g, int32_t N, int32_t M,
-                                CompactVol cv, uint32_t *mask, uint32_t *base, void *codes,
-                                uint32_t *tile_sums, int64_t W, int cus, hipStream_t st);
+                                CompactVol cv, uint32_t *mb, void *codes, uint32_t *tile_sums, int64_t W,
+                                int cus, hipStream_t st);
 
-// point-balanced chunks: Q = max(kChunkPoints, ceil(P / kMaxChunks)) points, at most kMaxChunks
-constexpr int64_t kChunkPoints = 4096;
-constexpr int64_t kMaxChunks = int64_t(1) << 20;
-hipError_t launch_partition(const int64_t *offsets, int64_t S, int32_t *first /* [kMaxChunks+1] */, int cus,
+// nparts point-balanced ranges of whole streamlines: first[nparts + 1]
+hipError_t launch_partition(const int64_t *offsets, int64_t S, int64_t nparts, int32_t *first, int cus,
                             hipStream_t st);
+// resident 256-thread workgroups per CU of the flat-stream kernel
+int count_stream_blocks_per_cu(bool scaled, bool packed, int batch, int depth);
 
 hipError_t launch_count_wave(const CountArgs &a, const RasterVol &rv, int blocks, hipStream_t st);
-hipError_t launch_count_stream(const CountArgs &a, const CompactVol &cv, const int32_t *first, int blocks,
-                               hipStream_t st);
+// wavefronts take the nparts ranges of `first` from ovf.work; batch: 64-point windows per
+// pipelined batch (2, 4 or 8); depth: batches of points in flight per wavefront (1 or 2)
+hipError_t launch_count_stream(const CountArgs &a, const CompactVol &cv, const int32_t *first, int64_t nparts,
+                               int blocks, int batch, int depth, hipStream_t st);
 hipError_t launch_fallback_raster(const CountArgs &a, const RasterVol &rv, FallbackScratch fs,
                                   hipStream_t st);
 hipError_t launch_fallback_compact(const CountArgs &a, const CompactVol &cv, FallbackScratch fs,

@@ -75,9 +75,14 @@ __device__ __forceinline__ uint32_t compact_word(const CompactVol &c, int ix, in
     return (sb << 5) | (b >> 5);
 }
 
-__device__ __forceinline__ void compact_decode(const CompactVol &c, uint32_t word, uint32_t bit, uint32_t mw,
-                                               int &r, int &m) {
-    const uint32_t rank = c.base[word] + __popc(mw & ((1u << bit) - 1u));
+__device__ __forceinline__ void compact_get(const CompactVol &c, int ix, int iy, int iz, int &r, int &m) {
+    uint32_t bit;
+    const uint32_t w = compact_word(c, ix, iy, iz, bit);
+    const uint2 e = c.mb[w];
+    r = -1;
+    m = -1;
+    if (!((e.x >> bit) & 1u)) return;
+    const uint32_t rank = e.y + __popc(e.x & ((1u << bit) - 1u));
     if (c.packed) {
         const uint32_t code = c.codes32[rank];
         const uint32_t rv = code & c.rmask, mv = code >> c.rbits;
@@ -88,15 +93,6 @@ __device__ __forceinline__ void compact_decode(const CompactVol &c, uint32_t wor
         r = code.x;
         m = code.y;
     }
-}
-
-__device__ __forceinline__ void compact_get(const CompactVol &c, int ix, int iy, int iz, int &r, int &m) {
-    uint32_t bit;
-    const uint32_t w = compact_word(c, ix, iy, iz, bit);
-    const uint32_t mw = c.mask[w];
-    r = -1;
-    m = -1;
-    if ((mw >> bit) & 1u) compact_decode(c, w, bit, mw, r, m);
 }
 
 struct RasterLookup {
@@ -137,7 +133,7 @@ struct WaveSet {
         const int lane = lane_id();
         bool active = (cand >> lane) & 1ull;
         bool fresh = false;
-        uint32_t h = (key * 0x9E3779B1u) >> (32 - kLog2);
+        uint32_t h = (__umul24(key ^ (key >> 20), 0x9E3779u) >> 12) & (CAP - 1);
         while (__ballot(active)) {
             if (active) {
                 const uint32_t old = atomicCAS(&tab[h], kEmpty, key);
@@ -175,21 +171,158 @@ struct WaveSet {
         nI = nM = 0;
     }
 
-    // The streamline ends: C(i, m) += 1 for all its rows i and labels m, then reset.
-    __device__ void close(int32_t *__restrict__ C, int32_t M) {
+    // The streamline ends: C(i, m) += 1 for all its rows i and labels m (through `sink`), then reset.
+    template <typename Sink>
+    __device__ void close(Sink &sink, int32_t M) {
         if (!skip && nI > 0 && nM > 0) {
             for (int b = 0; b < nI; b += kWave) {
                 const int k = b + lane_id();
                 const bool ok = k < nI;
                 const uint32_t i = ok ? tab[slots[k]] : 0u;
-                int32_t *row = C + (int64_t)i * M;
+                const uint32_t row = i * (uint32_t)M;   // N*M < 2^31
                 for (int j = 0; j < nM; ++j) {
                     const uint32_t mk = __builtin_amdgcn_readfirstlane(tab[slots[kHalf - 1 - j]]) & ~kLabelTag;
-                    if (ok) atomicAdd(row + mk, 1);
+                    sink.push(ok, row + mk);
                 }
             }
         }
         clear_entries();
+        skip = false;
+    }
+};
+
+// C updates straight to global memory (one atomic per pair).
+struct DirectSink {
+    int32_t *C;
+    __device__ void push(bool valid, uint32_t idx) {
+        if (valid) atomicAdd(C + idx, 1);
+    }
+};
+
+// C updates buffered per wavefront in LDS and issued 64 at a time: a wave-wide atomic
+// instruction instead of one per closing streamline.  On this architecture every vector memory
+// wait also waits for older atomics, so fewer, fuller atomic instructions stall the stream less.
+struct BufferedSink {
+    uint32_t *buf;  // [kWave] LDS
+    int n;          // pending entries (wave-uniform)
+    int32_t *C;
+    __device__ void init(uint32_t *b, int32_t *c) {
+        buf = b;
+        n = 0;
+        C = c;
+    }
+    __device__ void push(bool valid, uint32_t idx) {
+        const uint64_t vm = __ballot(valid);
+        if (!vm) return;
+        const int pos = n + mbcnt(vm);
+        if (valid && pos < kWave) buf[pos] = idx;
+        const int cnt = __popcll(vm);
+        if (n + cnt >= kWave) {
+            atomicAdd(C + buf[lane_id()], 1);
+            if (valid && pos >= kWave) buf[pos - kWave] = idx;
+            n = n + cnt - kWave;
+        } else {
+            n += cnt;
+        }
+    }
+    __device__ void drain() {
+        if (lane_id() < n) atomicAdd(C + buf[lane_id()], 1);
+        n = 0;
+    }
+};
+
+// Per-wavefront state of the flat-stream kernel's open streamline: raw candidate lists (hits
+// that differ from the previous point's), de-duplicated only when the streamline closes and only
+// if it has both rows and labels.  tab is an open-addressing set, empty between closes; it holds
+// at most RCAP + LCAP <= TCAP/2 keys, so probing always ends.
+template <int RCAP, int LCAP, int TCAP>
+struct DeferredSet {
+    static_assert(RCAP + LCAP <= TCAP / 2, "set must stay at most half full");
+    uint32_t *rows;   // [RCAP] raw row candidates; at close: table slot of each new row, or kEmpty
+    uint32_t *labs;   // [LCAP] raw label candidates; at close: table slot of each new label, or kEmpty
+    uint32_t *ulab;   // [LCAP] distinct labels (at close)
+    uint32_t *tab;    // [TCAP]
+    int nR, nL;
+    bool skip;        // the open streamline overflowed: its hits go to the fallback kernel
+
+    __device__ void init(uint32_t *base) {
+        rows = base;
+        labs = rows + RCAP;
+        ulab = labs + LCAP;
+        tab = ulab + LCAP;
+        nR = nL = 0;
+        skip = false;
+        for (int k = lane_id(); k < TCAP; k += kWave) tab[k] = kEmpty;
+    }
+    __device__ bool has_state() const { return (nR | nL) != 0 || skip; }
+
+    // Appends the candidates of the lanes in cR (rows) and cM (labels); false when a list is full.
+    __device__ bool append(uint64_t cR, int r, uint64_t cM, int m) {
+        const int addR = __popcll(cR), addM = __popcll(cM);
+        if (nR + addR > RCAP || nL + addM > LCAP) return false;
+        const int lane = lane_id();
+        if ((cR >> lane) & 1ull) rows[nR + mbcnt(cR)] = (uint32_t)r;
+        if ((cM >> lane) & 1ull) labs[nL + mbcnt(cM)] = (uint32_t)m;
+        nR += addR;
+        nL += addM;
+        return true;
+    }
+
+    __device__ static uint32_t slot_of(uint32_t key) {
+        return (key ^ (key >> 9) ^ (key >> 18) ^ (key >> 27)) & (TCAP - 1);
+    }
+    // Inserts the key of every lane in `cand`; returns the lanes whose key was new (slot set).
+    __device__ uint64_t insert(uint64_t cand, uint32_t key, uint32_t &slot) const {
+        const int lane = lane_id();
+        bool active = (cand >> lane) & 1ull;
+        bool fresh = false;
+        uint32_t h = slot_of(key);
+        while (__ballot(active)) {
+            if (active) {
+                const uint32_t old = atomicCAS(&tab[h], kEmpty, key);
+                fresh = old == kEmpty;
+                active = !fresh && old != key;
+                slot = h;
+                h = (h + 1u) & (TCAP - 1);
+            }
+        }
+        return __ballot(fresh);
+    }
+
+    // The streamline ends: C(i, m) += 1 for each distinct row i and distinct label m, then reset.
+    template <typename Sink>
+    __device__ void close(Sink &sink, int32_t M) {
+        if (!skip && nR > 0 && nL > 0) {
+            const int lane = lane_id();
+            int nU = 0;
+            for (int b = 0; b < nL; b += kWave) {
+                const int k = b + lane;
+                const bool ok = k < nL;
+                const uint32_t m = ok ? labs[k] : 0u;
+                uint32_t slot = 0;
+                const uint64_t fresh = insert(__ballot(ok), m | kLabelTag, slot);
+                const bool f = (fresh >> lane) & 1ull;
+                if (f) ulab[nU + mbcnt(fresh)] = m;
+                if (ok) labs[k] = f ? slot : kEmpty;
+                nU += __popcll(fresh);
+            }
+            for (int b = 0; b < nR; b += kWave) {
+                const int k = b + lane;
+                const bool ok = k < nR;
+                const uint32_t i = ok ? rows[k] : 0u;
+                uint32_t slot = 0;
+                const uint64_t fresh = insert(__ballot(ok), i, slot);
+                const bool f = (fresh >> lane) & 1ull;
+                const uint32_t row = i * (uint32_t)M;   // N*M < 2^31
+                for (int j = 0; j < nU; ++j) sink.push(f, row + __builtin_amdgcn_readfirstlane(ulab[j]));
+                if (ok) rows[k] = f ? slot : kEmpty;
+            }
+            for (int k = lane; k < nL; k += kWave)
+                if (labs[k] != kEmpty) tab[labs[k]] = kEmpty;
+            for (int k = lane; k < nR; k += kWave)
+                if (rows[k] != kEmpty) tab[rows[k]] = kEmpty;
+        }
+        nR = nL = 0;
         skip = false;
     }
 };
@@ -240,7 +373,7 @@ hipError_t launch_fill_u64(unsigned long long *p, int64_t n, int cus, hipStream_
 
 // one thread per voxel (coalesced reads of both volumes); occupied voxels set their bit
 __global__ void k_compact_mark(const int32_t *__restrict__ roi, const int32_t *__restrict__ lab, Grid g,
-                               int32_t N, int32_t M, int32_t SBX, int32_t SBXY, uint32_t *__restrict__ mask) {
+                               int32_t N, int32_t M, int32_t SBX, int32_t SBXY, uint32_t *__restrict__ mb) {
     const int64_t nvox = (int64_t)g.X * g.Y * g.Z;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t lin = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; lin < nvox; lin += stride) {
@@ -252,7 +385,7 @@ __global__ void k_compact_mark(const int32_t *__restrict__ roi, const int32_t *_
             const int z = (int)(t / g.Y);
             const uint32_t sb = (uint32_t)(x >> 4) + (uint32_t)SBX * (uint32_t)(y >> 3) + (uint32_t)SBXY * (uint32_t)(z >> 3);
             const uint32_t b = (uint32_t)(x & 15) | ((uint32_t)(y & 7) << 4) | ((uint32_t)(z & 7) << 7);
-            atomicOr(&mask[(sb << 5) | (b >> 5)], 1u << (b & 31u));
+            atomicOr(&mb[2 * ((sb << 5) | (b >> 5))], 1u << (b & 31u));
         }
     }
 }
@@ -276,12 +409,12 @@ __device__ uint32_t block_scan_incl(uint32_t v, uint32_t *lds4, uint32_t &total)
 
 constexpr int kWordsPerThread = kScanTile / kBlock;  // 8
 
-__global__ void k_compact_tile_sums(const uint32_t *__restrict__ mask, int64_t W, uint32_t *__restrict__ tile_sums) {
+__global__ void k_compact_tile_sums(const uint32_t *__restrict__ mb, int64_t W, uint32_t *__restrict__ tile_sums) {
     __shared__ uint32_t lds4[4];
     const int64_t w0 = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kWordsPerThread;
     uint32_t s = 0;
     for (int k = 0; k < kWordsPerThread; ++k)
-        if (w0 + k < W) s += __popc(mask[w0 + k]);
+        if (w0 + k < W) s += __popc(mb[2 * (w0 + k)]);
     uint32_t total;
     block_scan_incl(s, lds4, total);
     if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
@@ -302,15 +435,15 @@ __global__ void k_compact_scan_tiles(uint32_t *__restrict__ tile_sums, int64_t n
 }
 
 template <bool PACKED>
-__global__ void k_compact_codes(const uint32_t *__restrict__ mask, const uint32_t *__restrict__ tile_base, int64_t W,
+__global__ void k_compact_codes(uint32_t *__restrict__ mb, const uint32_t *__restrict__ tile_base, int64_t W,
                                 const int32_t *__restrict__ roi, const int32_t *__restrict__ lab, Grid g, CompactVol cv,
-                                int32_t SBY, uint32_t *__restrict__ base, void *__restrict__ codes) {
+                                int32_t SBY, void *__restrict__ codes) {
     __shared__ uint32_t lds4[4];
     const int64_t w0 = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kWordsPerThread;
     uint32_t words[kWordsPerThread];
     uint32_t s = 0;
     for (int k = 0; k < kWordsPerThread; ++k) {
-        words[k] = (w0 + k < W) ? mask[w0 + k] : 0u;
+        words[k] = (w0 + k < W) ? mb[2 * (w0 + k)] : 0u;
         s += __popc(words[k]);
     }
     uint32_t total;
@@ -318,7 +451,7 @@ __global__ void k_compact_codes(const uint32_t *__restrict__ mask, const uint32_
     for (int k = 0; k < kWordsPerThread; ++k) {
         const int64_t w = w0 + k;
         if (w >= W) break;
-        base[w] = run;
+        mb[2 * w + 1] = run;
         uint32_t bits = words[k];
         const uint32_t sb = (uint32_t)(w >> 5), wl = (uint32_t)(w & 31);
         const int sbx = (int)(sb % (uint32_t)cv.SBX);
@@ -345,58 +478,48 @@ __global__ void k_compact_codes(const uint32_t *__restrict__ mask, const uint32_
 }
 
 hipError_t launch_compact_build(const int32_t *roi, const int32_t *lab, Grid g, int32_t N, int32_t M, CompactVol cv,
-                                uint32_t *mask, uint32_t *base, void *codes, uint32_t *tile_sums, int64_t W, int cus,
-                                hipStream_t st) {
+                                uint32_t *mb, void *codes, uint32_t *tile_sums, int64_t W, int cus, hipStream_t st) {
     const int64_t ntiles = (W + kScanTile - 1) / kScanTile;
     const int32_t SBY = cv.SBXY / cv.SBX;
-    k_fill_i32<<<fill_blocks(W, cus), kBlock, 0, st>>>(reinterpret_cast<int32_t *>(mask), W, 0);
+    k_fill_i32<<<fill_blocks(2 * W, cus), kBlock, 0, st>>>(reinterpret_cast<int32_t *>(mb), 2 * W, 0);
     const int64_t nvox = (int64_t)g.X * g.Y * g.Z;
-    k_compact_mark<<<fill_blocks(nvox, cus * 2), kBlock, 0, st>>>(roi, lab, g, N, M, cv.SBX, cv.SBXY, mask);
-    k_compact_tile_sums<<<(unsigned)ntiles, kBlock, 0, st>>>(mask, W, tile_sums);
+    k_compact_mark<<<fill_blocks(nvox, cus * 2), kBlock, 0, st>>>(roi, lab, g, N, M, cv.SBX, cv.SBXY, mb);
+    k_compact_tile_sums<<<(unsigned)ntiles, kBlock, 0, st>>>(mb, W, tile_sums);
     k_compact_scan_tiles<<<1, kBlock, 0, st>>>(tile_sums, ntiles);
     if (cv.packed)
-        k_compact_codes<true><<<(unsigned)ntiles, kBlock, 0, st>>>(mask, tile_sums, W, roi, lab, g, cv, SBY, base, codes);
+        k_compact_codes<true><<<(unsigned)ntiles, kBlock, 0, st>>>(mb, tile_sums, W, roi, lab, g, cv, SBY, codes);
     else
-        k_compact_codes<false><<<(unsigned)ntiles, kBlock, 0, st>>>(mask, tile_sums, W, roi, lab, g, cv, SBY, base, codes);
+        k_compact_codes<false><<<(unsigned)ntiles, kBlock, 0, st>>>(mb, tile_sums, W, roi, lab, g, cv, SBY, codes);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------------------------
-// partition: first[c] = first streamline starting at or after point c*Q (first[nchunks] = S)
+// partition: first[i] = first streamline starting at or after point floor(i * P / nparts),
+// first[nparts] = S, with P = offsets[S] read on the device (launches stay asynchronous)
 // ---------------------------------------------------------------------------------------------
 
-// Chunk size from the point count P = offsets[S] (read on the device, so launches stay
-// asynchronous): Q = max(kChunkPoints, ceil(P / kMaxChunks)), nchunks = ceil(P / Q) <= kMaxChunks.
-__device__ __forceinline__ void chunking(const int64_t *offsets, int64_t S, int64_t &P, int64_t &Q, int64_t &nchunks) {
-    P = offsets[S];
+__global__ void k_partition(const int64_t *__restrict__ offsets, int64_t S, int64_t nparts, int32_t *__restrict__ first) {
+    int64_t P = offsets[S];
     if (P < 0) P = 0;
-    Q = (P + kMaxChunks - 1) / kMaxChunks;
-    if (Q < kChunkPoints) Q = kChunkPoints;
-    nchunks = (P + Q - 1) / Q;
-}
-
-__global__ void k_partition(const int64_t *__restrict__ offsets, int64_t S, int32_t *__restrict__ first) {
-    int64_t P, Q, nchunks;
-    chunking(offsets, S, P, Q, nchunks);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c <= nchunks; c += stride) {
-        if (c == nchunks) {
-            first[c] = (int32_t)S;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= nparts; i += stride) {
+        if (i == nparts) {
+            first[i] = (int32_t)S;
             continue;
         }
-        const int64_t target = c * Q;
+        const int64_t target = (int64_t)(((__int128)i * P) / nparts);
         int64_t lo = 0, hi = S;
         while (lo < hi) {
             const int64_t mid = (lo + hi) >> 1;
             if (offsets[mid] < target) lo = mid + 1;
             else hi = mid;
         }
-        first[c] = (int32_t)lo;
+        first[i] = (int32_t)lo;
     }
 }
 
-hipError_t launch_partition(const int64_t *offsets, int64_t S, int32_t *first, int cus, hipStream_t st) {
-    k_partition<<<fill_blocks(kMaxChunks + 1, cus), kBlock, 0, st>>>(offsets, S, first);
+hipError_t launch_partition(const int64_t *offsets, int64_t S, int64_t nparts, int32_t *first, int cus, hipStream_t st) {
+    k_partition<<<fill_blocks(nparts + 1, cus), kBlock, 0, st>>>(offsets, S, nparts, first);
     return hipGetLastError();
 }
 
@@ -411,6 +534,7 @@ __global__ void __launch_bounds__(kBlock) k_count_wave(CountArgs a, RasterVol rv
     const int lane = lane_id(), wv = threadIdx.x >> 6;
     WaveSet<kSetCap> set;
     set.init(s_tab + wv * kSetCap, s_slots + wv * (kSetCap / 2));
+    DirectSink sink{a.C};
     const int64_t Ptot = a.offsets[a.S] > 0 ? a.offsets[a.S] : 0;
     const int64_t nw = (int64_t)gridDim.x * kWavesPerBlock;
     for (int64_t s = (int64_t)blockIdx.x * kWavesPerBlock + wv; s < a.S; s += nw) {
@@ -443,7 +567,7 @@ __global__ void __launch_bounds__(kBlock) k_count_wave(CountArgs a, RasterVol rv
                 set.skip = true;
             }
         }
-        set.close(a.C, a.M);
+        set.close(sink, a.M);
     }
 }
 
@@ -454,118 +578,353 @@ hipError_t launch_count_wave(const CountArgs &a, const RasterVol &rv, int blocks
 }
 
 // ---------------------------------------------------------------------------------------------
-// count, variant 2: flat point stream over point-balanced chunks of whole streamlines
+// count, variant 2: flat point stream over point-balanced ranges of whole streamlines
 // ---------------------------------------------------------------------------------------------
 //
-// Chunk c owns the streamlines that start in [c*Q, (c+1)*Q).  A wavefront walks its chunk in
-// 64-point windows regardless of streamline boundaries; the starts that fall inside a window
-// come from a block of 64 offsets held one per lane.  Most points touch neither volume: the
-// occupancy bit (a 2-3 MB structure that stays in L2) filters them, and only flagged lanes fetch
-// a code.  Segments of a window (lane ranges between starts) are folded into the open
-// streamline's LDS set in order; each start closes the open streamline.
+// Wavefront w owns the streamlines [first[w], first[w+1]): one contiguous range of about P/W
+// points.  It walks the range in batches of kBatch 64-point windows regardless of streamline
+// boundaries.  Per batch: voxelise, occupancy-bit gathers (a 2-3 MB structure that stays in L2),
+// and for the few flagged lanes the rank and code gathers; only then are the next batch's
+// streaming loads issued (vector loads return in issue order, so no gather wait of this batch
+// covers them), and the windows are folded into the open streamline's LDS set while they are in
+// flight.  The streamline starts inside a window come from a block of 64 offsets held one per
+// lane; each start closes the open streamline.
+//
+// All global reads go through buffer resources: out-of-range offsets read zero instead of
+// faulting, so the point stream needs no per-lane clamping (lanes past the range are masked by
+// their index) and a lane's load offset is one constant register plus a scalar batch offset.
 
-template <bool SCALED>
-__global__ void __launch_bounds__(kBlock) k_count_stream(CountArgs a, CompactVol cv, const int32_t *__restrict__ first) {
-    __shared__ uint32_t s_tab[kWavesPerBlock * kSetCap];
-    __shared__ uint32_t s_slots[kWavesPerBlock * (kSetCap / 2)];
-    const int lane = lane_id(), wv = threadIdx.x >> 6;
-    WaveSet<kSetCap> set;
-    set.init(s_tab + wv * kSetCap, s_slots + wv * (kSetCap / 2));
+constexpr uint32_t kRsrcWord3 = 0x00020000u;   // raw 32-bit buffer, gfx9-family descriptor
+constexpr int kAuxStream = 2;                  // non-temporal: points are read once
+constexpr int kAuxCached = 0;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, uint64_t bytes) {
+    const uint32_t n = bytes > 0xFFFFFFF0ull ? 0xFFFFFFF0u : (uint32_t)bytes;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)n, (int)kRsrcWord3);
+}
+
+__device__ __forceinline__ uint32_t fbits(float f) { return __float_as_uint(f); }
+
+// wave-uniform copies (the values are uniform already; this tells the compiler)
+__device__ __forceinline__ int uniform32(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t readlane64(int64_t v, int k) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, k);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), k);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+template <bool SCALED, bool PACKED, int kBatch, int kDepth>
+__global__ void __launch_bounds__(kBlock) k_count_stream(CountArgs a, CompactVol cv, const int32_t *__restrict__ first,
+                                                         int64_t nparts) {
+    constexpr int RCAP = 192, LCAP = 64, TCAP = 512;
+    constexpr int kSetWords = RCAP + 2 * LCAP + TCAP;
+    __shared__ uint32_t s_set[kWavesPerBlock * kSetWords];
+    __shared__ uint32_t s_pend[kWavesPerBlock * kWave];
+    const int lane = lane_id(), wv = uniform32(threadIdx.x >> 6);
+    DeferredSet<RCAP, LCAP, TCAP> set;
+    set.init(s_set + wv * kSetWords);
+    BufferedSink sink;
+    sink.init(s_pend + wv * kWave, a.C);
     const int64_t S = a.S;
-    int64_t Ptot, Q, nchunks;
-    chunking(a.offsets, S, Ptot, Q, nchunks);
-    const int64_t nw = (int64_t)gridDim.x * kWavesPerBlock;
-    for (int64_t c = (int64_t)blockIdx.x * kWavesPerBlock + wv; c < nchunks; c += nw) {
-        const int64_t s0 = clamp64(first[c], 0, S);
-        const int64_t s1 = clamp64(first[c + 1], s0, S);
+    const int64_t Ptot = uniform64(a.offsets[S] > 0 ? a.offsets[S] : 0);
+    const __amdgpu_buffer_rsrc_t rmb = make_rsrc(cv.mb, 8ull * cv.W);
+    const __amdgpu_buffer_rsrc_t rcode = make_rsrc(PACKED ? (const void *)cv.codes32 : (const void *)cv.codes64,
+                                                   (PACKED ? 4ull : 8ull) * cv.ncodes);
+    const uint32_t lane12 = 12u * (uint32_t)lane;
+    const uint32_t bX = fbits(a.g.Xf), bY = fbits(a.g.Yf), bZ = fbits(a.g.Zf);
+    const uint32_t SBX = (uint32_t)cv.SBX, SBXY = (uint32_t)cv.SBXY;
+
+    for (;;) {
+        // next point range: streamlines [first[part], first[part+1])
+        unsigned long long t = 0;
+        if (lane == 0) t = atomicAdd(a.ovf.work, 1ull);
+        const int64_t part = uniform64((int64_t)t);
+        if (part >= nparts) break;
+        const int64_t s0 = uniform64(clamp64(first[part], 0, S));
+        const int64_t s1 = uniform64(clamp64(first[part + 1], s0, S));
         if (s0 >= s1) continue;
-        const int64_t P0 = clamp64(a.offsets[s0], 0, Ptot);
-        const int64_t P1 = clamp64(a.offsets[s1], P0, Ptot);
-        // starts of streamlines s0+1 .. s1-1, 64 at a time (P1 = "no more starts")
+        const int64_t P0 = uniform64(clamp64(a.offsets[s0], 0, Ptot));
+        const int64_t P1 = uniform64(clamp64(a.offsets[s1], P0, Ptot));
+        if (P0 >= P1) continue;
+        // Starts of streamlines s0+1 .. s1-1, 64 at a time, one per lane (P1 = "no more starts");
+        // k0 of them are consumed and `nxt` (uniform) is the next unconsumed start.
         int64_t vb = s0 + 1;
-        int64_t voff = (vb + lane < s1) ? clamp64(a.offsets[vb + lane], P0, P1) : P1;
+        int64_t voff = 0, nxt = P1;
         int k0 = 0;
-        int last_r = -1, last_m = -1;
-        for (int64_t w0 = P0; w0 < P1; w0 += kWave) {
-            const int64_t wend = (w0 + kWave < P1) ? w0 + kWave : P1;
-            const int64_t p = w0 + lane;
-            bool flag = false;
-            uint32_t word = 0, bit = 0, mw = 0;
-            if (p < wend) {
-                const float x = load_stream(a.pts + 3 * p), y = load_stream(a.pts + 3 * p + 1),
-                            z = load_stream(a.pts + 3 * p + 2);
-                int ix, iy, iz;
-                if (voxelise<SCALED>(x, y, z, a.scale, a.g, ix, iy, iz)) {
-                    word = compact_word(cv, ix, iy, iz, bit);
-                    mw = cv.mask[word];
-                    flag = (mw >> bit) & 1u;
-                }
-            }
-            // streamline starts inside this window -> bit q of `starts` for lane q
-            uint64_t starts = 0;
-            for (;;) {
-                const uint64_t inwin = __ballot(lane >= k0 && voff < wend);
-                if (inwin) {
-                    int64_t qv = voff - w0;
-                    qv = qv < 0 ? 0 : (qv > kWave - 1 ? kWave - 1 : qv);
-                    uint64_t it = inwin;
-                    while (it) {
-                        const int k = __builtin_ctzll(it);
-                        it &= it - 1ull;
-                        starts |= 1ull << __builtin_amdgcn_readlane((int)qv, k);
-                    }
-                    k0 += __popcll(inwin);
-                }
-                if (k0 < kWave) break;
+        auto load_starts = [&]() {
+            voff = (vb + lane < s1) ? clamp64(a.offsets[vb + lane], P0, P1) : P1;
+            k0 = 0;
+            nxt = readlane64(voff, 0);
+        };
+        auto consumed = [&](uint64_t taken) {
+            k0 += __popcll(taken);
+            if (k0 >= kWave) {
                 vb += kWave;
-                voff = (vb + lane < s1) ? clamp64(a.offsets[vb + lane], P0, P1) : P1;
-                k0 = 0;
+                load_starts();
+            } else {
+                nxt = readlane64(voff, k0);
             }
-            const uint64_t F = __ballot(flag);
-            if (F == 0ull) {
-                if (starts && (set.nI | set.nM | (int)set.skip)) set.close(a.C, a.M);
+        };
+        // starts in [wb, wend) (wend <= wb + 64) as lane bits relative to wb; consumes them
+        auto take_starts = [&](int64_t wb, int64_t wend) -> uint64_t {
+            uint64_t starts = 0;
+            while (nxt < wend) {
+                const uint64_t inwin = __ballot(lane >= k0 && voff < wend);
+                int64_t qv = voff - wb;
+                qv = qv < 0 ? 0 : (qv > kWave - 1 ? kWave - 1 : qv);
+                uint64_t it = inwin;
+                while (it) {
+                    const int k = __builtin_ctzll(it);
+                    it &= it - 1ull;
+                    starts |= 1ull << __builtin_amdgcn_readlane((int)qv, k);
+                }
+                consumed(inwin);
+            }
+            return starts;
+        };
+        auto skip_starts = [&](int64_t limit) {
+            while (nxt < limit) consumed(__ballot(lane >= k0 && voff < limit));
+        };
+        load_starts();
+        int last_r = -1, last_m = -1;
+        // points from `pbase` (re-based if a range ever passes 4 GB)
+        int64_t pbase = P0;
+        __amdgpu_buffer_rsrc_t rp = make_rsrc(a.pts + 3 * pbase, 12ull * (uint64_t)(Ptot - pbase));
+        const int64_t BW = (int64_t)kWave * kBatch;   // points per batch
+
+        // kDepth register sets: while batch k is voxelised, looked up and folded, the next
+        // kDepth-1 batches are in flight; batch k+kDepth is issued into k's registers once k's
+        // gathers have returned.
+        float ax[kBatch], ay[kBatch], az[kBatch], bx[kBatch], by[kBatch], bz[kBatch];
+        auto load_batch = [&](int64_t w, float (&x)[kBatch], float (&y)[kBatch], float (&z)[kBatch]) {
+            if (12 * (w - pbase) + 12 * BW > (int64_t)0xF0000000ll) {
+                pbase = w;
+                rp = make_rsrc(a.pts + 3 * pbase, 12ull * (uint64_t)(Ptot - pbase));
+            }
+            const uint32_t so = (uint32_t)(12 * (w - pbase));
+#pragma unroll
+            for (int b = 0; b < kBatch; ++b) {
+                const auto v = __builtin_amdgcn_raw_buffer_load_b96(rp, lane12, so + 768u * b, kAuxStream);
+                x[b] = __uint_as_float(v[0]);
+                y[b] = __uint_as_float(v[1]);
+                z[b] = __uint_as_float(v[2]);
+            }
+        };
+        auto run_batch = [&](int64_t w0, float (&px)[kBatch], float (&py)[kBatch], float (&pz)[kBatch]) {
+            const int64_t rem64 = P1 - w0;
+            const int rem = rem64 > BW ? (int)BW : (int)rem64;   // valid points in this batch
+            // phase 1: voxelise; one 8-byte gather per point gives its occupancy word and rank base
+            uint32_t word[kBatch], bit[kBatch];
+            bool in[kBatch];
+#pragma unroll
+            for (int b = 0; b < kBatch; ++b) {
+                float x = px[b], y = py[b], z = pz[b];
+                if (SCALED) {
+                    x = __fmul_rn(x, a.scale);
+                    y = __fmul_rn(y, a.scale);
+                    z = __fmul_rn(z, a.scale);
+                }
+                const float tx = __fadd_rn(x, 0.5f), ty = __fadd_rn(y, 0.5f), tz = __fadd_rn(z, 0.5f);
+                // 0 <= t < bound  <=>  bits(t) < bits(bound) as unsigned (t is never -0; NaN and
+                // negative values compare above every finite positive bound)
+                in[b] = (int)(fbits(tx) < bX) & (int)(fbits(ty) < bY) & (int)(fbits(tz) < bZ) &
+                        (int)(lane + b * kWave < rem);
+                const uint32_t ix = (uint32_t)(int)tx, iy = (uint32_t)(int)ty, iz = (uint32_t)(int)tz;
+                const uint32_t sb = __umul24(iz >> 3, SBXY) + __umul24(iy >> 3, SBX) + (ix >> 4);
+                const uint32_t bb = (ix & 15u) | ((iy & 7u) << 4) | ((iz & 7u) << 7);
+                word[b] = in[b] ? ((sb << 5) | (bb >> 5)) : 0u;
+                bit[b] = bb & 31u;
+            }
+            uint32_t mw[kBatch], rank[kBatch];
+#pragma unroll
+            for (int b = 0; b < kBatch; ++b) {
+                const auto e = __builtin_amdgcn_raw_buffer_load_b64(rmb, word[b] << 3, 0, kAuxCached);
+                mw[b] = e[0];
+                rank[b] = e[1];
+            }
+            bool flag[kBatch];
+            bool any = false;
+#pragma unroll
+            for (int b = 0; b < kBatch; ++b) {
+                flag[b] = in[b] && ((mw[b] >> bit[b]) & 1u);
+                any |= flag[b];
+            }
+            int r[kBatch], m[kBatch];
+#pragma unroll
+            for (int b = 0; b < kBatch; ++b) r[b] = m[b] = -1;
+            if (__ballot(any)) {
+                // phase 2: codes of the flagged voxels (other lanes read entry 0)
+#pragma unroll
+                for (int b = 0; b < kBatch; ++b)
+                    rank[b] = flag[b] ? rank[b] + __popc(mw[b] & ((1u << bit[b]) - 1u)) : 0u;
+                if (PACKED) {
+                    uint32_t code[kBatch];
+#pragma unroll
+                    for (int b = 0; b < kBatch; ++b)
+                        code[b] = __builtin_amdgcn_raw_buffer_load_b32(rcode, rank[b] << 2, 0, kAuxCached);
+#pragma unroll
+                    for (int b = 0; b < kBatch; ++b) {
+                        const uint32_t rv = code[b] & cv.rmask, mv = code[b] >> cv.rbits;
+                        r[b] = (flag[b] && rv < (uint32_t)cv.N) ? (int)rv : -1;
+                        m[b] = (flag[b] && mv < (uint32_t)cv.M) ? (int)mv : -1;
+                    }
+                } else {
+#pragma unroll
+                    for (int b = 0; b < kBatch; ++b) {
+                        const auto c2 = __builtin_amdgcn_raw_buffer_load_b64(rcode, rank[b] << 3, 0, kAuxCached);
+                        r[b] = flag[b] ? (int)c2[0] : -1;
+                        m[b] = flag[b] ? (int)c2[1] : -1;
+                    }
+                }
+            }
+            // every gather of this batch has returned; this batch's registers now take batch k+kDepth
+            const int64_t w2 = w0 + kDepth * BW;
+            __builtin_amdgcn_sched_barrier(0);
+            if (w2 < P1) load_batch(w2, px, py, pz);
+            __builtin_amdgcn_sched_barrier(0);
+            uint64_t fl[kBatch];
+            uint64_t fall = 0;
+#pragma unroll
+            for (int b = 0; b < kBatch; ++b) {
+                fl[b] = __ballot(flag[b]);
+                fall |= fl[b];
+            }
+            if (fall == 0ull) {
+                // nothing looked up: only a streamline start inside the batch matters (it closes the
+                // open streamline, whose hits all came earlier)
+                const int64_t bend = (w0 + BW < P1) ? w0 + BW : P1;
+                if (nxt < bend) {
+                    if (set.has_state()) set.close(sink, a.M);
+                    skip_starts(bend);
+                }
                 last_r = last_m = -1;
-                continue;
+                return;
             }
-            int r = -1, m = -1;
-            if (flag) compact_decode(cv, word, bit, mw, r, m);
-            int rp = __shfl_up(r, 1), mp = __shfl_up(m, 1);
-            if (lane == 0) {
-                rp = last_r;
-                mp = last_m;
-            }
-            if ((starts >> lane) & 1ull) rp = mp = -1;  // first point of a streamline
-            const uint64_t candR = __ballot(r >= 0 && r != rp);
-            const uint64_t candM = __ballot(m >= 0 && m != mp);
-            last_r = __shfl(r, kWave - 1);
-            last_m = __shfl(m, kWave - 1);
-            int pos = 0;
-            uint64_t st = starts;
-            for (;;) {
-                const int end = st ? __builtin_ctzll(st) : kWave;
-                const uint64_t seg = lanes_between(pos, end);
-                const uint64_t cR = candR & seg, cM = candM & seg;
-                if ((cR | cM) && !set.skip) {
-                    if (!set.add(cR, r, cM, m)) {
-                        push_overflow(a.ovf, w0 + pos);
-                        set.clear_entries();
+#pragma unroll
+            for (int b = 0; b < kBatch; ++b) {
+                const int64_t wb = w0 + (int64_t)b * kWave;
+                if (wb >= P1) break;
+                const int64_t wend = (wb + kWave < P1) ? wb + kWave : P1;
+                // streamline starts inside this window -> bit q of `starts` for lane q
+                const uint64_t starts = (nxt < wend) ? take_starts(wb, wend) : 0ull;
+                if (fl[b] == 0ull) {
+                    if (starts && set.has_state()) set.close(sink, a.M);
+                    last_r = last_m = -1;
+                    continue;
+                }
+                const int rb = r[b], mb = m[b];
+                // previous point's row / label (lane 0: the last point of the previous window)
+                int rp_ = __builtin_amdgcn_update_dpp(last_r, rb, 0x138, 0xF, 0xF, false);   // wave_shr:1
+                int mp_ = __builtin_amdgcn_update_dpp(last_m, mb, 0x138, 0xF, 0xF, false);
+                if ((starts >> lane) & 1ull) rp_ = mp_ = -1;  // first point of a streamline
+                const uint64_t candR = __ballot(rb >= 0 && rb != rp_);
+                const uint64_t candM = __ballot(mb >= 0 && mb != mp_);
+                last_r = __builtin_amdgcn_readlane(rb, kWave - 1);
+                last_m = __builtin_amdgcn_readlane(mb, kWave - 1);
+                if (!starts) {   // the whole window belongs to the open streamline
+                    if ((candR | candM) && !set.skip && !set.append(candR, rb, candM, mb)) {
+                        push_overflow(a.ovf, wb);
+                        set.nR = set.nL = 0;
                         set.skip = true;
                     }
+                    continue;
                 }
-                if (!st) break;
-                set.close(a.C, a.M);
-                pos = end;
-                st &= st - 1ull;
+                int pos = 0;
+                uint64_t st = starts;
+                for (;;) {
+                    const int end = st ? __builtin_ctzll(st) : kWave;
+                    const uint64_t seg = lanes_between(pos, end);
+                    const uint64_t cR = candR & seg, cM = candM & seg;
+                    if ((cR | cM) && !set.skip && !set.append(cR, rb, cM, mb)) {
+                        push_overflow(a.ovf, wb + pos);
+                        set.nR = set.nL = 0;
+                        set.skip = true;
+                    }
+                    if (!st) break;
+                    set.close(sink, a.M);
+                    pos = end;
+                    st &= st - 1ull;
+                }
+            }
+        };
+        load_batch(P0, ax, ay, az);
+        if (kDepth == 1) {
+            for (int64_t w0 = P0; w0 < P1; w0 += BW) run_batch(w0, ax, ay, az);
+        } else {
+            if (P0 + BW < P1) load_batch(P0 + BW, bx, by, bz);
+            for (int64_t w0 = P0;;) {
+                run_batch(w0, ax, ay, az);
+                w0 += BW;
+                if (w0 >= P1) break;
+                run_batch(w0, bx, by, bz);
+                w0 += BW;
+                if (w0 >= P1) break;
             }
         }
-        set.close(a.C, a.M);
+        set.close(sink, a.M);
+    }
+    sink.drain();
+}
+
+template <bool SCALED, bool PACKED, int B, int D>
+static int blocks_per_cu_of() {
+    int n = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &n, reinterpret_cast<const void *>(&k_count_stream<SCALED, PACKED, B, D>), kBlock, 0);
+    return (e == hipSuccess && n > 0) ? n : 4;
+}
+
+template <int B, int D>
+static int blocks_per_cu_bd(bool scaled, bool packed) {
+    if (scaled) return packed ? blocks_per_cu_of<true, true, B, D>() : blocks_per_cu_of<true, false, B, D>();
+    return packed ? blocks_per_cu_of<false, true, B, D>() : blocks_per_cu_of<false, false, B, D>();
+}
+
+int count_stream_blocks_per_cu(bool scaled, bool packed, int batch, int depth) {
+    if (depth == 2) {
+        switch (batch) {
+            case 2: return blocks_per_cu_bd<2, 2>(scaled, packed);
+            case 8: return blocks_per_cu_bd<8, 2>(scaled, packed);
+            default: return blocks_per_cu_bd<4, 2>(scaled, packed);
+        }
+    }
+    switch (batch) {
+        case 2: return blocks_per_cu_bd<2, 1>(scaled, packed);
+        case 8: return blocks_per_cu_bd<8, 1>(scaled, packed);
+        default: return blocks_per_cu_bd<4, 1>(scaled, packed);
     }
 }
 
-hipError_t launch_count_stream(const CountArgs &a, const CompactVol &cv, const int32_t *first, int blocks,
-                               hipStream_t st) {
-    if (a.scale != 1.0f) k_count_stream<true><<<blocks, kBlock, 0, st>>>(a, cv, first);
-    else k_count_stream<false><<<blocks, kBlock, 0, st>>>(a, cv, first);
+template <int B, int D>
+static void launch_stream_bd(const CountArgs &a, const CompactVol &cv, const int32_t *first, int64_t nparts, int blocks,
+                             hipStream_t st) {
+    const bool scaled = a.scale != 1.0f;
+    if (scaled && cv.packed) k_count_stream<true, true, B, D><<<blocks, kBlock, 0, st>>>(a, cv, first, nparts);
+    else if (scaled) k_count_stream<true, false, B, D><<<blocks, kBlock, 0, st>>>(a, cv, first, nparts);
+    else if (cv.packed) k_count_stream<false, true, B, D><<<blocks, kBlock, 0, st>>>(a, cv, first, nparts);
+    else k_count_stream<false, false, B, D><<<blocks, kBlock, 0, st>>>(a, cv, first, nparts);
+}
+
+hipError_t launch_count_stream(const CountArgs &a, const CompactVol &cv, const int32_t *first, int64_t nparts,
+                               int blocks, int batch, int depth, hipStream_t st) {
+    if (depth == 2) {
+        switch (batch) {
+            case 2: launch_stream_bd<2, 2>(a, cv, first, nparts, blocks, st); break;
+            case 8: launch_stream_bd<8, 2>(a, cv, first, nparts, blocks, st); break;
+            default: launch_stream_bd<4, 2>(a, cv, first, nparts, blocks, st); break;
+        }
+    } else {
+        switch (batch) {
+            case 2: launch_stream_bd<2, 1>(a, cv, first, nparts, blocks, st); break;
+            case 8: launch_stream_bd<8, 1>(a, cv, first, nparts, blocks, st); break;
+            default: launch_stream_bd<4, 1>(a, cv, first, nparts, blocks, st); break;
+        }
+    }
     return hipGetLastError();
 }
 

@@ -35,7 +35,8 @@ class FastcodError(RuntimeError):
 
 class Opts(ctypes.Structure):
     _fields_ = [("scale", ctypes.c_float), ("upsample", ctypes.c_int32), ("flags", ctypes.c_uint32),
-                ("variant", ctypes.c_int32), ("event_begin", ctypes.c_void_p), ("event_end", ctypes.c_void_p)]
+                ("variant", ctypes.c_int32), ("event_begin", ctypes.c_void_p), ("event_end", ctypes.c_void_p),
+                ("batch", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32), ("depth", ctypes.c_int32)]
 
 
 _lib = None
@@ -109,7 +110,8 @@ def _dev(t: torch.Tensor, dtype, name: str, shape=None) -> torch.Tensor:
 
 
 def make_opts(scale: float = 1.0, upsample: int = 1, accumulate: bool = False, validate: bool = False,
-              variant: int = VARIANT_AUTO, events: Optional[Tuple[int, int]] = None) -> Opts:
+              variant: int = VARIANT_AUTO, events: Optional[Tuple[int, int]] = None, batch: int = 0,
+              blocks_per_cu: int = 0, depth: int = 0) -> Opts:
     o = load().fastcod_default_opts()
     o.scale = float(scale)
     o.upsample = int(upsample)
@@ -117,13 +119,17 @@ def make_opts(scale: float = 1.0, upsample: int = 1, accumulate: bool = False, v
     o.variant = int(variant)
     if events is not None:
         o.event_begin, o.event_end = events
+    o.batch = int(batch)
+    o.blocks_per_cu = int(blocks_per_cu)
+    o.depth = int(depth)
     return o
 
 
 def count(points: torch.Tensor, offsets: torch.Tensor, roi: torch.Tensor, lab: torch.Tensor, N: int, M: int, *,
           scale: float = 1.0, upsample: int = 1, accumulate: bool = False, validate: bool = False,
           variant: int = VARIANT_AUTO, out: Optional[torch.Tensor] = None, stream=None,
-          events: Optional[Tuple[int, int]] = None) -> torch.Tensor:
+          events: Optional[Tuple[int, int]] = None, batch: int = 0, blocks_per_cu: int = 0,
+          depth: int = 0) -> torch.Tensor:
     """C[N, M] (int32, on the points' device) of the pass-through definition (fastcod_count_ex).
 
     points [P,3] float32, offsets [S+1] int64, roi/lab [Z,Y,X] int32, all on one HIP device.
@@ -141,7 +147,7 @@ def count(points: torch.Tensor, offsets: torch.Tensor, roi: torch.Tensor, lab: t
     if tuple(out.shape) != (N, M):
         raise ValueError("out must be [N, M]")
     dims = (ctypes.c_int32 * 3)(int(roi.shape[2]), int(roi.shape[1]), int(roi.shape[0]))
-    o = make_opts(scale, upsample, accumulate, validate, variant, events)
+    o = make_opts(scale, upsample, accumulate, validate, variant, events, batch, blocks_per_cu, depth)
     S = int(offsets.shape[0]) - 1
     with torch.cuda.device(points.device):
         _check(lib.fastcod_count_ex(_points_ptr(points), offsets.data_ptr(), S, roi.data_ptr(), lab.data_ptr(),
