@@ -85,6 +85,7 @@ struct Workspace {
     DevBuf ovf;         // overflow counter + queue
     DevBuf fallback;    // fallback scratch (all-zero between launches)
     DevBuf flags;       // validation flags
+    DevBuf ct;          // transposed accumulation copy of C
 };
 
 std::mutex g_ws_mu;
@@ -116,6 +117,7 @@ int cu_count(int dev) {
 }
 
 // ---- compact volume layout ----
+constexpr int32_t kMaxCoarseWords = 8192;   // 32 KB of LDS per counting workgroup
 struct CompactLayout {
     int32_t SBX, SBY, SBZ;
     int64_t W;        // words
@@ -123,7 +125,8 @@ struct CompactLayout {
     int64_t nvox;
     bool packed;
     int32_t rbits;
-    size_t off_mb, off_tiles, off_codes, bytes;
+    int32_t cs, CBX, CBY, CBZ, ncoarse_words;
+    size_t off_mb, off_tiles, off_coarse, off_codes, bytes;
 };
 
 bool compact_layout(const int32_t dims[3], int32_t N, int32_t M, CompactLayout &L) {
@@ -139,10 +142,25 @@ bool compact_layout(const int32_t dims[3], int32_t N, int32_t M, CompactLayout &
     const int rb = bit_width((uint32_t)N), lb = bit_width((uint32_t)M);
     L.packed = rb + lb <= 32;
     L.rbits = rb;
+    // buffer-resource offsets are 32-bit: occupancy pairs and codes must stay below 4 GB
+    if (8 * L.W >= (int64_t(1) << 32) || (L.packed ? 4 : 8) * L.nvox >= (int64_t(1) << 32)) return false;
+    // coarse occupancy (kept in LDS by the counting kernel): smallest block side 8, 16 or 32 whose
+    // bit map fits kMaxCoarseWords
+    for (L.cs = 3; L.cs <= 5; ++L.cs) {
+        const int32_t c = 1 << L.cs;
+        L.CBX = (dims[0] + c - 1) / c;
+        L.CBY = (dims[1] + c - 1) / c;
+        L.CBZ = (dims[2] + c - 1) / c;
+        const int64_t ncb = (int64_t)L.CBX * L.CBY * L.CBZ;
+        L.ncoarse_words = (int32_t)(2 * ((ncb + 63) / 64));
+        if (L.ncoarse_words <= kMaxCoarseWords) break;
+    }
+    if (L.cs > 5) return false;
     auto align = [](size_t v) { return (v + 255) & ~size_t(255); };
     L.off_mb = 0;
     L.off_tiles = align(L.off_mb + 8 * (size_t)L.W);
-    L.off_codes = align(L.off_tiles + 4 * (size_t)L.ntiles);
+    L.off_coarse = align(L.off_tiles + 4 * (size_t)L.ntiles);
+    L.off_codes = align(L.off_coarse + 4 * (size_t)L.ncoarse_words);
     L.bytes = L.off_codes + (L.packed ? 4 : 8) * (size_t)L.nvox;   // at most every voxel occupied
     return true;
 }
@@ -151,6 +169,11 @@ fc::CompactVol compact_view(void *buf, const CompactLayout &L, int32_t N, int32_
     char *b = static_cast<char *>(buf);
     fc::CompactVol cv;
     cv.mb = reinterpret_cast<const uint2 *>(b + L.off_mb);
+    cv.coarse = reinterpret_cast<const uint32_t *>(b + L.off_coarse);
+    cv.cs = L.cs;
+    cv.CBX = L.CBX;
+    cv.CBXY = L.CBX * L.CBY;
+    cv.ncoarse_words = L.ncoarse_words;
     cv.codes32 = reinterpret_cast<const uint32_t *>(b + L.off_codes);
     cv.codes64 = reinterpret_cast<const int2 *>(b + L.off_codes);
     cv.SBX = L.SBX;
@@ -240,7 +263,10 @@ int enqueue_count(Workspace &ws, int dev, const float *points, const int64_t *of
                   const fc::Grid &g, int32_t N, int32_t M, const fc::RasterVol *rv, const fc::CompactVol *cv,
                   int32_t *C, const fastcod_opts &o, hipStream_t st) {
     const int cus = cu_count(dev);
-    if (!(o.flags & FASTCOD_ACCUMULATE)) FC_HIP(fc::launch_fill_i32(C, (int64_t)N * M, 0, cus, st));
+    // The flat-stream path accumulates into a transposed workspace copy CT[M][N]: the rows of one
+    // streamline are neighbouring ROI indices, so its pair updates share memory lines there.
+    const bool transposed = cv != nullptr && S > 0 && M > 1 && N >= 64;
+    if (!(o.flags & FASTCOD_ACCUMULATE) && !transposed) FC_HIP(fc::launch_fill_i32(C, (int64_t)N * M, 0, cus, st));
     if (S == 0) {
         if (o.event_begin) FC_HIP(hipEventRecord((hipEvent_t)o.event_begin, st));
         if (o.event_end) FC_HIP(hipEventRecord((hipEvent_t)o.event_end, st));
@@ -254,7 +280,15 @@ int enqueue_count(Workspace &ws, int dev, const float *points, const int64_t *of
     a.g = g;
     a.scale = o.scale;
     a.C = C;
-    a.M = M;
+    a.si = (uint32_t)M;
+    a.sm = 1u;
+    if (transposed) {
+        FC_HIP(ws.ct.ensure(4 * (size_t)N * (size_t)M, false));
+        a.C = static_cast<int32_t *>(ws.ct.p);
+        a.si = 1u;
+        a.sm = (uint32_t)N;
+        FC_HIP(fc::launch_fill_i32(a.C, (int64_t)N * M, 0, cus, st));
+    }
     a.ovf.count = static_cast<unsigned long long *>(ws.ovf.p);
     a.ovf.list = reinterpret_cast<int64_t *>(static_cast<char *>(ws.ovf.p) + 256);
     a.ovf.cap = S;
@@ -267,7 +301,8 @@ int enqueue_count(Workspace &ws, int dev, const float *points, const int64_t *of
     if (cv) {
         const int batch = o.batch == 2 || o.batch == 8 ? o.batch : 4;
         const int depth = o.depth == 2 ? 2 : 1;
-        int per_cu = fc::count_stream_blocks_per_cu(o.scale != 1.0f, cv->packed != 0, batch, depth);
+        int per_cu = fc::count_stream_blocks_per_cu(o.scale != 1.0f, cv->packed != 0, batch, depth,
+                                                    4 * (size_t)cv->ncoarse_words);
         if (o.blocks_per_cu > 0 && o.blocks_per_cu < per_cu) per_cu = o.blocks_per_cu;
         const int64_t blocks = (int64_t)cus * per_cu;
         const int64_t nparts = blocks * fc::kWavesPerBlock * kRangesPerWave;
@@ -278,6 +313,7 @@ int enqueue_count(Workspace &ws, int dev, const float *points, const int64_t *of
         FC_HIP(fc::launch_count_stream(a, *cv, first, nparts, (int)blocks, batch, depth, st));
         if (o.event_end) FC_HIP(hipEventRecord((hipEvent_t)o.event_end, st));
         FC_HIP(fc::launch_fallback_compact(a, *cv, fs, st));
+        if (transposed) FC_HIP(fc::launch_transpose(a.C, C, N, M, (o.flags & FASTCOD_ACCUMULATE) != 0, st));
     } else {
         int64_t blocks = (S + fc::kWavesPerBlock - 1) / fc::kWavesPerBlock;
         if (blocks > resident) blocks = resident;
@@ -364,7 +400,8 @@ int fastcod_count_ex(const float *points, const int64_t *offsets, int64_t S, con
     fc::CompactVol cv = compact_view(ws.compact.p, L, N, M);
     char *b = static_cast<char *>(ws.compact.p);
     FC_HIP(fc::launch_compact_build(roi, lab, g, N, M, cv, reinterpret_cast<uint32_t *>(b + L.off_mb), b + L.off_codes,
-                                    reinterpret_cast<uint32_t *>(b + L.off_tiles), L.W, cu_count(dev), st));
+                                    reinterpret_cast<uint32_t *>(b + L.off_tiles),
+                                    reinterpret_cast<uint32_t *>(b + L.off_coarse), L.W, cu_count(dev), st));
     return enqueue_count(ws, dev, points, offsets, S, g, N, M, nullptr, &cv, C, o, st);
 }
 
@@ -404,7 +441,8 @@ int fastcod_volume_create(const int32_t *roi, const int32_t *lab, const int32_t 
         Workspace &ws = *workspace_for(dev, st);
         std::lock_guard<std::mutex> lock(ws.mu);
         e = fc::launch_compact_build(roi, lab, g, N, M, cv, reinterpret_cast<uint32_t *>(b + L.off_mb), b + L.off_codes,
-                                     reinterpret_cast<uint32_t *>(b + L.off_tiles), L.W, cu_count(dev), st);
+                                     reinterpret_cast<uint32_t *>(b + L.off_tiles),
+                                     reinterpret_cast<uint32_t *>(b + L.off_coarse), L.W, cu_count(dev), st);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&v->ready, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventRecord(v->ready, st);
     }
@@ -486,6 +524,7 @@ int fastcod_release(void) {
         w->ovf.release();
         w->fallback.release();
         w->flags.release();
+        w->ct.release();
         delete w;
     }
     g_ws.clear();

@@ -31,6 +31,10 @@ struct RasterVol {
 // code per occupied voxel in that order.
 struct CompactVol {
     const uint2 *mb;          // [W] {occupancy word, rank base}
+    const uint32_t *coarse;   // one bit per (2^cs)^3 block: any occupied voxel inside
+    int32_t cs;               // log2 of the coarse block side (3, 4 or 5)
+    int32_t CBX, CBXY;        // coarse blocks along x, and per z-slab
+    int32_t ncoarse_words;    // words of `coarse` (a multiple of 2)
     const uint32_t *codes32;  // packed (row | label << rbits), if packed
     const int2 *codes64;      // (row, label) pairs, if not packed
     int32_t SBX, SBXY;        // super-bricks along x, and per z-slab
@@ -59,6 +63,8 @@ struct FallbackScratch {
     int32_t nwordsN, nwordsM;
 };
 
+// C is addressed as C[i * si + m * sm]: row-major [N][M] (si = M, sm = 1) or the transposed
+// accumulation layout [M][N] (si = 1, sm = N); N * M < 2^31.
 struct CountArgs {
     const float *pts;
     const int64_t *offsets;
@@ -66,7 +72,7 @@ struct CountArgs {
     Grid g;
     float scale;
     int32_t *C;
-    int32_t M;
+    uint32_t si, sm;
     Overflow ovf;
 };
 
@@ -77,14 +83,14 @@ hipError_t launch_fill_u64(unsigned long long *p, int64_t n, int cus, hipStream_
 // compact volume build: mb holds W {word, base} pairs, tile_sums ceil(W / kScanTile) words
 constexpr int kScanTile = 2048;
 hipError_t launch_compact_build(const int32_t *roi, const int32_t *lab, Grid g, int32_t N, int32_t M,
-                                CompactVol cv, uint32_t *mb, void *codes, uint32_t *tile_sums, int64_t W,
-                                int cus, hipStream_t st);
+                                CompactVol cv, uint32_t *mb, void *codes, uint32_t *tile_sums, uint32_t *coarse,
+                                int64_t W, int cus, hipStream_t st);
 
 // nparts point-balanced ranges of whole streamlines: first[nparts + 1]
 hipError_t launch_partition(const int64_t *offsets, int64_t S, int64_t nparts, int32_t *first, int cus,
                             hipStream_t st);
 // resident 256-thread workgroups per CU of the flat-stream kernel
-int count_stream_blocks_per_cu(bool scaled, bool packed, int batch, int depth);
+int count_stream_blocks_per_cu(bool scaled, bool packed, int batch, int depth, size_t dyn_lds);
 
 hipError_t launch_count_wave(const CountArgs &a, const RasterVol &rv, int blocks, hipStream_t st);
 // wavefronts take the nparts ranges of `first` from ovf.work; batch: 64-point windows per
@@ -95,6 +101,9 @@ hipError_t launch_fallback_raster(const CountArgs &a, const RasterVol &rv, Fallb
                                   hipStream_t st);
 hipError_t launch_fallback_compact(const CountArgs &a, const CompactVol &cv, FallbackScratch fs,
                                    hipStream_t st);
+
+// C[i][m] = CT[m][i] (or += with accumulate), C [N][M], CT [M][N]
+hipError_t launch_transpose(const int32_t *CT, int32_t *C, int32_t N, int32_t M, bool accumulate, hipStream_t st);
 
 hipError_t launch_validate(const int64_t *offsets, int64_t S, const int32_t *roi, const int32_t *lab,
                            int64_t nvox, int32_t N, int32_t M, int32_t *flags, int cus, hipStream_t st);

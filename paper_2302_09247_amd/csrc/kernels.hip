@@ -173,16 +173,16 @@ struct WaveSet {
 
     // The streamline ends: C(i, m) += 1 for all its rows i and labels m (through `sink`), then reset.
     template <typename Sink>
-    __device__ void close(Sink &sink, int32_t M) {
+    __device__ void close(Sink &sink, uint32_t si, uint32_t sm) {
         if (!skip && nI > 0 && nM > 0) {
             for (int b = 0; b < nI; b += kWave) {
                 const int k = b + lane_id();
                 const bool ok = k < nI;
                 const uint32_t i = ok ? tab[slots[k]] : 0u;
-                const uint32_t row = i * (uint32_t)M;   // N*M < 2^31
+                const uint32_t row = i * si;   // N*M < 2^31
                 for (int j = 0; j < nM; ++j) {
                     const uint32_t mk = __builtin_amdgcn_readfirstlane(tab[slots[kHalf - 1 - j]]) & ~kLabelTag;
-                    sink.push(ok, row + mk);
+                    sink.push(ok, row + mk * sm);
                 }
             }
         }
@@ -291,7 +291,7 @@ struct DeferredSet {
 
     // The streamline ends: C(i, m) += 1 for each distinct row i and distinct label m, then reset.
     template <typename Sink>
-    __device__ void close(Sink &sink, int32_t M) {
+    __device__ void close(Sink &sink, uint32_t si, uint32_t sm) {
         if (!skip && nR > 0 && nL > 0) {
             const int lane = lane_id();
             int nU = 0;
@@ -313,8 +313,8 @@ struct DeferredSet {
                 uint32_t slot = 0;
                 const uint64_t fresh = insert(__ballot(ok), i, slot);
                 const bool f = (fresh >> lane) & 1ull;
-                const uint32_t row = i * (uint32_t)M;   // N*M < 2^31
-                for (int j = 0; j < nU; ++j) sink.push(f, row + __builtin_amdgcn_readfirstlane(ulab[j]));
+                const uint32_t row = i * si;   // N*M < 2^31
+                for (int j = 0; j < nU; ++j) sink.push(f, row + __builtin_amdgcn_readfirstlane(ulab[j]) * sm);
                 if (ok) rows[k] = f ? slot : kEmpty;
             }
             for (int k = lane; k < nL; k += kWave)
@@ -477,8 +477,43 @@ __global__ void k_compact_codes(uint32_t *__restrict__ mb, const uint32_t *__res
     }
 }
 
+// Coarse occupancy: bit of block (cx, cy, cz) of side 2^cs is set iff an occupancy word covering
+// it has a bit inside it.  One thread per block, 64 blocks per wavefront packed with a ballot.
+__global__ void k_compact_coarse(const uint32_t *__restrict__ mb, int32_t SBX, int32_t SBY, int32_t SBZ, int32_t cs,
+                                 int32_t CBX, int32_t CBY, int32_t CBZ, uint32_t *__restrict__ coarse) {
+    const int64_t ncb = (int64_t)CBX * CBY * CBZ;
+    const int64_t cb = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool occ = false;
+    if (cb < ncb) {
+        const int cx = (int)(cb % CBX);
+        const int64_t t = cb / CBX;
+        const int cy = (int)(t % CBY), cz = (int)(t / CBY);
+        if (cs == 3) {
+            // half of one 16x8x8 super-brick: x in [0,8) are bits 0-7 and 16-23 of each word
+            const uint32_t half = (cx & 1) ? 0xFF00FF00u : 0x00FF00FFu;
+            const int64_t sb = (cx >> 1) + (int64_t)SBX * (cy + (int64_t)SBY * cz);
+            for (int wl = 0; wl < 32; ++wl) occ |= (mb[2 * (sb * 32 + wl)] & half) != 0u;
+        } else {
+            const int fx = 1 << (cs - 4), fyz = 1 << (cs - 3);   // super-bricks per block side
+            for (int sz = cz * fyz; sz < (cz + 1) * fyz && sz < SBZ; ++sz)
+                for (int sy = cy * fyz; sy < (cy + 1) * fyz && sy < SBY; ++sy)
+                    for (int sx = cx * fx; sx < (cx + 1) * fx && sx < SBX; ++sx) {
+                        const int64_t sb = sx + (int64_t)SBX * (sy + (int64_t)SBY * sz);
+                        for (int wl = 0; wl < 32; ++wl) occ |= mb[2 * (sb * 32 + wl)] != 0u;
+                    }
+        }
+    }
+    const uint64_t bits = __ballot(occ);
+    const int64_t w = cb >> 6;   // this wavefront's 64 blocks
+    if ((threadIdx.x & 63) == 0) {
+        coarse[2 * w] = (uint32_t)bits;
+        coarse[2 * w + 1] = (uint32_t)(bits >> 32);
+    }
+}
+
 hipError_t launch_compact_build(const int32_t *roi, const int32_t *lab, Grid g, int32_t N, int32_t M, CompactVol cv,
-                                uint32_t *mb, void *codes, uint32_t *tile_sums, int64_t W, int cus, hipStream_t st) {
+                                uint32_t *mb, void *codes, uint32_t *tile_sums, uint32_t *coarse, int64_t W, int cus,
+                                hipStream_t st) {
     const int64_t ntiles = (W + kScanTile - 1) / kScanTile;
     const int32_t SBY = cv.SBXY / cv.SBX;
     k_fill_i32<<<fill_blocks(2 * W, cus), kBlock, 0, st>>>(reinterpret_cast<int32_t *>(mb), 2 * W, 0);
@@ -490,6 +525,12 @@ hipError_t launch_compact_build(const int32_t *roi, const int32_t *lab, Grid g, 
         k_compact_codes<true><<<(unsigned)ntiles, kBlock, 0, st>>>(mb, tile_sums, W, roi, lab, g, cv, SBY, codes);
     else
         k_compact_codes<false><<<(unsigned)ntiles, kBlock, 0, st>>>(mb, tile_sums, W, roi, lab, g, cv, SBY, codes);
+    const int32_t SBZ = (int32_t)(W / 32 / cv.SBXY);
+    const int32_t c = 1 << cv.cs;
+    const int32_t CBY = (g.Y + c - 1) >> cv.cs, CBZ = (g.Z + c - 1) >> cv.cs;
+    const int64_t nthreads = (int64_t)cv.ncoarse_words * 32;
+    k_compact_coarse<<<(unsigned)((nthreads + kBlock - 1) / kBlock), kBlock, 0, st>>>(mb, cv.SBX, SBY, SBZ, cv.cs, cv.CBX,
+                                                                                    CBY, CBZ, coarse);
     return hipGetLastError();
 }
 
@@ -567,7 +608,7 @@ __global__ void __launch_bounds__(kBlock) k_count_wave(CountArgs a, RasterVol rv
                 set.skip = true;
             }
         }
-        set.close(sink, a.M);
+        set.close(sink, a.si, a.sm);
     }
 }
 
@@ -625,7 +666,10 @@ __global__ void __launch_bounds__(kBlock) k_count_stream(CountArgs a, CompactVol
     constexpr int kSetWords = RCAP + 2 * LCAP + TCAP;
     __shared__ uint32_t s_set[kWavesPerBlock * kSetWords];
     __shared__ uint32_t s_pend[kWavesPerBlock * kWave];
+    extern __shared__ uint32_t s_coarse[];   // coarse occupancy bit map, cv.ncoarse_words words
     const int lane = lane_id(), wv = uniform32(threadIdx.x >> 6);
+    for (int k = threadIdx.x; k < cv.ncoarse_words; k += blockDim.x) s_coarse[k] = cv.coarse[k];
+    __syncthreads();
     DeferredSet<RCAP, LCAP, TCAP> set;
     set.init(s_set + wv * kSetWords);
     BufferedSink sink;
@@ -638,6 +682,8 @@ __global__ void __launch_bounds__(kBlock) k_count_stream(CountArgs a, CompactVol
     const uint32_t lane12 = 12u * (uint32_t)lane;
     const uint32_t bX = fbits(a.g.Xf), bY = fbits(a.g.Yf), bZ = fbits(a.g.Zf);
     const uint32_t SBX = (uint32_t)cv.SBX, SBXY = (uint32_t)cv.SBXY;
+    const uint32_t cs = (uint32_t)cv.cs, CBX = (uint32_t)cv.CBX, CBXY = (uint32_t)cv.CBXY;
+    constexpr uint32_t kOutOfRange = 0xFFFFFFF8u;   // buffer offset past every resource: reads 0, no traffic
 
     for (;;) {
         // next point range: streamlines [first[part], first[part+1])
@@ -718,9 +764,11 @@ __global__ void __launch_bounds__(kBlock) k_count_stream(CountArgs a, CompactVol
         auto run_batch = [&](int64_t w0, float (&px)[kBatch], float (&py)[kBatch], float (&pz)[kBatch]) {
             const int64_t rem64 = P1 - w0;
             const int rem = rem64 > BW ? (int)BW : (int)rem64;   // valid points in this batch
-            // phase 1: voxelise; one 8-byte gather per point gives its occupancy word and rank base
+            // phase 1: voxelise and test the coarse occupancy bit in LDS; only points in occupied
+            // coarse blocks gather their occupancy word and rank base (8 bytes)
             uint32_t word[kBatch], bit[kBatch];
             bool in[kBatch];
+            bool anyc = false;
 #pragma unroll
             for (int b = 0; b < kBatch; ++b) {
                 float x = px[b], y = py[b], z = pz[b];
@@ -737,15 +785,24 @@ __global__ void __launch_bounds__(kBlock) k_count_stream(CountArgs a, CompactVol
                 const uint32_t ix = (uint32_t)(int)tx, iy = (uint32_t)(int)ty, iz = (uint32_t)(int)tz;
                 const uint32_t sb = __umul24(iz >> 3, SBXY) + __umul24(iy >> 3, SBX) + (ix >> 4);
                 const uint32_t bb = (ix & 15u) | ((iy & 7u) << 4) | ((iz & 7u) << 7);
+                const uint32_t cb = __umul24(iz >> cs, CBXY) + __umul24(iy >> cs, CBX) + (ix >> cs);
+                const uint32_t cw = s_coarse[in[b] ? (cb >> 5) : 0u];
+                in[b] = in[b] && ((cw >> (cb & 31u)) & 1u);
+                anyc |= in[b];
                 word[b] = in[b] ? ((sb << 5) | (bb >> 5)) : 0u;
                 bit[b] = bb & 31u;
             }
             uint32_t mw[kBatch], rank[kBatch];
 #pragma unroll
-            for (int b = 0; b < kBatch; ++b) {
-                const auto e = __builtin_amdgcn_raw_buffer_load_b64(rmb, word[b] << 3, 0, kAuxCached);
-                mw[b] = e[0];
-                rank[b] = e[1];
+            for (int b = 0; b < kBatch; ++b) mw[b] = rank[b] = 0u;
+            if (__ballot(anyc)) {
+#pragma unroll
+                for (int b = 0; b < kBatch; ++b) {
+                    const auto e = __builtin_amdgcn_raw_buffer_load_b64(rmb, in[b] ? (word[b] << 3) : kOutOfRange, 0,
+                                                                        kAuxCached);
+                    mw[b] = e[0];
+                    rank[b] = e[1];
+                }
             }
             bool flag[kBatch];
             bool any = false;
@@ -799,7 +856,7 @@ __global__ void __launch_bounds__(kBlock) k_count_stream(CountArgs a, CompactVol
                 // open streamline, whose hits all came earlier)
                 const int64_t bend = (w0 + BW < P1) ? w0 + BW : P1;
                 if (nxt < bend) {
-                    if (set.has_state()) set.close(sink, a.M);
+                    if (set.has_state()) set.close(sink, a.si, a.sm);
                     skip_starts(bend);
                 }
                 last_r = last_m = -1;
@@ -813,7 +870,7 @@ __global__ void __launch_bounds__(kBlock) k_count_stream(CountArgs a, CompactVol
                 // streamline starts inside this window -> bit q of `starts` for lane q
                 const uint64_t starts = (nxt < wend) ? take_starts(wb, wend) : 0ull;
                 if (fl[b] == 0ull) {
-                    if (starts && set.has_state()) set.close(sink, a.M);
+                    if (starts && set.has_state()) set.close(sink, a.si, a.sm);
                     last_r = last_m = -1;
                     continue;
                 }
@@ -846,7 +903,7 @@ __global__ void __launch_bounds__(kBlock) k_count_stream(CountArgs a, CompactVol
                         set.skip = true;
                     }
                     if (!st) break;
-                    set.close(sink, a.M);
+                    set.close(sink, a.si, a.sm);
                     pos = end;
                     st &= st - 1ull;
                 }
@@ -866,37 +923,37 @@ __global__ void __launch_bounds__(kBlock) k_count_stream(CountArgs a, CompactVol
                 if (w0 >= P1) break;
             }
         }
-        set.close(sink, a.M);
+        set.close(sink, a.si, a.sm);
     }
     sink.drain();
 }
 
 template <bool SCALED, bool PACKED, int B, int D>
-static int blocks_per_cu_of() {
+static int blocks_per_cu_of(size_t dyn) {
     int n = 0;
     const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &n, reinterpret_cast<const void *>(&k_count_stream<SCALED, PACKED, B, D>), kBlock, 0);
+        &n, reinterpret_cast<const void *>(&k_count_stream<SCALED, PACKED, B, D>), kBlock, dyn);
     return (e == hipSuccess && n > 0) ? n : 4;
 }
 
 template <int B, int D>
-static int blocks_per_cu_bd(bool scaled, bool packed) {
-    if (scaled) return packed ? blocks_per_cu_of<true, true, B, D>() : blocks_per_cu_of<true, false, B, D>();
-    return packed ? blocks_per_cu_of<false, true, B, D>() : blocks_per_cu_of<false, false, B, D>();
+static int blocks_per_cu_bd(bool scaled, bool packed, size_t dyn) {
+    if (scaled) return packed ? blocks_per_cu_of<true, true, B, D>(dyn) : blocks_per_cu_of<true, false, B, D>(dyn);
+    return packed ? blocks_per_cu_of<false, true, B, D>(dyn) : blocks_per_cu_of<false, false, B, D>(dyn);
 }
 
-int count_stream_blocks_per_cu(bool scaled, bool packed, int batch, int depth) {
+int count_stream_blocks_per_cu(bool scaled, bool packed, int batch, int depth, size_t dyn) {
     if (depth == 2) {
         switch (batch) {
-            case 2: return blocks_per_cu_bd<2, 2>(scaled, packed);
-            case 8: return blocks_per_cu_bd<8, 2>(scaled, packed);
-            default: return blocks_per_cu_bd<4, 2>(scaled, packed);
+            case 2: return blocks_per_cu_bd<2, 2>(scaled, packed, dyn);
+            case 8: return blocks_per_cu_bd<8, 2>(scaled, packed, dyn);
+            default: return blocks_per_cu_bd<4, 2>(scaled, packed, dyn);
         }
     }
     switch (batch) {
-        case 2: return blocks_per_cu_bd<2, 1>(scaled, packed);
-        case 8: return blocks_per_cu_bd<8, 1>(scaled, packed);
-        default: return blocks_per_cu_bd<4, 1>(scaled, packed);
+        case 2: return blocks_per_cu_bd<2, 1>(scaled, packed, dyn);
+        case 8: return blocks_per_cu_bd<8, 1>(scaled, packed, dyn);
+        default: return blocks_per_cu_bd<4, 1>(scaled, packed, dyn);
     }
 }
 
@@ -904,10 +961,11 @@ template <int B, int D>
 static void launch_stream_bd(const CountArgs &a, const CompactVol &cv, const int32_t *first, int64_t nparts, int blocks,
                              hipStream_t st) {
     const bool scaled = a.scale != 1.0f;
-    if (scaled && cv.packed) k_count_stream<true, true, B, D><<<blocks, kBlock, 0, st>>>(a, cv, first, nparts);
-    else if (scaled) k_count_stream<true, false, B, D><<<blocks, kBlock, 0, st>>>(a, cv, first, nparts);
-    else if (cv.packed) k_count_stream<false, true, B, D><<<blocks, kBlock, 0, st>>>(a, cv, first, nparts);
-    else k_count_stream<false, false, B, D><<<blocks, kBlock, 0, st>>>(a, cv, first, nparts);
+    const size_t dyn = 4 * (size_t)cv.ncoarse_words;
+    if (scaled && cv.packed) k_count_stream<true, true, B, D><<<blocks, kBlock, dyn, st>>>(a, cv, first, nparts);
+    else if (scaled) k_count_stream<true, false, B, D><<<blocks, kBlock, dyn, st>>>(a, cv, first, nparts);
+    else if (cv.packed) k_count_stream<false, true, B, D><<<blocks, kBlock, dyn, st>>>(a, cv, first, nparts);
+    else k_count_stream<false, false, B, D><<<blocks, kBlock, dyn, st>>>(a, cv, first, nparts);
 }
 
 hipError_t launch_count_stream(const CountArgs &a, const CompactVol &cv, const int32_t *first, int64_t nparts,
@@ -979,9 +1037,9 @@ __global__ void __launch_bounds__(kBlock) k_fallback(CountArgs a, Lookup lk, Fal
                 if (r >= 0) {
                     const uint32_t bitr = 1u << (r & 31);
                     if (!(atomicOr(&bmN[r >> 5], bitr) & bitr)) {
-                        int32_t *row = a.C + (int64_t)r * a.M;
+                        int32_t *row = a.C + (uint32_t)r * a.si;
                         for (int k = 0; k < nlab; ++k)
-                            atomicAdd(row + __hip_atomic_load(&labels[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), 1);
+                            atomicAdd(row + __hip_atomic_load(&labels[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) * a.sm, 1);
                     }
                 }
             }
@@ -1013,6 +1071,37 @@ hipError_t launch_fallback_raster(const CountArgs &a, const RasterVol &rv, Fallb
 
 hipError_t launch_fallback_compact(const CountArgs &a, const CompactVol &cv, FallbackScratch fs, hipStream_t st) {
     return launch_fallback(a, CompactLookup{cv}, fs, st);
+}
+
+// ---------------------------------------------------------------------------------------------
+// transpose of the accumulation layout: C[i][m] (+)= CT[m][i], 32x32 tiles through LDS
+// ---------------------------------------------------------------------------------------------
+
+template <bool ACC>
+__global__ void __launch_bounds__(256) k_transpose(const int32_t *__restrict__ CT, int32_t *__restrict__ C, int32_t N,
+                                                   int32_t M) {
+    __shared__ int32_t tile[32][33];
+    const int i0 = blockIdx.x * 32, m0 = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+    for (int k = ty; k < 32; k += 8) {
+        const int m = m0 + k, i = i0 + tx;
+        tile[k][tx] = (m < M && i < N) ? CT[(int64_t)m * N + i] : 0;
+    }
+    __syncthreads();
+    for (int k = ty; k < 32; k += 8) {
+        const int i = i0 + k, m = m0 + tx;
+        if (i < N && m < M) {
+            int32_t *dst = C + (int64_t)i * M + m;
+            *dst = ACC ? *dst + tile[tx][k] : tile[tx][k];
+        }
+    }
+}
+
+hipError_t launch_transpose(const int32_t *CT, int32_t *C, int32_t N, int32_t M, bool accumulate, hipStream_t st) {
+    const dim3 grid((unsigned)((N + 31) / 32), (unsigned)((M + 31) / 32));
+    if (accumulate) k_transpose<true><<<grid, 256, 0, st>>>(CT, C, N, M);
+    else k_transpose<false><<<grid, 256, 0, st>>>(CT, C, N, M);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------------------------
