@@ -88,6 +88,11 @@ def main():
     ap.add_argument("--cpu-sample-streamlines", type=int, default=1_500_000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (for rocprofv3 counter scaling)")
+    ap.add_argument("--form", choices=("plain", "batched", "served"), default="plain",
+                    help="plain: the 0.7 mm subject (default); batched: many subjects in one graph launch; "
+                         "served: Poisson request stream")
+    ap.add_argument("--subjects", type=int, default=32)
+    ap.add_argument("--tune-cache", default=None)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the counting path runs on a single MI355X here "
@@ -108,6 +113,11 @@ def main():
 
     from paper_2302_09247_amd import fastcod, synth
     fastcod.load()
+    if args.form == "batched":
+        return bench_batched(args)
+    if args.form == "served":
+        import serve_bench
+        return serve_bench.main(args)
     t0 = time.time()
     vols = synth.volumes_07mm()
     log(f"volumes: N={vols.N} M={vols.M} dims={vols.dims} ({time.time() - t0:.1f}s)")
@@ -187,6 +197,72 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic_per_launch(),
                      "kernel_ms": k_ms, "algorithmic_bytes": alg_bytes},
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_batched(args):
+    """All subjects of the batched workload counted by one tuned, graph-captured plan launch, against
+    the same subjects counted one by one with resident volumes (plain path) on the same GPU."""
+    import torch
+    from paper_2302_09247_amd import fastcod, synth
+    t0 = time.time()
+    subs = []
+    for k in range(args.subjects):
+        w = synth.make_batch_subject(k, device="cuda")
+        subs.append(dict(points=w.points, offsets=w.offsets, roi=w.roi, lab=w.lab, N=w.N, M=w.M, scale=1.0,
+                         C=torch.empty((w.N, w.M), dtype=torch.int32, device="cuda")))
+        log(f"subject {k}: dims {w.dims} N={w.N} M={w.M} S={w.S} P={w.P}")
+    torch.cuda.synchronize()
+    P = sum(int(d["points"].shape[0]) for d in subs)
+    S = sum(int(d["offsets"].shape[0]) - 1 for d in subs)
+    log(f"batched workload: {len(subs)} subjects, S={S} P={P} ({12 * P / 1e9:.1f} GB) in {time.time() - t0:.0f}s")
+    t0 = time.time()
+    plan = fastcod.Plan(subs, tune=True, tune_cache=args.tune_cache)
+    log(f"plan (with tuning) built in {time.time() - t0:.1f}s, schedule {plan.schedule}")
+    ev = HipEvents()
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        plan.launch(stream)
+    torch.cuda.synchronize()
+    a, b = ev.create(), ev.create()
+    hip = ev.hip
+    hip.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    hip.hipEventRecord(a, stream.cuda_stream)
+    for _ in range(args.steps):
+        plan.launch(stream)
+    hip.hipEventRecord(b, stream.cuda_stream)
+    batched_ms = ev.elapsed_ms(a, b) / args.steps
+    batched_C = [d["C"].clone() for d in subs]
+    # plain: resident volume per subject, one fastcod_volume_count call each
+    vols = [fastcod.Volume(d["roi"], d["lab"], d["N"], d["M"]) for d in subs]
+    torch.cuda.synchronize()
+    outs = [torch.empty_like(d["C"]) for d in subs]
+    for v, d, o in zip(vols, subs, outs):
+        for _ in range(max(1, args.warmup)):
+            v.count(d["points"], d["offsets"], out=o)
+    torch.cuda.synchronize()
+    plain_ms = 0.0
+    for v, d, o in zip(vols, subs, outs):
+        hip.hipEventRecord(a, stream.cuda_stream)
+        for _ in range(args.steps):
+            v.count(d["points"], d["offsets"], out=o)
+        hip.hipEventRecord(b, stream.cuda_stream)
+        plain_ms += ev.elapsed_ms(a, b) / args.steps
+    identical = all(torch.equal(c, o) for c, o in zip(batched_C, outs))
+    for v in vols:
+        v.close()
+    plan.close()
+    log(f"batched {batched_ms:.3f} ms per launch, plain sum {plain_ms:.3f} ms, identical={identical}")
+    out = {
+        "metric": "batched streamline points/s (all subjects, one graph launch) vs the plain per-subject path",
+        "value": P / (batched_ms * 1e-3), "unit": "points/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": batched_ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{len(subs)} subjects, grids between 64^3 and 145x174x145, N 5k-45k, "
+                               f"M in {{70,180,360}}, S 100k-2M", "S": S, "P": P, "schedule": plan.schedule},
+        "plain_value": P / (plain_ms * 1e-3), "plain_ms": plain_ms,
+        "batched_over_plain": plain_ms / batched_ms, "bit_identical": identical,
     }
     print(json.dumps(out), flush=True)
 

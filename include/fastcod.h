@@ -69,12 +69,11 @@ typedef struct fastcod_opts {
     int32_t variant;    /* FASTCOD_VARIANT_*                                                        */
     void *event_begin;  /* optional hipEvent_t, recorded on `stream` just before the counting kernel */
     void *event_end;    /* optional hipEvent_t, recorded on `stream` just after it                  */
-    int32_t batch;      /* flat-stream schedule: 64-point windows per pipelined batch, 2/4/8; 0 = 4 */
+    int32_t batch;      /* flat-stream schedule: 64-point windows per pipelined batch, 2 or 4; 0 = 4 */
     int32_t blocks_per_cu; /* flat-stream schedule: resident workgroups per CU, 0 = occupancy limit */
-    int32_t depth;      /* flat-stream schedule: point batches in flight per wavefront, 1/2; 0 = 1   */
 } fastcod_opts;
 
-/* Default options: {1.0f, 1, 0, FASTCOD_VARIANT_AUTO, NULL, NULL, 0, 0, 0}. */
+/* Default options: {1.0f, 1, 0, FASTCOD_VARIANT_AUTO, NULL, NULL, 0, 0}. */
 fastcod_opts fastcod_default_opts(void);
 
 /*
@@ -121,6 +120,58 @@ int fastcod_volume_count(const fastcod_volume *vol, const float *points, const i
                          void *stream);
 /* Frees the handle (synchronises its device first). */
 int fastcod_volume_destroy(fastcod_volume *vol);
+
+/*
+ * Batched form: many subjects (each its own streamlines, volumes, N, M, scale and C) counted by one
+ * persistent kernel that takes (subject, point range) work items from a single counter, the whole
+ * sequence (zero every C, partition, count, overflow fallback) captured once in a hipGraph and
+ * replayed by every launch.  Each subject's C is identical to what fastcod_count_ex gives for it
+ * (counts are exact integers and C is additive over streamline ranges).
+ */
+typedef struct fastcod_subject {
+    const float *points;              /* [P][3] float32, device                                         */
+    const int64_t *offsets;           /* [S+1] int64, device                                             */
+    int64_t n_streamlines;            /* S, 0 <= S <= INT32_MAX                                          */
+    const int32_t *roi_index_vol;     /* [Z][Y][X] int32, device                                         */
+    const int32_t *target_label_vol;  /* [Z][Y][X] int32, device                                         */
+    int32_t dims[3];                  /* {X, Y, Z}, each >= 1, X*Y*Z < 2^31                              */
+    int32_t N, M;                     /* N, M >= 1, N*M < 2^31                                           */
+    float scale;                      /* coordinate scale, finite and > 0 (1.0f = none)                  */
+    int32_t *C_out;                   /* [N][M] int32, device; overwritten by every launch               */
+} fastcod_subject;
+
+/* Schedule of the batched kernel (chosen by the tuner or the defaults). */
+typedef struct fastcod_schedule {
+    int32_t batch;           /* 64-point windows per pipelined batch: 2 or 4                             */
+    int32_t blocks_per_cu;   /* resident 256-thread workgroups per CU                                    */
+    int32_t items_per_wave;  /* work items per wavefront (point-balanced over all subjects)              */
+    float tuned_ms;          /* duration of one launch measured by the tuner (0 if not tuned)           */
+} fastcod_schedule;
+
+typedef struct fastcod_plan fastcod_plan;
+
+#define FASTCOD_PLAN_TUNE 1u  /* time candidate schedules on these subjects and keep the fastest        */
+
+/*
+ * Builds a plan (synchronous on `stream`): compact volumes of every distinct volume pair (built
+ * once, kept by the plan; the source volumes may be freed afterwards), work-item tables, scratch,
+ * and the captured graph.  Points, offsets and C_out are read/written by every launch, so their
+ * contents may change between launches but their addresses and sizes may not.
+ * tune_cache: optional HOST path of a text file of tuned schedules (read, and appended to when
+ * FASTCOD_PLAN_TUNE times a new kind of batch); NULL = no file.
+ * Errors: EINVAL (bad subject, or a grid too thin for the compact volume), ENOMEM, EHIP.
+ */
+int fastcod_plan_create(const fastcod_subject *subjects, int32_t n, uint32_t flags, const char *tune_cache,
+                        void *stream, fastcod_plan **out);
+/* One replay of the captured graph on `stream` (asynchronous).  Launches of one plan must not
+ * overlap in time (they share the plan's counters); serialise them on one stream. */
+int fastcod_plan_launch(fastcod_plan *plan, void *stream);
+/* The schedule the plan uses. */
+int fastcod_plan_get_schedule(const fastcod_plan *plan, fastcod_schedule *out);
+/* Frees the plan (synchronises its device first). */
+int fastcod_plan_destroy(fastcod_plan *plan);
+/* create + launch + synchronise + destroy, default schedule. */
+int fastcod_count_batched(const fastcod_subject *subjects, int32_t n, void *stream);
 
 /*
  * Input check (synchronous): offsets[0] == 0 and nondecreasing, ROI values < N and label

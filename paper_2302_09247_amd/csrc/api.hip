@@ -3,7 +3,11 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
+#include <tuple>
+#include <cstdio>
 #include <map>
+#include <vector>
 #include <mutex>
 #include <string>
 #include <utility>
@@ -129,7 +133,8 @@ struct CompactLayout {
     size_t off_mb, off_tiles, off_coarse, off_codes, bytes;
 };
 
-bool compact_layout(const int32_t dims[3], int32_t N, int32_t M, CompactLayout &L) {
+bool compact_layout(const int32_t dims[3], int32_t N, int32_t M, CompactLayout &L,
+                    int32_t max_coarse_words = kMaxCoarseWords) {
     L.SBX = (dims[0] + 15) / 16;
     L.SBY = (dims[1] + 7) / 8;
     L.SBZ = (dims[2] + 7) / 8;
@@ -153,7 +158,7 @@ bool compact_layout(const int32_t dims[3], int32_t N, int32_t M, CompactLayout &
         L.CBZ = (dims[2] + c - 1) / c;
         const int64_t ncb = (int64_t)L.CBX * L.CBY * L.CBZ;
         L.ncoarse_words = (int32_t)(2 * ((ncb + 63) / 64));
-        if (L.ncoarse_words <= kMaxCoarseWords) break;
+        if (L.ncoarse_words <= max_coarse_words) break;
     }
     if (L.cs > 5) return false;
     auto align = [](size_t v) { return (v + 255) & ~size_t(255); };
@@ -217,9 +222,8 @@ int check_stream_args(const float *points, const int64_t *offsets, int64_t S, in
     if (o.upsample != 1) return fail(FASTCOD_EINVAL, "upsample must be 1");
     if (!(o.scale == o.scale) || o.scale <= 0.0f || isinf(o.scale)) return fail(FASTCOD_EINVAL, "scale must be finite and > 0");
     if (o.variant < FASTCOD_VARIANT_AUTO || o.variant > FASTCOD_VARIANT_STREAM) return fail(FASTCOD_EINVAL, "unknown variant");
-    if (o.batch != 0 && o.batch != 2 && o.batch != 4 && o.batch != 8) return fail(FASTCOD_EINVAL, "batch must be 0, 2, 4 or 8");
+    if (o.batch != 0 && o.batch != 2 && o.batch != 4) return fail(FASTCOD_EINVAL, "batch must be 0, 2 or 4");
     if (o.blocks_per_cu < 0) return fail(FASTCOD_EINVAL, "blocks_per_cu must be >= 0");
-    if (o.depth != 0 && o.depth != 1 && o.depth != 2) return fail(FASTCOD_EINVAL, "depth must be 0, 1 or 2");
     return FASTCOD_OK;
 }
 
@@ -299,9 +303,8 @@ int enqueue_count(Workspace &ws, int dev, const float *points, const int64_t *of
     FC_HIP(fc::launch_fill_u64(a.ovf.count, 2, cus, st));   // overflow count and range counter
     const int64_t resident = (int64_t)cus * kBlocksPerCU;
     if (cv) {
-        const int batch = o.batch == 2 || o.batch == 8 ? o.batch : 4;
-        const int depth = o.depth == 2 ? 2 : 1;
-        int per_cu = fc::count_stream_blocks_per_cu(o.scale != 1.0f, cv->packed != 0, batch, depth,
+        const int batch = o.batch == 2 ? 2 : 4;
+        int per_cu = fc::count_stream_blocks_per_cu(o.scale != 1.0f, cv->packed != 0, batch,
                                                     4 * (size_t)cv->ncoarse_words);
         if (o.blocks_per_cu > 0 && o.blocks_per_cu < per_cu) per_cu = o.blocks_per_cu;
         const int64_t blocks = (int64_t)cus * per_cu;
@@ -310,7 +313,7 @@ int enqueue_count(Workspace &ws, int dev, const float *points, const int64_t *of
         int32_t *first = static_cast<int32_t *>(ws.first.p);
         FC_HIP(fc::launch_partition(offsets, S, nparts, first, cus, st));
         if (o.event_begin) FC_HIP(hipEventRecord((hipEvent_t)o.event_begin, st));
-        FC_HIP(fc::launch_count_stream(a, *cv, first, nparts, (int)blocks, batch, depth, st));
+        FC_HIP(fc::launch_count_stream(a, *cv, first, nparts, (int)blocks, batch, st));
         if (o.event_end) FC_HIP(hipEventRecord((hipEvent_t)o.event_end, st));
         FC_HIP(fc::launch_fallback_compact(a, *cv, fs, st));
         if (transposed) FC_HIP(fc::launch_transpose(a.C, C, N, M, (o.flags & FASTCOD_ACCUMULATE) != 0, st));
@@ -324,6 +327,312 @@ int enqueue_count(Workspace &ws, int dev, const float *points, const int64_t *of
     }
     (void)N;
     return FASTCOD_OK;
+}
+
+// ---- batched plans ----
+constexpr int32_t kBatchedCoarseWords = 512;   // per-wavefront LDS coarse map of the batched kernel (2 KB)
+
+struct PlanSched {
+    int batch = 4, blocks_per_cu = 0, items_per_wave = 4;
+    float ms = 0.f;
+};
+
+std::string arch_name(int dev) {
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, dev) != hipSuccess) return "unknown";
+    std::string a = p.gcnArchName;
+    const size_t c = a.find(':');
+    return c == std::string::npos ? a : a.substr(0, c);
+}
+
+int log2_bucket(double v) {
+    int b = 0;
+    while (v >= 2.0) {
+        v /= 2.0;
+        ++b;
+    }
+    return b;
+}
+
+bool read_tune_cache(const char *path, const std::string &key, PlanSched &out) {
+    if (!path) return false;
+    FILE *f = fopen(path, "r");
+    if (!f) return false;
+    char k[512];
+    PlanSched ps;
+    bool found = false;
+    while (fscanf(f, "%511s %d %d %d %f", k, &ps.batch, &ps.blocks_per_cu, &ps.items_per_wave, &ps.ms) == 5)
+        if (key == k) {
+            out = ps;
+            found = true;
+        }
+    fclose(f);
+    return found;
+}
+
+void append_tune_cache(const char *path, const std::string &key, const PlanSched &ps) {
+    if (!path) return;
+    FILE *f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "%s %d %d %d %.4f\n", key.c_str(), ps.batch, ps.blocks_per_cu, ps.items_per_wave, ps.ms);
+    fclose(f);
+}
+
+}  // namespace
+
+
+struct fastcod_plan {
+    int device = 0;
+    int32_t n = 0;
+    std::vector<fc::StreamSubject> subs;   // host copy of the descriptor table
+    std::vector<int64_t> points;           // P of every subject (read at creation)
+    std::vector<int64_t> sizes;            // N*M of every subject
+    std::vector<void *> volumes;           // owned compact volumes
+    DevBuf d_subs, d_sizes, d_item_base, d_items, d_ovf, d_fallback;
+    fc::FallbackScratch fs{};
+    fc::Overflow ovf{};
+    PlanSched sched;
+    int64_t nitems = 0;
+    int blocks = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+// Work-item split for a schedule: items in proportion to every subject's points.
+int plan_items(fastcod_plan &pl, const PlanSched &ps, int cus, hipStream_t st) {
+    int per_cu = fc::count_batched_blocks_per_cu(ps.batch, kBatchedCoarseWords);
+    if (ps.blocks_per_cu > 0 && ps.blocks_per_cu < per_cu) per_cu = ps.blocks_per_cu;
+    pl.blocks = cus * per_cu;
+    const int64_t total = (int64_t)pl.blocks * fc::kWavesPerBlock * ps.items_per_wave;
+    double ptot = 0;
+    for (int64_t p : pl.points) ptot += (double)p;
+    std::vector<int64_t> base(pl.n + 1, 0);
+    for (int32_t k = 0; k < pl.n; ++k) {
+        int64_t ni = 0;
+        if (pl.subs[k].S > 0) {
+            ni = ptot > 0 ? (int64_t)((double)total * (double)pl.points[k] / ptot + 0.5) : 1;
+            if (ni < 1) ni = 1;
+            if (ni > pl.subs[k].S) ni = pl.subs[k].S;
+        }
+        base[k + 1] = base[k] + ni;
+    }
+    pl.nitems = base[pl.n];
+    FC_HIP(pl.d_item_base.ensure(8 * (size_t)(pl.n + 1), false));
+    FC_HIP(pl.d_items.ensure(8 * (size_t)(pl.nitems + 1), false));
+    FC_HIP(hipMemcpyAsync(pl.d_item_base.p, base.data(), 8 * (size_t)(pl.n + 1), hipMemcpyHostToDevice, st));
+    FC_HIP(hipStreamSynchronize(st));
+    return FASTCOD_OK;
+}
+
+// The launch sequence (eager or under capture).
+int plan_enqueue(fastcod_plan &pl, int cus, hipStream_t st) {
+    const auto *subs = static_cast<const fc::StreamSubject *>(pl.d_subs.p);
+    FC_HIP(fc::launch_zero_subjects(subs, static_cast<const int64_t *>(pl.d_sizes.p), pl.n, cus, st));
+    FC_HIP(fc::launch_fill_u64(pl.ovf.count, 2, cus, st));
+    if (pl.nitems > 0) {
+        FC_HIP(fc::launch_partition_batched(subs, static_cast<const int64_t *>(pl.d_item_base.p), pl.n, pl.nitems,
+                                            static_cast<int2 *>(pl.d_items.p), cus, st));
+        FC_HIP(fc::launch_count_batched(subs, static_cast<const int2 *>(pl.d_items.p), pl.nitems, pl.ovf,
+                                        kBatchedCoarseWords, pl.blocks, pl.sched.batch, st));
+        FC_HIP(fc::launch_fallback_batched(subs, pl.n, pl.ovf, pl.fs, st));
+    }
+    return FASTCOD_OK;
+}
+
+int plan_capture(fastcod_plan &pl, int cus) {
+    hipStream_t cs = nullptr;
+    FC_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    int rc = FASTCOD_OK;
+    if (e == hipSuccess) rc = plan_enqueue(pl, cus, cs);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(cs, &g);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
+    pl.graph = g;
+    FC_HIP(hipGraphInstantiate(&pl.exec, g, nullptr, nullptr, 0));
+    return FASTCOD_OK;
+}
+
+void plan_free(fastcod_plan *pl) {
+    if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+    if (pl->graph) (void)hipGraphDestroy(pl->graph);
+    for (void *v : pl->volumes) (void)hipFree(v);
+    pl->d_subs.release();
+    pl->d_sizes.release();
+    pl->d_item_base.release();
+    pl->d_items.release();
+    pl->d_ovf.release();
+    pl->d_fallback.release();
+    delete pl;
+}
+
+int plan_check(const fastcod_subject *subjects, int32_t n) {
+    for (int32_t k = 0; k < n; ++k) {
+        const fastcod_subject &u = subjects[k];
+        int rc = check_volume_args(u.roi_index_vol, u.target_label_vol, u.dims, u.N, u.M);
+        if (rc) return fail(rc, "subject " + std::to_string(k) + ": " + g_last_error);
+        fastcod_opts o = fastcod_default_opts();
+        o.scale = u.scale;
+        rc = check_stream_args(u.points, u.offsets, u.n_streamlines, u.C_out, o);
+        if (rc) return fail(rc, "subject " + std::to_string(k) + ": " + g_last_error);
+        CompactLayout L;
+        if (!compact_layout(u.dims, u.N, u.M, L, kBatchedCoarseWords))
+            return fail(FASTCOD_EINVAL, "subject " + std::to_string(k) + ": grid too thin for the compact volume");
+    }
+    return FASTCOD_OK;
+}
+
+int plan_build(const fastcod_subject *subjects, int32_t n, uint32_t flags, const char *tune_cache, hipStream_t st,
+               fastcod_plan *pl) {
+    int dev;
+    int rc = current_device(&dev);
+    if (rc) return rc;
+    pl->device = dev;
+    pl->n = n;
+    const int cus = cu_count(dev);
+    // validate, and build one compact volume per distinct volume pair
+    struct Key {
+        const int32_t *roi, *lab;
+        int32_t X, Y, Z, N, M;
+        bool operator<(const Key &o) const {
+            return std::tie(roi, lab, X, Y, Z, N, M) < std::tie(o.roi, o.lab, o.X, o.Y, o.Z, o.N, o.M);
+        }
+    };
+    std::map<Key, fc::CompactVol> built;
+    int64_t total_s = 0, max_nw_n = 1, max_nw_m = 1, max_m = 1;
+    for (int32_t k = 0; k < n; ++k) {
+        const fastcod_subject &u = subjects[k];
+        rc = check_volume_args(u.roi_index_vol, u.target_label_vol, u.dims, u.N, u.M);
+        if (rc) return fail(rc, "subject " + std::to_string(k) + ": " + g_last_error);
+        fastcod_opts o = fastcod_default_opts();
+        o.scale = u.scale;
+        rc = check_stream_args(u.points, u.offsets, u.n_streamlines, u.C_out, o);
+        if (rc) return fail(rc, "subject " + std::to_string(k) + ": " + g_last_error);
+        CompactLayout L;
+        if (!compact_layout(u.dims, u.N, u.M, L, kBatchedCoarseWords))
+            return fail(FASTCOD_EINVAL, "subject " + std::to_string(k) + ": grid too thin for the compact volume");
+        const Key key{u.roi_index_vol, u.target_label_vol, u.dims[0], u.dims[1], u.dims[2], u.N, u.M};
+        fc::CompactVol cv;
+        auto it = built.find(key);
+        if (it == built.end()) {
+            void *buf = nullptr;
+            hipError_t e = hipMalloc(&buf, L.bytes);
+            if (e != hipSuccess) return fail(FASTCOD_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+            pl->volumes.push_back(buf);
+            cv = compact_view(buf, L, u.N, u.M);
+            char *b = static_cast<char *>(buf);
+            FC_HIP(fc::launch_compact_build(u.roi_index_vol, u.target_label_vol, make_grid(u.dims), u.N, u.M, cv,
+                                            reinterpret_cast<uint32_t *>(b + L.off_mb), b + L.off_codes,
+                                            reinterpret_cast<uint32_t *>(b + L.off_tiles),
+                                            reinterpret_cast<uint32_t *>(b + L.off_coarse), L.W, cus, st));
+            built[key] = cv;
+        } else {
+            cv = it->second;
+        }
+        fc::StreamSubject ss;
+        ss.pts = u.points;
+        ss.offsets = u.offsets;
+        ss.S = u.n_streamlines;
+        ss.g = make_grid(u.dims);
+        ss.scale = u.scale;
+        ss.cv = cv;
+        ss.C = u.C_out;
+        ss.si = (uint32_t)u.M;
+        ss.sm = 1u;
+        pl->subs.push_back(ss);
+        pl->sizes.push_back((int64_t)u.N * u.M);
+        total_s += u.n_streamlines;
+        max_nw_n = std::max<int64_t>(max_nw_n, (u.N + 31) / 32);
+        max_nw_m = std::max<int64_t>(max_nw_m, (u.M + 31) / 32);
+        max_m = std::max<int64_t>(max_m, u.M);
+    }
+    // point counts (the item split follows them)
+    pl->points.assign(n, 0);
+    for (int32_t k = 0; k < n; ++k)
+        if (pl->subs[k].S > 0)
+            FC_HIP(hipMemcpyAsync(&pl->points[k], pl->subs[k].offsets + pl->subs[k].S, 8, hipMemcpyDeviceToHost, st));
+    FC_HIP(hipStreamSynchronize(st));
+    // device tables
+    FC_HIP(pl->d_subs.ensure(sizeof(fc::StreamSubject) * (size_t)n, false));
+    FC_HIP(pl->d_sizes.ensure(8 * (size_t)n, false));
+    FC_HIP(hipMemcpyAsync(pl->d_subs.p, pl->subs.data(), sizeof(fc::StreamSubject) * (size_t)n, hipMemcpyHostToDevice, st));
+    FC_HIP(hipMemcpyAsync(pl->d_sizes.p, pl->sizes.data(), 8 * (size_t)n, hipMemcpyHostToDevice, st));
+    FC_HIP(pl->d_ovf.ensure(256 + 8 * (size_t)std::max<int64_t>(total_s, 1), false));
+    pl->ovf.count = static_cast<unsigned long long *>(pl->d_ovf.p);
+    pl->ovf.work = pl->ovf.count + 1;
+    pl->ovf.list = reinterpret_cast<int64_t *>(static_cast<char *>(pl->d_ovf.p) + 256);
+    pl->ovf.cap = std::max<int64_t>(total_s, 1);
+    pl->fs.nwordsN = (int32_t)max_nw_n;
+    pl->fs.nwordsM = (int32_t)max_nw_m;
+    pl->fs.stride = (max_nw_n + max_nw_m + max_m + 63) & ~int64_t(63);
+    int64_t fb = (int64_t(256) << 20) / (4 * pl->fs.stride);
+    fb = std::min<int64_t>(std::max<int64_t>(fb, 1), 64);
+    pl->fs.blocks = (int32_t)fb;
+    FC_HIP(pl->d_fallback.ensure((size_t)(4 * pl->fs.stride * fb), true));
+    pl->fs.words = static_cast<uint32_t *>(pl->d_fallback.p);
+    // schedule: cache, tuner, or defaults
+    double ptot = 0, nm = 0, spts = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        ptot += (double)pl->points[k];
+        nm += (double)pl->sizes[k];
+        spts += (double)pl->subs[k].S;
+    }
+    const std::string key = arch_name(dev) + ":cu" + std::to_string(cus) + ":n" + std::to_string(log2_bucket(n)) +
+                            ":P" + std::to_string(log2_bucket(ptot)) + ":NM" + std::to_string(log2_bucket(nm / n)) +
+                            ":T" + std::to_string(log2_bucket(spts > 0 ? ptot / spts : 0));
+    PlanSched ps;
+    if (read_tune_cache(tune_cache, key, ps)) {
+        pl->sched = ps;
+    } else if (flags & FASTCOD_PLAN_TUNE) {
+        hipEvent_t e0, e1;
+        FC_HIP(hipEventCreate(&e0));
+        FC_HIP(hipEventCreate(&e1));
+        PlanSched best;
+        best.ms = -1.f;
+        for (int batch : {2, 4}) {
+            const int occ = fc::count_batched_blocks_per_cu(batch, kBatchedCoarseWords);
+            for (int bpc : {occ, occ - 1, occ - 2}) {
+                if (bpc < 1) continue;
+                for (int ipw : {2, 4, 8}) {
+                    PlanSched c;
+                    c.batch = batch;
+                    c.blocks_per_cu = bpc;
+                    c.items_per_wave = ipw;
+                    rc = plan_items(*pl, c, cus, st);
+                    if (rc) return rc;
+                    pl->sched = c;
+                    float ms = 0.f;
+                    for (int rep = 0; rep < 2; ++rep) {
+                        FC_HIP(hipEventRecord(e0, st));
+                        rc = plan_enqueue(*pl, cus, st);
+                        if (rc) return rc;
+                        FC_HIP(hipEventRecord(e1, st));
+                        FC_HIP(hipEventSynchronize(e1));
+                        FC_HIP(hipEventElapsedTime(&ms, e0, e1));
+                    }
+                    c.ms = ms;
+                    if (best.ms < 0.f || ms < best.ms) best = c;
+                }
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        pl->sched = best;
+        append_tune_cache(tune_cache, key, best);
+    } else {
+        pl->sched = PlanSched{};
+    }
+    rc = plan_items(*pl, pl->sched, cus, st);
+    if (rc) return rc;
+    return plan_capture(*pl, cus);
 }
 
 }  // namespace
@@ -349,7 +658,6 @@ fastcod_opts fastcod_default_opts(void) {
     o.event_end = nullptr;
     o.batch = 0;
     o.blocks_per_cu = 0;
-    o.depth = 0;
     return o;
 }
 
@@ -529,6 +837,75 @@ int fastcod_release(void) {
     }
     g_ws.clear();
     (void)hipSetDevice(prev);
+    return FASTCOD_OK;
+}
+
+int fastcod_plan_create(const fastcod_subject *subjects, int32_t n, uint32_t flags, const char *tune_cache,
+                        void *stream, fastcod_plan **out) {
+    g_last_error.clear();
+    if (!out) return fail(FASTCOD_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || !subjects) return fail(FASTCOD_EINVAL, "need at least one subject");
+    const int rc0 = plan_check(subjects, n);   // argument errors before any HIP call
+    if (rc0) return rc0;
+    fastcod_plan *pl = new fastcod_plan();
+    const int rc = plan_build(subjects, n, flags, tune_cache, static_cast<hipStream_t>(stream), pl);
+    if (rc) {
+        const std::string msg = g_last_error;
+        (void)hipDeviceSynchronize();
+        plan_free(pl);
+        return fail(rc, msg);
+    }
+    *out = pl;
+    return FASTCOD_OK;
+}
+
+int fastcod_plan_launch(fastcod_plan *plan, void *stream) {
+    g_last_error.clear();
+    if (!plan || !plan->exec) return fail(FASTCOD_EINVAL, "plan is NULL");
+    int dev;
+    const int rc = current_device(&dev);
+    if (rc) return rc;
+    if (dev != plan->device) return fail(FASTCOD_EINVAL, "plan lives on another device");
+    FC_HIP(hipGraphLaunch(plan->exec, static_cast<hipStream_t>(stream)));
+    return FASTCOD_OK;
+}
+
+int fastcod_plan_get_schedule(const fastcod_plan *plan, fastcod_schedule *out) {
+    g_last_error.clear();
+    if (!plan || !out) return fail(FASTCOD_EINVAL, "NULL argument");
+    out->batch = plan->sched.batch;
+    out->blocks_per_cu = plan->blocks / std::max(1, cu_count(plan->device));
+    out->items_per_wave = plan->sched.items_per_wave;
+    out->tuned_ms = plan->sched.ms;
+    return FASTCOD_OK;
+}
+
+int fastcod_plan_destroy(fastcod_plan *plan) {
+    g_last_error.clear();
+    if (!plan) return FASTCOD_OK;
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(plan->device);
+    const hipError_t e = hipDeviceSynchronize();
+    plan_free(plan);
+    (void)hipSetDevice(prev);
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    return FASTCOD_OK;
+}
+
+int fastcod_count_batched(const fastcod_subject *subjects, int32_t n, void *stream) {
+    fastcod_plan *pl = nullptr;
+    int rc = fastcod_plan_create(subjects, n, 0, nullptr, stream, &pl);
+    if (rc) return rc;
+    rc = fastcod_plan_launch(pl, stream);
+    if (rc == FASTCOD_OK) {
+        const hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+        if (e != hipSuccess) rc = hip_fail(e, "hipStreamSynchronize");
+    }
+    const std::string msg = g_last_error;
+    fastcod_plan_destroy(pl);
+    if (rc) return fail(rc, msg);
     return FASTCOD_OK;
 }
 

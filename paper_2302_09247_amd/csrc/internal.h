@@ -76,6 +76,19 @@ struct CountArgs {
     Overflow ovf;
 };
 
+// Everything the flat-stream kernels need about one subject (also a device-side descriptor of the
+// batched form).
+struct StreamSubject {
+    const float *pts;
+    const int64_t *offsets;
+    int64_t S;
+    Grid g;
+    float scale;
+    CompactVol cv;
+    int32_t *C;
+    uint32_t si, sm;
+};
+
 // ---- launchers (kernels.hip); every launcher returns the hipError_t of its launch ----
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, int cus, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long *p, int64_t n, int cus, hipStream_t st);
@@ -90,13 +103,13 @@ hipError_t launch_compact_build(const int32_t *roi, const int32_t *lab, Grid g, 
 hipError_t launch_partition(const int64_t *offsets, int64_t S, int64_t nparts, int32_t *first, int cus,
                             hipStream_t st);
 // resident 256-thread workgroups per CU of the flat-stream kernel
-int count_stream_blocks_per_cu(bool scaled, bool packed, int batch, int depth, size_t dyn_lds);
+int count_stream_blocks_per_cu(bool scaled, bool packed, int batch, size_t dyn_lds);
 
 hipError_t launch_count_wave(const CountArgs &a, const RasterVol &rv, int blocks, hipStream_t st);
 // wavefronts take the nparts ranges of `first` from ovf.work; batch: 64-point windows per
-// pipelined batch (2, 4 or 8); depth: batches of points in flight per wavefront (1 or 2)
+// pipelined batch (2 or 4)
 hipError_t launch_count_stream(const CountArgs &a, const CompactVol &cv, const int32_t *first, int64_t nparts,
-                               int blocks, int batch, int depth, hipStream_t st);
+                               int blocks, int batch, hipStream_t st);
 hipError_t launch_fallback_raster(const CountArgs &a, const RasterVol &rv, FallbackScratch fs,
                                   hipStream_t st);
 hipError_t launch_fallback_compact(const CountArgs &a, const CompactVol &cv, FallbackScratch fs,
@@ -104,6 +117,16 @@ hipError_t launch_fallback_compact(const CountArgs &a, const CompactVol &cv, Fal
 
 // C[i][m] = CT[m][i] (or += with accumulate), C [N][M], CT [M][N]
 hipError_t launch_transpose(const int32_t *CT, int32_t *C, int32_t N, int32_t M, bool accumulate, hipStream_t st);
+
+// batched form
+hipError_t launch_zero_subjects(const StreamSubject *subs, const int64_t *sizes, int32_t nsub, int cus, hipStream_t st);
+hipError_t launch_partition_batched(const StreamSubject *subs, const int64_t *item_base, int32_t nsub, int64_t nitems,
+                                    int2 *items, int cus, hipStream_t st);
+int count_batched_blocks_per_cu(int batch, int coarse_words);
+hipError_t launch_count_batched(const StreamSubject *subs, const int2 *items, int64_t nitems, const Overflow &ovf,
+                                int32_t coarse_words, int blocks, int batch, hipStream_t st);
+hipError_t launch_fallback_batched(const StreamSubject *subs, int32_t nsub, const Overflow &ovf, FallbackScratch fs,
+                                   hipStream_t st);
 
 hipError_t launch_validate(const int64_t *offsets, int64_t S, const int32_t *roi, const int32_t *lab,
                            int64_t nvox, int32_t N, int32_t M, int32_t *flags, int cus, hipStream_t st);

@@ -327,10 +327,12 @@ struct DeferredSet {
     }
 };
 
-__device__ __forceinline__ void push_overflow(const Overflow &o, int64_t point_index) {
+// Queue entries: point index in bits 0..47, subject in bits 48..62.
+constexpr int kSubjectShift = 48;
+__device__ __forceinline__ void push_overflow(const Overflow &o, int64_t point_index, int32_t subject = 0) {
     if (lane_id() == 0) {
         const unsigned long long k = atomicAdd(o.count, 1ull);
-        if ((int64_t)k < o.cap) o.list[k] = point_index;
+        if ((int64_t)k < o.cap) o.list[k] = point_index | ((int64_t)subject << kSubjectShift);
     }
 }
 
@@ -659,330 +661,366 @@ __device__ __forceinline__ int64_t uniform64(int64_t v) {
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-template <bool SCALED, bool PACKED, int kBatch, int kDepth>
-__global__ void __launch_bounds__(kBlock) k_count_stream(CountArgs a, CompactVol cv, const int32_t *__restrict__ first,
+constexpr int kRCap = 192, kLCap = 64, kTCap = 512;   // per-wave candidate lists and set
+constexpr int kSetWords = kRCap + 2 * kLCap + kTCap;
+using StreamSet = DeferredSet<kRCap, kLCap, kTCap>;
+
+// Counts streamlines [s0, s1) of one subject (whole streamlines only) into sub.C through `sink`.
+// `coarse` is the subject's coarse occupancy map in LDS.  PACKED: 0/1 = code width known at compile
+// time, 2 = read from cv.packed.
+template <bool SCALED, int PACKED, int kBatch>
+__device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, int64_t s0, int64_t s1, int32_t subject,
+                             const Overflow &ovf, StreamSet &set, BufferedSink &sink) {
+    const int lane = lane_id();
+    const CompactVol &cv = sub.cv;
+    const int64_t S = sub.S;
+    const int64_t Ptot = uniform64(sub.offsets[S] > 0 ? sub.offsets[S] : 0);
+    const bool packed = PACKED == 1 || (PACKED == 2 && cv.packed);
+    const __amdgpu_buffer_rsrc_t rmb = make_rsrc(cv.mb, 8ull * cv.W);
+    const __amdgpu_buffer_rsrc_t rcode = make_rsrc(packed ? (const void *)cv.codes32 : (const void *)cv.codes64,
+                                                   (packed ? 4ull : 8ull) * cv.ncodes);
+    const uint32_t lane12 = 12u * (uint32_t)lane;
+    const uint32_t bX = fbits(sub.g.Xf), bY = fbits(sub.g.Yf), bZ = fbits(sub.g.Zf);
+    const uint32_t SBX = (uint32_t)cv.SBX, SBXY = (uint32_t)cv.SBXY;
+    const uint32_t cs = (uint32_t)cv.cs, CBX = (uint32_t)cv.CBX, CBXY = (uint32_t)cv.CBXY;
+    constexpr uint32_t kOutOfRange = 0xFFFFFFF8u;   // buffer offset past every resource: reads 0, no traffic
+    const int64_t P0 = uniform64(clamp64(sub.offsets[s0], 0, Ptot));
+    const int64_t P1 = uniform64(clamp64(sub.offsets[s1], P0, Ptot));
+    if (P0 >= P1) return;
+    // Starts of streamlines s0+1 .. s1-1, 64 at a time, one per lane (P1 = "no more starts");
+    // k0 of them are consumed and `nxt` (uniform) is the next unconsumed start.
+    int64_t vb = s0 + 1;
+    int64_t voff = 0, nxt = P1;
+    int k0 = 0;
+    auto load_starts = [&]() {
+        voff = (vb + lane < s1) ? clamp64(sub.offsets[vb + lane], P0, P1) : P1;
+        k0 = 0;
+        nxt = readlane64(voff, 0);
+    };
+    auto consumed = [&](uint64_t taken) {
+        k0 += __popcll(taken);
+        if (k0 >= kWave) {
+            vb += kWave;
+            load_starts();
+        } else {
+            nxt = readlane64(voff, k0);
+        }
+    };
+    // starts in [wb, wend) (wend <= wb + 64) as lane bits relative to wb; consumes them
+    auto take_starts = [&](int64_t wb, int64_t wend) -> uint64_t {
+        uint64_t starts = 0;
+        while (nxt < wend) {
+            const uint64_t inwin = __ballot(lane >= k0 && voff < wend);
+            int64_t qv = voff - wb;
+            qv = qv < 0 ? 0 : (qv > kWave - 1 ? kWave - 1 : qv);
+            uint64_t it = inwin;
+            while (it) {
+                const int k = __builtin_ctzll(it);
+                it &= it - 1ull;
+                starts |= 1ull << __builtin_amdgcn_readlane((int)qv, k);
+            }
+            consumed(inwin);
+        }
+        return starts;
+    };
+    auto skip_starts = [&](int64_t limit) {
+        while (nxt < limit) consumed(__ballot(lane >= k0 && voff < limit));
+    };
+    load_starts();
+    int last_r = -1, last_m = -1;
+    // points from `pbase` (re-based if a range ever passes 4 GB)
+    int64_t pbase = P0;
+    __amdgpu_buffer_rsrc_t rp = make_rsrc(sub.pts + 3 * pbase, 12ull * (uint64_t)(Ptot - pbase));
+    const int64_t BW = (int64_t)kWave * kBatch;   // points per batch
+
+    // one register set of points: batch k+1 is issued into it once batch k's gathers have
+    // returned, and streams in while batch k is folded into the set
+    float ax[kBatch], ay[kBatch], az[kBatch];
+    auto load_batch = [&](int64_t w, float (&x)[kBatch], float (&y)[kBatch], float (&z)[kBatch]) {
+        if (12 * (w - pbase) + 12 * BW > (int64_t)0xF0000000ll) {
+            pbase = w;
+            rp = make_rsrc(sub.pts + 3 * pbase, 12ull * (uint64_t)(Ptot - pbase));
+        }
+        const uint32_t so = (uint32_t)(12 * (w - pbase));
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+            const auto v = __builtin_amdgcn_raw_buffer_load_b96(rp, lane12, so + 768u * b, kAuxStream);
+            x[b] = __uint_as_float(v[0]);
+            y[b] = __uint_as_float(v[1]);
+            z[b] = __uint_as_float(v[2]);
+        }
+    };
+    auto run_batch = [&](int64_t w0, float (&px)[kBatch], float (&py)[kBatch], float (&pz)[kBatch]) {
+        const int64_t rem64 = P1 - w0;
+        const int rem = rem64 > BW ? (int)BW : (int)rem64;   // valid points in this batch
+        // phase 1: voxelise and test the coarse occupancy bit in LDS; only points in occupied
+        // coarse blocks gather their occupancy word and rank base (8 bytes)
+        uint32_t word[kBatch], bit[kBatch];
+        bool in[kBatch];
+        bool anyc = false;
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+            float x = px[b], y = py[b], z = pz[b];
+            if (SCALED) {
+                x = __fmul_rn(x, sub.scale);
+                y = __fmul_rn(y, sub.scale);
+                z = __fmul_rn(z, sub.scale);
+            }
+            const float tx = __fadd_rn(x, 0.5f), ty = __fadd_rn(y, 0.5f), tz = __fadd_rn(z, 0.5f);
+            // 0 <= t < bound  <=>  bits(t) < bits(bound) as unsigned (t is never -0; NaN and
+            // negative values compare above every finite positive bound)
+            in[b] = (int)(fbits(tx) < bX) & (int)(fbits(ty) < bY) & (int)(fbits(tz) < bZ) &
+                    (int)(lane + b * kWave < rem);
+            const uint32_t ix = (uint32_t)(int)tx, iy = (uint32_t)(int)ty, iz = (uint32_t)(int)tz;
+            const uint32_t sb = __umul24(iz >> 3, SBXY) + __umul24(iy >> 3, SBX) + (ix >> 4);
+            const uint32_t bb = (ix & 15u) | ((iy & 7u) << 4) | ((iz & 7u) << 7);
+            const uint32_t cb = __umul24(iz >> cs, CBXY) + __umul24(iy >> cs, CBX) + (ix >> cs);
+            const uint32_t cw = coarse[in[b] ? (cb >> 5) : 0u];
+            in[b] = in[b] && ((cw >> (cb & 31u)) & 1u);
+            anyc |= in[b];
+            word[b] = in[b] ? ((sb << 5) | (bb >> 5)) : 0u;
+            bit[b] = bb & 31u;
+        }
+        uint32_t mw[kBatch], rank[kBatch];
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) mw[b] = rank[b] = 0u;
+        if (__ballot(anyc)) {
+#pragma unroll
+            for (int b = 0; b < kBatch; ++b) {
+                const auto e = __builtin_amdgcn_raw_buffer_load_b64(rmb, in[b] ? (word[b] << 3) : kOutOfRange, 0,
+                                                                    kAuxCached);
+                mw[b] = e[0];
+                rank[b] = e[1];
+            }
+        }
+        bool flag[kBatch];
+        bool any = false;
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+            flag[b] = in[b] && ((mw[b] >> bit[b]) & 1u);
+            any |= flag[b];
+        }
+        int r[kBatch], m[kBatch];
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) r[b] = m[b] = -1;
+        if (__ballot(any)) {
+            // phase 2: codes of the flagged voxels (other lanes read entry 0)
+#pragma unroll
+            for (int b = 0; b < kBatch; ++b)
+                rank[b] = flag[b] ? rank[b] + __popc(mw[b] & ((1u << bit[b]) - 1u)) : 0u;
+            if (PACKED == 1 || (PACKED == 2 && cv.packed)) {
+                uint32_t code[kBatch];
+#pragma unroll
+                for (int b = 0; b < kBatch; ++b)
+                    code[b] = __builtin_amdgcn_raw_buffer_load_b32(rcode, rank[b] << 2, 0, kAuxCached);
+#pragma unroll
+                for (int b = 0; b < kBatch; ++b) {
+                    const uint32_t rv = code[b] & cv.rmask, mv = code[b] >> cv.rbits;
+                    r[b] = (flag[b] && rv < (uint32_t)cv.N) ? (int)rv : -1;
+                    m[b] = (flag[b] && mv < (uint32_t)cv.M) ? (int)mv : -1;
+                }
+            } else {
+#pragma unroll
+                for (int b = 0; b < kBatch; ++b) {
+                    const auto c2 = __builtin_amdgcn_raw_buffer_load_b64(rcode, rank[b] << 3, 0, kAuxCached);
+                    r[b] = flag[b] ? (int)c2[0] : -1;
+                    m[b] = flag[b] ? (int)c2[1] : -1;
+                }
+            }
+        }
+        // every gather of this batch has returned; its point registers now take the next batch
+        const int64_t w2 = w0 + BW;
+        __builtin_amdgcn_sched_barrier(0);
+        if (w2 < P1) load_batch(w2, px, py, pz);
+        __builtin_amdgcn_sched_barrier(0);
+        uint64_t fl[kBatch];
+        uint64_t fall = 0;
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+            fl[b] = __ballot(flag[b]);
+            fall |= fl[b];
+        }
+        if (fall == 0ull) {
+            // nothing looked up: only a streamline start inside the batch matters (it closes the
+            // open streamline, whose hits all came earlier)
+            const int64_t bend = (w0 + BW < P1) ? w0 + BW : P1;
+            if (nxt < bend) {
+                if (set.has_state()) set.close(sink, sub.si, sub.sm);
+                skip_starts(bend);
+            }
+            last_r = last_m = -1;
+            return;
+        }
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+            const int64_t wb = w0 + (int64_t)b * kWave;
+            if (wb >= P1) break;
+            const int64_t wend = (wb + kWave < P1) ? wb + kWave : P1;
+            // streamline starts inside this window -> bit q of `starts` for lane q
+            const uint64_t starts = (nxt < wend) ? take_starts(wb, wend) : 0ull;
+            if (fl[b] == 0ull) {
+                if (starts && set.has_state()) set.close(sink, sub.si, sub.sm);
+                last_r = last_m = -1;
+                continue;
+            }
+            const int rb = r[b], mb = m[b];
+            // previous point's row / label (lane 0: the last point of the previous window)
+            int rp_ = __builtin_amdgcn_update_dpp(last_r, rb, 0x138, 0xF, 0xF, false);   // wave_shr:1
+            int mp_ = __builtin_amdgcn_update_dpp(last_m, mb, 0x138, 0xF, 0xF, false);
+            if ((starts >> lane) & 1ull) rp_ = mp_ = -1;  // first point of a streamline
+            const uint64_t candR = __ballot(rb >= 0 && rb != rp_);
+            const uint64_t candM = __ballot(mb >= 0 && mb != mp_);
+            last_r = __builtin_amdgcn_readlane(rb, kWave - 1);
+            last_m = __builtin_amdgcn_readlane(mb, kWave - 1);
+            if (!starts) {   // the whole window belongs to the open streamline
+                if ((candR | candM) && !set.skip && !set.append(candR, rb, candM, mb)) {
+                    push_overflow(ovf, wb, subject);
+                    set.nR = set.nL = 0;
+                    set.skip = true;
+                }
+                continue;
+            }
+            int pos = 0;
+            uint64_t st = starts;
+            for (;;) {
+                const int end = st ? __builtin_ctzll(st) : kWave;
+                const uint64_t seg = lanes_between(pos, end);
+                const uint64_t cR = candR & seg, cM = candM & seg;
+                if ((cR | cM) && !set.skip && !set.append(cR, rb, cM, mb)) {
+                    push_overflow(ovf, wb + pos, subject);
+                    set.nR = set.nL = 0;
+                    set.skip = true;
+                }
+                if (!st) break;
+                set.close(sink, sub.si, sub.sm);
+                pos = end;
+                st &= st - 1ull;
+            }
+        }
+    };
+    load_batch(P0, ax, ay, az);
+    for (int64_t w0 = P0; w0 < P1; w0 += BW) run_batch(w0, ax, ay, az);
+    set.close(sink, sub.si, sub.sm);
+}
+
+template <bool SCALED, bool PACKED, int kBatch>
+__global__ void __launch_bounds__(kBlock) k_count_stream(StreamSubject sub, Overflow ovf, const int32_t *__restrict__ first,
                                                          int64_t nparts) {
-    constexpr int RCAP = 192, LCAP = 64, TCAP = 512;
-    constexpr int kSetWords = RCAP + 2 * LCAP + TCAP;
     __shared__ uint32_t s_set[kWavesPerBlock * kSetWords];
     __shared__ uint32_t s_pend[kWavesPerBlock * kWave];
     extern __shared__ uint32_t s_coarse[];   // coarse occupancy bit map, cv.ncoarse_words words
     const int lane = lane_id(), wv = uniform32(threadIdx.x >> 6);
-    for (int k = threadIdx.x; k < cv.ncoarse_words; k += blockDim.x) s_coarse[k] = cv.coarse[k];
+    for (int k = threadIdx.x; k < sub.cv.ncoarse_words; k += blockDim.x) s_coarse[k] = sub.cv.coarse[k];
     __syncthreads();
-    DeferredSet<RCAP, LCAP, TCAP> set;
+    StreamSet set;
     set.init(s_set + wv * kSetWords);
     BufferedSink sink;
-    sink.init(s_pend + wv * kWave, a.C);
-    const int64_t S = a.S;
-    const int64_t Ptot = uniform64(a.offsets[S] > 0 ? a.offsets[S] : 0);
-    const __amdgpu_buffer_rsrc_t rmb = make_rsrc(cv.mb, 8ull * cv.W);
-    const __amdgpu_buffer_rsrc_t rcode = make_rsrc(PACKED ? (const void *)cv.codes32 : (const void *)cv.codes64,
-                                                   (PACKED ? 4ull : 8ull) * cv.ncodes);
-    const uint32_t lane12 = 12u * (uint32_t)lane;
-    const uint32_t bX = fbits(a.g.Xf), bY = fbits(a.g.Yf), bZ = fbits(a.g.Zf);
-    const uint32_t SBX = (uint32_t)cv.SBX, SBXY = (uint32_t)cv.SBXY;
-    const uint32_t cs = (uint32_t)cv.cs, CBX = (uint32_t)cv.CBX, CBXY = (uint32_t)cv.CBXY;
-    constexpr uint32_t kOutOfRange = 0xFFFFFFF8u;   // buffer offset past every resource: reads 0, no traffic
-
+    sink.init(s_pend + wv * kWave, sub.C);
     for (;;) {
         // next point range: streamlines [first[part], first[part+1])
         unsigned long long t = 0;
-        if (lane == 0) t = atomicAdd(a.ovf.work, 1ull);
+        if (lane == 0) t = atomicAdd(ovf.work, 1ull);
         const int64_t part = uniform64((int64_t)t);
         if (part >= nparts) break;
-        const int64_t s0 = uniform64(clamp64(first[part], 0, S));
-        const int64_t s1 = uniform64(clamp64(first[part + 1], s0, S));
+        const int64_t s0 = uniform64(clamp64(first[part], 0, sub.S));
+        const int64_t s1 = uniform64(clamp64(first[part + 1], s0, sub.S));
         if (s0 >= s1) continue;
-        const int64_t P0 = uniform64(clamp64(a.offsets[s0], 0, Ptot));
-        const int64_t P1 = uniform64(clamp64(a.offsets[s1], P0, Ptot));
-        if (P0 >= P1) continue;
-        // Starts of streamlines s0+1 .. s1-1, 64 at a time, one per lane (P1 = "no more starts");
-        // k0 of them are consumed and `nxt` (uniform) is the next unconsumed start.
-        int64_t vb = s0 + 1;
-        int64_t voff = 0, nxt = P1;
-        int k0 = 0;
-        auto load_starts = [&]() {
-            voff = (vb + lane < s1) ? clamp64(a.offsets[vb + lane], P0, P1) : P1;
-            k0 = 0;
-            nxt = readlane64(voff, 0);
-        };
-        auto consumed = [&](uint64_t taken) {
-            k0 += __popcll(taken);
-            if (k0 >= kWave) {
-                vb += kWave;
-                load_starts();
-            } else {
-                nxt = readlane64(voff, k0);
-            }
-        };
-        // starts in [wb, wend) (wend <= wb + 64) as lane bits relative to wb; consumes them
-        auto take_starts = [&](int64_t wb, int64_t wend) -> uint64_t {
-            uint64_t starts = 0;
-            while (nxt < wend) {
-                const uint64_t inwin = __ballot(lane >= k0 && voff < wend);
-                int64_t qv = voff - wb;
-                qv = qv < 0 ? 0 : (qv > kWave - 1 ? kWave - 1 : qv);
-                uint64_t it = inwin;
-                while (it) {
-                    const int k = __builtin_ctzll(it);
-                    it &= it - 1ull;
-                    starts |= 1ull << __builtin_amdgcn_readlane((int)qv, k);
-                }
-                consumed(inwin);
-            }
-            return starts;
-        };
-        auto skip_starts = [&](int64_t limit) {
-            while (nxt < limit) consumed(__ballot(lane >= k0 && voff < limit));
-        };
-        load_starts();
-        int last_r = -1, last_m = -1;
-        // points from `pbase` (re-based if a range ever passes 4 GB)
-        int64_t pbase = P0;
-        __amdgpu_buffer_rsrc_t rp = make_rsrc(a.pts + 3 * pbase, 12ull * (uint64_t)(Ptot - pbase));
-        const int64_t BW = (int64_t)kWave * kBatch;   // points per batch
-
-        // kDepth register sets: while batch k is voxelised, looked up and folded, the next
-        // kDepth-1 batches are in flight; batch k+kDepth is issued into k's registers once k's
-        // gathers have returned.
-        float ax[kBatch], ay[kBatch], az[kBatch], bx[kBatch], by[kBatch], bz[kBatch];
-        auto load_batch = [&](int64_t w, float (&x)[kBatch], float (&y)[kBatch], float (&z)[kBatch]) {
-            if (12 * (w - pbase) + 12 * BW > (int64_t)0xF0000000ll) {
-                pbase = w;
-                rp = make_rsrc(a.pts + 3 * pbase, 12ull * (uint64_t)(Ptot - pbase));
-            }
-            const uint32_t so = (uint32_t)(12 * (w - pbase));
-#pragma unroll
-            for (int b = 0; b < kBatch; ++b) {
-                const auto v = __builtin_amdgcn_raw_buffer_load_b96(rp, lane12, so + 768u * b, kAuxStream);
-                x[b] = __uint_as_float(v[0]);
-                y[b] = __uint_as_float(v[1]);
-                z[b] = __uint_as_float(v[2]);
-            }
-        };
-        auto run_batch = [&](int64_t w0, float (&px)[kBatch], float (&py)[kBatch], float (&pz)[kBatch]) {
-            const int64_t rem64 = P1 - w0;
-            const int rem = rem64 > BW ? (int)BW : (int)rem64;   // valid points in this batch
-            // phase 1: voxelise and test the coarse occupancy bit in LDS; only points in occupied
-            // coarse blocks gather their occupancy word and rank base (8 bytes)
-            uint32_t word[kBatch], bit[kBatch];
-            bool in[kBatch];
-            bool anyc = false;
-#pragma unroll
-            for (int b = 0; b < kBatch; ++b) {
-                float x = px[b], y = py[b], z = pz[b];
-                if (SCALED) {
-                    x = __fmul_rn(x, a.scale);
-                    y = __fmul_rn(y, a.scale);
-                    z = __fmul_rn(z, a.scale);
-                }
-                const float tx = __fadd_rn(x, 0.5f), ty = __fadd_rn(y, 0.5f), tz = __fadd_rn(z, 0.5f);
-                // 0 <= t < bound  <=>  bits(t) < bits(bound) as unsigned (t is never -0; NaN and
-                // negative values compare above every finite positive bound)
-                in[b] = (int)(fbits(tx) < bX) & (int)(fbits(ty) < bY) & (int)(fbits(tz) < bZ) &
-                        (int)(lane + b * kWave < rem);
-                const uint32_t ix = (uint32_t)(int)tx, iy = (uint32_t)(int)ty, iz = (uint32_t)(int)tz;
-                const uint32_t sb = __umul24(iz >> 3, SBXY) + __umul24(iy >> 3, SBX) + (ix >> 4);
-                const uint32_t bb = (ix & 15u) | ((iy & 7u) << 4) | ((iz & 7u) << 7);
-                const uint32_t cb = __umul24(iz >> cs, CBXY) + __umul24(iy >> cs, CBX) + (ix >> cs);
-                const uint32_t cw = s_coarse[in[b] ? (cb >> 5) : 0u];
-                in[b] = in[b] && ((cw >> (cb & 31u)) & 1u);
-                anyc |= in[b];
-                word[b] = in[b] ? ((sb << 5) | (bb >> 5)) : 0u;
-                bit[b] = bb & 31u;
-            }
-            uint32_t mw[kBatch], rank[kBatch];
-#pragma unroll
-            for (int b = 0; b < kBatch; ++b) mw[b] = rank[b] = 0u;
-            if (__ballot(anyc)) {
-#pragma unroll
-                for (int b = 0; b < kBatch; ++b) {
-                    const auto e = __builtin_amdgcn_raw_buffer_load_b64(rmb, in[b] ? (word[b] << 3) : kOutOfRange, 0,
-                                                                        kAuxCached);
-                    mw[b] = e[0];
-                    rank[b] = e[1];
-                }
-            }
-            bool flag[kBatch];
-            bool any = false;
-#pragma unroll
-            for (int b = 0; b < kBatch; ++b) {
-                flag[b] = in[b] && ((mw[b] >> bit[b]) & 1u);
-                any |= flag[b];
-            }
-            int r[kBatch], m[kBatch];
-#pragma unroll
-            for (int b = 0; b < kBatch; ++b) r[b] = m[b] = -1;
-            if (__ballot(any)) {
-                // phase 2: codes of the flagged voxels (other lanes read entry 0)
-#pragma unroll
-                for (int b = 0; b < kBatch; ++b)
-                    rank[b] = flag[b] ? rank[b] + __popc(mw[b] & ((1u << bit[b]) - 1u)) : 0u;
-                if (PACKED) {
-                    uint32_t code[kBatch];
-#pragma unroll
-                    for (int b = 0; b < kBatch; ++b)
-                        code[b] = __builtin_amdgcn_raw_buffer_load_b32(rcode, rank[b] << 2, 0, kAuxCached);
-#pragma unroll
-                    for (int b = 0; b < kBatch; ++b) {
-                        const uint32_t rv = code[b] & cv.rmask, mv = code[b] >> cv.rbits;
-                        r[b] = (flag[b] && rv < (uint32_t)cv.N) ? (int)rv : -1;
-                        m[b] = (flag[b] && mv < (uint32_t)cv.M) ? (int)mv : -1;
-                    }
-                } else {
-#pragma unroll
-                    for (int b = 0; b < kBatch; ++b) {
-                        const auto c2 = __builtin_amdgcn_raw_buffer_load_b64(rcode, rank[b] << 3, 0, kAuxCached);
-                        r[b] = flag[b] ? (int)c2[0] : -1;
-                        m[b] = flag[b] ? (int)c2[1] : -1;
-                    }
-                }
-            }
-            // every gather of this batch has returned; this batch's registers now take batch k+kDepth
-            const int64_t w2 = w0 + kDepth * BW;
-            __builtin_amdgcn_sched_barrier(0);
-            if (w2 < P1) load_batch(w2, px, py, pz);
-            __builtin_amdgcn_sched_barrier(0);
-            uint64_t fl[kBatch];
-            uint64_t fall = 0;
-#pragma unroll
-            for (int b = 0; b < kBatch; ++b) {
-                fl[b] = __ballot(flag[b]);
-                fall |= fl[b];
-            }
-            if (fall == 0ull) {
-                // nothing looked up: only a streamline start inside the batch matters (it closes the
-                // open streamline, whose hits all came earlier)
-                const int64_t bend = (w0 + BW < P1) ? w0 + BW : P1;
-                if (nxt < bend) {
-                    if (set.has_state()) set.close(sink, a.si, a.sm);
-                    skip_starts(bend);
-                }
-                last_r = last_m = -1;
-                return;
-            }
-#pragma unroll
-            for (int b = 0; b < kBatch; ++b) {
-                const int64_t wb = w0 + (int64_t)b * kWave;
-                if (wb >= P1) break;
-                const int64_t wend = (wb + kWave < P1) ? wb + kWave : P1;
-                // streamline starts inside this window -> bit q of `starts` for lane q
-                const uint64_t starts = (nxt < wend) ? take_starts(wb, wend) : 0ull;
-                if (fl[b] == 0ull) {
-                    if (starts && set.has_state()) set.close(sink, a.si, a.sm);
-                    last_r = last_m = -1;
-                    continue;
-                }
-                const int rb = r[b], mb = m[b];
-                // previous point's row / label (lane 0: the last point of the previous window)
-                int rp_ = __builtin_amdgcn_update_dpp(last_r, rb, 0x138, 0xF, 0xF, false);   // wave_shr:1
-                int mp_ = __builtin_amdgcn_update_dpp(last_m, mb, 0x138, 0xF, 0xF, false);
-                if ((starts >> lane) & 1ull) rp_ = mp_ = -1;  // first point of a streamline
-                const uint64_t candR = __ballot(rb >= 0 && rb != rp_);
-                const uint64_t candM = __ballot(mb >= 0 && mb != mp_);
-                last_r = __builtin_amdgcn_readlane(rb, kWave - 1);
-                last_m = __builtin_amdgcn_readlane(mb, kWave - 1);
-                if (!starts) {   // the whole window belongs to the open streamline
-                    if ((candR | candM) && !set.skip && !set.append(candR, rb, candM, mb)) {
-                        push_overflow(a.ovf, wb);
-                        set.nR = set.nL = 0;
-                        set.skip = true;
-                    }
-                    continue;
-                }
-                int pos = 0;
-                uint64_t st = starts;
-                for (;;) {
-                    const int end = st ? __builtin_ctzll(st) : kWave;
-                    const uint64_t seg = lanes_between(pos, end);
-                    const uint64_t cR = candR & seg, cM = candM & seg;
-                    if ((cR | cM) && !set.skip && !set.append(cR, rb, cM, mb)) {
-                        push_overflow(a.ovf, wb + pos);
-                        set.nR = set.nL = 0;
-                        set.skip = true;
-                    }
-                    if (!st) break;
-                    set.close(sink, a.si, a.sm);
-                    pos = end;
-                    st &= st - 1ull;
-                }
-            }
-        };
-        load_batch(P0, ax, ay, az);
-        if (kDepth == 1) {
-            for (int64_t w0 = P0; w0 < P1; w0 += BW) run_batch(w0, ax, ay, az);
-        } else {
-            if (P0 + BW < P1) load_batch(P0 + BW, bx, by, bz);
-            for (int64_t w0 = P0;;) {
-                run_batch(w0, ax, ay, az);
-                w0 += BW;
-                if (w0 >= P1) break;
-                run_batch(w0, bx, by, bz);
-                w0 += BW;
-                if (w0 >= P1) break;
-            }
-        }
-        set.close(sink, a.si, a.sm);
+        stream_range<SCALED, PACKED ? 1 : 0, kBatch>(sub, s_coarse, s0, s1, 0, ovf, set, sink);
     }
     sink.drain();
 }
 
-template <bool SCALED, bool PACKED, int B, int D>
+// Batched form: work items (subject, first streamline) from every subject, handed out by one
+// counter; each wavefront keeps the coarse map of the subject it last worked on in its own LDS.
+// The scale is always applied (multiplying by 1.0f is exact), the code width is read per subject.
+template <int kBatch>
+__global__ void __launch_bounds__(kBlock) k_count_batched(const StreamSubject *__restrict__ subs,
+                                                          const int2 *__restrict__ items, int64_t nitems,
+                                                          Overflow ovf, int32_t coarse_words) {
+    __shared__ uint32_t s_set[kWavesPerBlock * kSetWords];
+    __shared__ uint32_t s_pend[kWavesPerBlock * kWave];
+    extern __shared__ uint32_t s_coarse[];   // kWavesPerBlock * coarse_words
+    const int lane = lane_id(), wv = uniform32(threadIdx.x >> 6);
+    uint32_t *coarse = s_coarse + wv * coarse_words;
+    StreamSet set;
+    set.init(s_set + wv * kSetWords);
+    BufferedSink sink;
+    sink.init(s_pend + wv * kWave, nullptr);
+    int loaded = -1;
+    for (;;) {
+        unsigned long long t = 0;
+        if (lane == 0) t = atomicAdd(ovf.work, 1ull);
+        const int64_t item = uniform64((int64_t)t);
+        if (item >= nitems) break;
+        const int2 it = items[item];
+        const int subject = uniform32(it.x);
+        const StreamSubject &sub = subs[subject];
+        const int64_t s0 = uniform64(clamp64(it.y, 0, sub.S));
+        int64_t s1 = sub.S;
+        if (item + 1 < nitems) {
+            const int2 nx = items[item + 1];
+            if (nx.x == subject) s1 = nx.y;
+        }
+        s1 = uniform64(clamp64(s1, s0, sub.S));
+        if (s0 >= s1) continue;
+        if (subject != loaded) {
+            for (int k = lane; k < sub.cv.ncoarse_words; k += kWave) coarse[k] = sub.cv.coarse[k];
+            loaded = subject;
+        }
+        sink.C = sub.C;
+        stream_range<true, 2, kBatch>(sub, coarse, s0, s1, subject, ovf, set, sink);
+        sink.drain();   // the next item may belong to another subject's C
+    }
+}
+
+template <bool SCALED, bool PACKED, int B>
 static int blocks_per_cu_of(size_t dyn) {
     int n = 0;
     const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &n, reinterpret_cast<const void *>(&k_count_stream<SCALED, PACKED, B, D>), kBlock, dyn);
+        &n, reinterpret_cast<const void *>(&k_count_stream<SCALED, PACKED, B>), kBlock, dyn);
     return (e == hipSuccess && n > 0) ? n : 4;
 }
 
-template <int B, int D>
-static int blocks_per_cu_bd(bool scaled, bool packed, size_t dyn) {
-    if (scaled) return packed ? blocks_per_cu_of<true, true, B, D>(dyn) : blocks_per_cu_of<true, false, B, D>(dyn);
-    return packed ? blocks_per_cu_of<false, true, B, D>(dyn) : blocks_per_cu_of<false, false, B, D>(dyn);
+template <int B>
+static int blocks_per_cu_b(bool scaled, bool packed, size_t dyn) {
+    if (scaled) return packed ? blocks_per_cu_of<true, true, B>(dyn) : blocks_per_cu_of<true, false, B>(dyn);
+    return packed ? blocks_per_cu_of<false, true, B>(dyn) : blocks_per_cu_of<false, false, B>(dyn);
 }
 
-int count_stream_blocks_per_cu(bool scaled, bool packed, int batch, int depth, size_t dyn) {
-    if (depth == 2) {
-        switch (batch) {
-            case 2: return blocks_per_cu_bd<2, 2>(scaled, packed, dyn);
-            case 8: return blocks_per_cu_bd<8, 2>(scaled, packed, dyn);
-            default: return blocks_per_cu_bd<4, 2>(scaled, packed, dyn);
-        }
-    }
-    switch (batch) {
-        case 2: return blocks_per_cu_bd<2, 1>(scaled, packed, dyn);
-        case 8: return blocks_per_cu_bd<8, 1>(scaled, packed, dyn);
-        default: return blocks_per_cu_bd<4, 1>(scaled, packed, dyn);
-    }
+int count_stream_blocks_per_cu(bool scaled, bool packed, int batch, size_t dyn) {
+    return batch == 2 ? blocks_per_cu_b<2>(scaled, packed, dyn) : blocks_per_cu_b<4>(scaled, packed, dyn);
 }
 
-template <int B, int D>
-static void launch_stream_bd(const CountArgs &a, const CompactVol &cv, const int32_t *first, int64_t nparts, int blocks,
-                             hipStream_t st) {
+static StreamSubject stream_subject(const CountArgs &a, const CompactVol &cv) {
+    StreamSubject s;
+    s.pts = a.pts;
+    s.offsets = a.offsets;
+    s.S = a.S;
+    s.g = a.g;
+    s.scale = a.scale;
+    s.cv = cv;
+    s.C = a.C;
+    s.si = a.si;
+    s.sm = a.sm;
+    return s;
+}
+
+template <int B>
+static void launch_stream_b(const CountArgs &a, const CompactVol &cv, const int32_t *first, int64_t nparts, int blocks,
+                            hipStream_t st) {
     const bool scaled = a.scale != 1.0f;
     const size_t dyn = 4 * (size_t)cv.ncoarse_words;
-    if (scaled && cv.packed) k_count_stream<true, true, B, D><<<blocks, kBlock, dyn, st>>>(a, cv, first, nparts);
-    else if (scaled) k_count_stream<true, false, B, D><<<blocks, kBlock, dyn, st>>>(a, cv, first, nparts);
-    else if (cv.packed) k_count_stream<false, true, B, D><<<blocks, kBlock, dyn, st>>>(a, cv, first, nparts);
-    else k_count_stream<false, false, B, D><<<blocks, kBlock, dyn, st>>>(a, cv, first, nparts);
+    const StreamSubject sub = stream_subject(a, cv);
+    if (scaled && cv.packed) k_count_stream<true, true, B><<<blocks, kBlock, dyn, st>>>(sub, a.ovf, first, nparts);
+    else if (scaled) k_count_stream<true, false, B><<<blocks, kBlock, dyn, st>>>(sub, a.ovf, first, nparts);
+    else if (cv.packed) k_count_stream<false, true, B><<<blocks, kBlock, dyn, st>>>(sub, a.ovf, first, nparts);
+    else k_count_stream<false, false, B><<<blocks, kBlock, dyn, st>>>(sub, a.ovf, first, nparts);
 }
 
 hipError_t launch_count_stream(const CountArgs &a, const CompactVol &cv, const int32_t *first, int64_t nparts,
-                               int blocks, int batch, int depth, hipStream_t st) {
-    if (depth == 2) {
-        switch (batch) {
-            case 2: launch_stream_bd<2, 2>(a, cv, first, nparts, blocks, st); break;
-            case 8: launch_stream_bd<8, 2>(a, cv, first, nparts, blocks, st); break;
-            default: launch_stream_bd<4, 2>(a, cv, first, nparts, blocks, st); break;
-        }
-    } else {
-        switch (batch) {
-            case 2: launch_stream_bd<2, 1>(a, cv, first, nparts, blocks, st); break;
-            case 8: launch_stream_bd<8, 1>(a, cv, first, nparts, blocks, st); break;
-            default: launch_stream_bd<4, 1>(a, cv, first, nparts, blocks, st); break;
-        }
-    }
+                               int blocks, int batch, hipStream_t st) {
+    if (batch == 2) launch_stream_b<2>(a, cv, first, nparts, blocks, st);
+    else launch_stream_b<4>(a, cv, first, nparts, blocks, st);
     return hipGetLastError();
 }
 
@@ -990,72 +1028,179 @@ hipError_t launch_count_stream(const CountArgs &a, const CompactVol &cv, const i
 // fallback for overflowed streamlines: one workgroup per queued streamline, global bit maps
 // ---------------------------------------------------------------------------------------------
 
+// One overflowed streamline (the one containing point p), counted by a whole workgroup with the
+// workgroup's all-zero scratch: a bit map over rows, one over labels and a list of the labels.
+template <typename Lookup, bool SCALED>
+__device__ void fallback_streamline(const float *__restrict__ pts, const int64_t *__restrict__ offsets, int64_t S,
+                                    const Grid &g, float scale, const Lookup &lk, int32_t *__restrict__ C, uint32_t si,
+                                    uint32_t sm, int64_t p, uint32_t *bmN, uint32_t *bmM, uint32_t *labels,
+                                    int *s_nlab) {
+    const int64_t Ptot = offsets[S] > 0 ? offsets[S] : 0;
+    // streamline containing point p: last s with offsets[s] <= p
+    int64_t lo = 0, hi = S;  // answer in [0, S-1]
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (offsets[mid] <= p) lo = mid;
+        else hi = mid;
+    }
+    const int64_t b0 = clamp64(offsets[lo], 0, Ptot);
+    const int64_t b1 = clamp64(offsets[lo + 1], b0, Ptot);
+    if (threadIdx.x == 0) *s_nlab = 0;
+    __syncthreads();
+    // distinct labels
+    for (int64_t j = b0 + threadIdx.x; j < b1; j += blockDim.x) {
+        int ix, iy, iz, r, m;
+        if (!voxelise<SCALED>(pts[3 * j], pts[3 * j + 1], pts[3 * j + 2], scale, g, ix, iy, iz)) continue;
+        lk.get(ix, iy, iz, r, m);
+        if (m >= 0) {
+            const uint32_t bitm = 1u << (m & 31);
+            if (!(atomicOr(&bmM[m >> 5], bitm) & bitm)) {
+                const int k = atomicAdd(s_nlab, 1);
+                atomicExch(&labels[k], (uint32_t)m);
+            }
+        }
+    }
+    __syncthreads();
+    const int nlab = *s_nlab;
+    // distinct rows: the first claimant of each row adds its pairs
+    if (nlab > 0) {
+        for (int64_t j = b0 + threadIdx.x; j < b1; j += blockDim.x) {
+            int ix, iy, iz, r, m;
+            if (!voxelise<SCALED>(pts[3 * j], pts[3 * j + 1], pts[3 * j + 2], scale, g, ix, iy, iz)) continue;
+            lk.get(ix, iy, iz, r, m);
+            if (r >= 0) {
+                const uint32_t bitr = 1u << (r & 31);
+                if (!(atomicOr(&bmN[r >> 5], bitr) & bitr)) {
+                    int32_t *row = C + (uint32_t)r * si;
+                    for (int k = 0; k < nlab; ++k)
+                        atomicAdd(row + __hip_atomic_load(&labels[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) * sm, 1);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // restore the all-zero scratch (bit maps and label list)
+    for (int64_t j = b0 + threadIdx.x; j < b1; j += blockDim.x) {
+        int ix, iy, iz, r, m;
+        if (!voxelise<SCALED>(pts[3 * j], pts[3 * j + 1], pts[3 * j + 2], scale, g, ix, iy, iz)) continue;
+        lk.get(ix, iy, iz, r, m);
+        if (r >= 0) atomicExch(&bmN[r >> 5], 0u);
+        if (m >= 0) atomicExch(&bmM[m >> 5], 0u);
+    }
+    for (int k = threadIdx.x; k < nlab; k += blockDim.x) atomicExch(&labels[k], 0u);
+    __syncthreads();
+}
+
+constexpr int64_t kPointMask = (int64_t(1) << kSubjectShift) - 1;
+
 template <typename Lookup, bool SCALED>
 __global__ void __launch_bounds__(kBlock) k_fallback(CountArgs a, Lookup lk, FallbackScratch fs) {
     __shared__ int s_nlab;
-    const int64_t S = a.S;
-    const int64_t Ptot = a.offsets[S] > 0 ? a.offsets[S] : 0;
     uint32_t *bmN = fs.words + (int64_t)blockIdx.x * fs.stride;
     uint32_t *bmM = bmN + fs.nwordsN;
     uint32_t *labels = bmM + fs.nwordsM;
     const int64_t nq = (int64_t)*a.ovf.count;
     const int64_t nq_c = nq < a.ovf.cap ? nq : a.ovf.cap;
+    for (int64_t q = blockIdx.x; q < nq_c; q += gridDim.x)
+        fallback_streamline<Lookup, SCALED>(a.pts, a.offsets, a.S, a.g, a.scale, lk, a.C, a.si, a.sm,
+                                            a.ovf.list[q] & kPointMask, bmN, bmM, labels, &s_nlab);
+}
+
+// Batched fallback: the queue entry names its subject.
+__global__ void __launch_bounds__(kBlock) k_fallback_batched(const StreamSubject *__restrict__ subs, int32_t nsub,
+                                                             Overflow ovf, FallbackScratch fs) {
+    __shared__ int s_nlab;
+    uint32_t *bmN = fs.words + (int64_t)blockIdx.x * fs.stride;
+    uint32_t *bmM = bmN + fs.nwordsN;
+    uint32_t *labels = bmM + fs.nwordsM;
+    const int64_t nq = (int64_t)*ovf.count;
+    const int64_t nq_c = nq < ovf.cap ? nq : ovf.cap;
     for (int64_t q = blockIdx.x; q < nq_c; q += gridDim.x) {
-        const int64_t p = a.ovf.list[q];
-        // streamline containing point p: last s with offsets[s] <= p
-        int64_t lo = 0, hi = S;  // answer in [0, S-1]
+        const int64_t e = ovf.list[q];
+        int32_t subject = (int32_t)(e >> kSubjectShift);
+        subject = subject < 0 ? 0 : (subject >= nsub ? nsub - 1 : subject);
+        const StreamSubject &sub = subs[subject];
+        fallback_streamline<CompactLookup, true>(sub.pts, sub.offsets, sub.S, sub.g, sub.scale, CompactLookup{sub.cv},
+                                                 sub.C, sub.si, sub.sm, e & kPointMask, bmN, bmM, labels, &s_nlab);
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// batched form: work items, zero fill of every C, launchers
+// ---------------------------------------------------------------------------------------------
+
+// items[i] = (subject, first streamline at or after point floor(j * P_s / n_s)) for the j-th of the
+// subject's n_s items; item_base[s] .. item_base[s+1] are subject s's items.
+__global__ void k_partition_batched(const StreamSubject *__restrict__ subs, const int64_t *__restrict__ item_base,
+                                    int32_t nsub, int2 *__restrict__ items) {
+    const int64_t n = item_base[nsub];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        int lo = 0, hi = nsub;   // subject: last s with item_base[s] <= i
         while (hi - lo > 1) {
-            const int64_t mid = (lo + hi) >> 1;
-            if (a.offsets[mid] <= p) lo = mid;
+            const int mid = (lo + hi) >> 1;
+            if (item_base[mid] <= i) lo = mid;
             else hi = mid;
         }
-        const int64_t b0 = clamp64(a.offsets[lo], 0, Ptot);
-        const int64_t b1 = clamp64(a.offsets[lo + 1], b0, Ptot);
-        if (threadIdx.x == 0) s_nlab = 0;
-        __syncthreads();
-        // distinct labels
-        for (int64_t j = b0 + threadIdx.x; j < b1; j += blockDim.x) {
-            int ix, iy, iz, r, m;
-            if (!voxelise<SCALED>(a.pts[3 * j], a.pts[3 * j + 1], a.pts[3 * j + 2], a.scale, a.g, ix, iy, iz)) continue;
-            lk.get(ix, iy, iz, r, m);
-            if (m >= 0) {
-                const uint32_t bitm = 1u << (m & 31);
-                if (!(atomicOr(&bmM[m >> 5], bitm) & bitm)) {
-                    const int k = atomicAdd(&s_nlab, 1);
-                    atomicExch(&labels[k], (uint32_t)m);
-                }
-            }
+        const StreamSubject &sub = subs[lo];
+        const int64_t j = i - item_base[lo], ns = item_base[lo + 1] - item_base[lo];
+        int64_t P = sub.offsets[sub.S];
+        if (P < 0) P = 0;
+        const int64_t target = (int64_t)(((__int128)j * P) / ns);
+        int64_t a = 0, b = sub.S;
+        while (a < b) {
+            const int64_t mid = (a + b) >> 1;
+            if (sub.offsets[mid] < target) a = mid + 1;
+            else b = mid;
         }
-        __syncthreads();
-        const int nlab = s_nlab;
-        // distinct rows: the first claimant of each row adds its pairs
-        if (nlab > 0) {
-            for (int64_t j = b0 + threadIdx.x; j < b1; j += blockDim.x) {
-                int ix, iy, iz, r, m;
-                if (!voxelise<SCALED>(a.pts[3 * j], a.pts[3 * j + 1], a.pts[3 * j + 2], a.scale, a.g, ix, iy, iz)) continue;
-                lk.get(ix, iy, iz, r, m);
-                if (r >= 0) {
-                    const uint32_t bitr = 1u << (r & 31);
-                    if (!(atomicOr(&bmN[r >> 5], bitr) & bitr)) {
-                        int32_t *row = a.C + (uint32_t)r * a.si;
-                        for (int k = 0; k < nlab; ++k)
-                            atomicAdd(row + __hip_atomic_load(&labels[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) * a.sm, 1);
-                    }
-                }
-            }
-        }
-        __syncthreads();
-        // restore the all-zero scratch (bit maps and label list)
-        for (int64_t j = b0 + threadIdx.x; j < b1; j += blockDim.x) {
-            int ix, iy, iz, r, m;
-            if (!voxelise<SCALED>(a.pts[3 * j], a.pts[3 * j + 1], a.pts[3 * j + 2], a.scale, a.g, ix, iy, iz)) continue;
-            lk.get(ix, iy, iz, r, m);
-            if (r >= 0) atomicExch(&bmN[r >> 5], 0u);
-            if (m >= 0) atomicExch(&bmM[m >> 5], 0u);
-        }
-        for (int k = threadIdx.x; k < nlab; k += blockDim.x) atomicExch(&labels[k], 0u);
-        __syncthreads();
+        items[i] = make_int2(lo, (int)a);
     }
+}
+
+// C of every subject set to zero (blockIdx.y = subject)
+__global__ void k_zero_subjects(const StreamSubject *__restrict__ subs, const int64_t *__restrict__ sizes) {
+    const StreamSubject &sub = subs[blockIdx.y];
+    const int64_t n = sizes[blockIdx.y];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) sub.C[i] = 0;
+}
+
+hipError_t launch_zero_subjects(const StreamSubject *subs, const int64_t *sizes, int32_t nsub, int cus, hipStream_t st) {
+    k_zero_subjects<<<dim3((unsigned)(cus > 0 ? cus : 64), (unsigned)nsub), kBlock, 0, st>>>(subs, sizes);
+    return hipGetLastError();
+}
+
+hipError_t launch_partition_batched(const StreamSubject *subs, const int64_t *item_base, int32_t nsub, int64_t nitems,
+                                    int2 *items, int cus, hipStream_t st) {
+    k_partition_batched<<<fill_blocks(nitems, cus), kBlock, 0, st>>>(subs, item_base, nsub, items);
+    return hipGetLastError();
+}
+
+template <int B>
+static int batched_blocks_per_cu_of(size_t dyn) {
+    int n = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &n, reinterpret_cast<const void *>(&k_count_batched<B>), kBlock, dyn);
+    return (e == hipSuccess && n > 0) ? n : 4;
+}
+
+int count_batched_blocks_per_cu(int batch, int coarse_words) {
+    const size_t dyn = 4 * (size_t)kWavesPerBlock * (size_t)coarse_words;
+    return batch == 2 ? batched_blocks_per_cu_of<2>(dyn) : batched_blocks_per_cu_of<4>(dyn);
+}
+
+hipError_t launch_count_batched(const StreamSubject *subs, const int2 *items, int64_t nitems, const Overflow &ovf,
+                                int32_t coarse_words, int blocks, int batch, hipStream_t st) {
+    const size_t dyn = 4 * (size_t)kWavesPerBlock * (size_t)coarse_words;
+    if (batch == 2) k_count_batched<2><<<blocks, kBlock, dyn, st>>>(subs, items, nitems, ovf, coarse_words);
+    else k_count_batched<4><<<blocks, kBlock, dyn, st>>>(subs, items, nitems, ovf, coarse_words);
+    return hipGetLastError();
+}
+
+hipError_t launch_fallback_batched(const StreamSubject *subs, int32_t nsub, const Overflow &ovf, FallbackScratch fs,
+                                   hipStream_t st) {
+    k_fallback_batched<<<fs.blocks, kBlock, 0, st>>>(subs, nsub, ovf, fs);
+    return hipGetLastError();
 }
 
 template <typename Lookup>

@@ -24,7 +24,10 @@ EXPORTS = (
     "fastcod_default_opts", "fastcod_count", "fastcod_count_ex", "fastcod_volume_create",
     "fastcod_volume_bytes", "fastcod_volume_count", "fastcod_volume_destroy", "fastcod_validate",
     "fastcod_strerror", "fastcod_last_error", "fastcod_release",
+    "fastcod_plan_create", "fastcod_plan_launch", "fastcod_plan_get_schedule", "fastcod_plan_destroy",
+    "fastcod_count_batched",
 )
+PLAN_TUNE = 1
 
 
 class FastcodError(RuntimeError):
@@ -36,7 +39,19 @@ class FastcodError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("scale", ctypes.c_float), ("upsample", ctypes.c_int32), ("flags", ctypes.c_uint32),
                 ("variant", ctypes.c_int32), ("event_begin", ctypes.c_void_p), ("event_end", ctypes.c_void_p),
-                ("batch", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32), ("depth", ctypes.c_int32)]
+                ("batch", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32)]
+
+
+class Subject(ctypes.Structure):
+    _fields_ = [("points", ctypes.c_void_p), ("offsets", ctypes.c_void_p), ("n_streamlines", ctypes.c_int64),
+                ("roi_index_vol", ctypes.c_void_p), ("target_label_vol", ctypes.c_void_p),
+                ("dims", ctypes.c_int32 * 3), ("N", ctypes.c_int32), ("M", ctypes.c_int32),
+                ("scale", ctypes.c_float), ("C_out", ctypes.c_void_p)]
+
+
+class Schedule(ctypes.Structure):
+    _fields_ = [("batch", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32), ("items_per_wave", ctypes.c_int32),
+                ("tuned_ms", ctypes.c_float)]
 
 
 _lib = None
@@ -64,10 +79,16 @@ def load(path: str = LIB_PATH):
     lib.fastcod_strerror.argtypes = [ctypes.c_int]
     lib.fastcod_strerror.restype = ctypes.c_char_p
     lib.fastcod_last_error.restype = ctypes.c_char_p
+    lib.fastcod_plan_create.argtypes = [ctypes.POINTER(Subject), i32, u32, ctypes.c_char_p, _vp, ctypes.POINTER(_vp)]
+    lib.fastcod_plan_launch.argtypes = [_vp, _vp]
+    lib.fastcod_plan_get_schedule.argtypes = [_vp, ctypes.POINTER(Schedule)]
+    lib.fastcod_plan_destroy.argtypes = [_vp]
+    lib.fastcod_count_batched.argtypes = [ctypes.POINTER(Subject), i32, _vp]
     for name in ("fastcod_count", "fastcod_count_ex", "fastcod_volume_create", "fastcod_volume_count",
-                 "fastcod_volume_destroy", "fastcod_validate", "fastcod_release"):
+                 "fastcod_volume_destroy", "fastcod_validate", "fastcod_release", "fastcod_plan_create",
+                 "fastcod_plan_launch", "fastcod_plan_get_schedule", "fastcod_plan_destroy",
+                 "fastcod_count_batched"):
         getattr(lib, name).restype = ctypes.c_int
-    del u32
     _lib = lib
     return lib
 
@@ -111,7 +132,7 @@ def _dev(t: torch.Tensor, dtype, name: str, shape=None) -> torch.Tensor:
 
 def make_opts(scale: float = 1.0, upsample: int = 1, accumulate: bool = False, validate: bool = False,
               variant: int = VARIANT_AUTO, events: Optional[Tuple[int, int]] = None, batch: int = 0,
-              blocks_per_cu: int = 0, depth: int = 0) -> Opts:
+              blocks_per_cu: int = 0) -> Opts:
     o = load().fastcod_default_opts()
     o.scale = float(scale)
     o.upsample = int(upsample)
@@ -121,15 +142,14 @@ def make_opts(scale: float = 1.0, upsample: int = 1, accumulate: bool = False, v
         o.event_begin, o.event_end = events
     o.batch = int(batch)
     o.blocks_per_cu = int(blocks_per_cu)
-    o.depth = int(depth)
     return o
 
 
 def count(points: torch.Tensor, offsets: torch.Tensor, roi: torch.Tensor, lab: torch.Tensor, N: int, M: int, *,
           scale: float = 1.0, upsample: int = 1, accumulate: bool = False, validate: bool = False,
           variant: int = VARIANT_AUTO, out: Optional[torch.Tensor] = None, stream=None,
-          events: Optional[Tuple[int, int]] = None, batch: int = 0, blocks_per_cu: int = 0,
-          depth: int = 0) -> torch.Tensor:
+          events: Optional[Tuple[int, int]] = None, batch: int = 0,
+          blocks_per_cu: int = 0) -> torch.Tensor:
     """C[N, M] (int32, on the points' device) of the pass-through definition (fastcod_count_ex).
 
     points [P,3] float32, offsets [S+1] int64, roi/lab [Z,Y,X] int32, all on one HIP device.
@@ -147,7 +167,7 @@ def count(points: torch.Tensor, offsets: torch.Tensor, roi: torch.Tensor, lab: t
     if tuple(out.shape) != (N, M):
         raise ValueError("out must be [N, M]")
     dims = (ctypes.c_int32 * 3)(int(roi.shape[2]), int(roi.shape[1]), int(roi.shape[0]))
-    o = make_opts(scale, upsample, accumulate, validate, variant, events, batch, blocks_per_cu, depth)
+    o = make_opts(scale, upsample, accumulate, validate, variant, events, batch, blocks_per_cu)
     S = int(offsets.shape[0]) - 1
     with torch.cuda.device(points.device):
         _check(lib.fastcod_count_ex(_points_ptr(points), offsets.data_ptr(), S, roi.data_ptr(), lab.data_ptr(),
@@ -220,3 +240,78 @@ def validate(offsets: torch.Tensor, roi: torch.Tensor, lab: torch.Tensor, N: int
 
 def release() -> None:
     _check(load().fastcod_release())
+
+
+def make_subject(points: torch.Tensor, offsets: torch.Tensor, roi: torch.Tensor, lab: torch.Tensor, N: int, M: int,
+                 C: torch.Tensor, scale: float = 1.0) -> Subject:
+    """C-ABI descriptor of one subject of a batched plan (the tensors must outlive the plan)."""
+    _dev(points, torch.float32, "points", (3,))
+    _dev(offsets, torch.int64, "offsets")
+    _dev(roi, torch.int32, "roi")
+    _dev(lab, torch.int32, "lab")
+    _dev(C, torch.int32, "C")
+    if roi.dim() != 3 or roi.shape != lab.shape or tuple(C.shape) != (N, M):
+        raise ValueError("bad volume or C shape")
+    u = Subject()
+    u.points = _points_ptr(points)
+    u.offsets = offsets.data_ptr()
+    u.n_streamlines = int(offsets.shape[0]) - 1
+    u.roi_index_vol = roi.data_ptr()
+    u.target_label_vol = lab.data_ptr()
+    u.dims[0], u.dims[1], u.dims[2] = int(roi.shape[2]), int(roi.shape[1]), int(roi.shape[0])
+    u.N, u.M = int(N), int(M)
+    u.scale = float(scale)
+    u.C_out = C.data_ptr()
+    return u
+
+
+class Plan:
+    """Batched counting plan (fastcod_plan_*): one captured graph counting every subject.
+
+    ``subjects``: sequence of dicts with points, offsets, roi, lab, N, M, C and optional scale
+    (CUDA tensors, kept alive by the plan object)."""
+
+    def __init__(self, subjects, tune: bool = False, tune_cache: Optional[str] = None, stream=None):
+        lib = load()
+        self._keep = list(subjects)
+        arr = (Subject * len(subjects))(*[make_subject(d["points"], d["offsets"], d["roi"], d["lab"], d["N"], d["M"],
+                                                       d["C"], d.get("scale", 1.0)) for d in subjects])
+        h = _vp()
+        dev = subjects[0]["points"].device
+        with torch.cuda.device(dev):
+            _check(lib.fastcod_plan_create(arr, len(subjects), PLAN_TUNE if tune else 0,
+                                           tune_cache.encode() if tune_cache else None, _stream_ptr(stream),
+                                           ctypes.byref(h)))
+        self._h = h
+        self.device = dev
+
+    def launch(self, stream=None) -> None:
+        with torch.cuda.device(self.device):
+            _check(load().fastcod_plan_launch(self._h, _stream_ptr(stream)))
+
+    @property
+    def schedule(self) -> dict:
+        sc = Schedule()
+        _check(load().fastcod_plan_get_schedule(self._h, ctypes.byref(sc)))
+        return {"batch": sc.batch, "blocks_per_cu": sc.blocks_per_cu, "items_per_wave": sc.items_per_wave,
+                "tuned_ms": sc.tuned_ms}
+
+    def close(self) -> None:
+        if self._h is not None and self._h.value:
+            _check(load().fastcod_plan_destroy(self._h))
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def count_batched(subjects, stream=None) -> None:
+    """One-shot batched count (fastcod_count_batched): every subject's C is overwritten."""
+    lib = load()
+    arr = (Subject * len(subjects))(*[make_subject(d["points"], d["offsets"], d["roi"], d["lab"], d["N"], d["M"],
+                                                   d["C"], d.get("scale", 1.0)) for d in subjects])
+    with torch.cuda.device(subjects[0]["points"].device):
+        _check(lib.fastcod_count_batched(arr, len(subjects), _stream_ptr(stream)))

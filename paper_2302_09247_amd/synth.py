@@ -379,3 +379,38 @@ def random_small(seed: int, dims=(12, 10, 9), S: int = 40, N: Optional[int] = No
     return Workload(f"small{seed}", torch.from_numpy(P.astype(np.float32)), torch.from_numpy(off),
                     torch.from_numpy(roi.reshape(Z, Y, X)), torch.from_numpy(lab.reshape(Z, Y, X)),
                     int(N), int(M))
+
+
+# ----------------------------------------------------------------------------------------------
+# batched form: subjects of uneven grid size, N, M and streamline count
+# ----------------------------------------------------------------------------------------------
+
+def volumes_batch_subject(k: int, seed: int = 4) -> Volumes:
+    """Subject k of the batched workload (seeded from seed*1000 + k): grid dims drawn per axis between
+    the 64^3 and the 1.25 mm sizes; brain ellipsoid proportional to the grid; a bilateral ROI of the
+    1.25 mm shape scaled to a target N drawn in [5k, 45k] (at most 30% of the mask); M drawn from
+    {70, 180, 360} labels on a 3-voxel shell."""
+    rng = np.random.default_rng([seed * 1000 + k, 1])
+    dims = (int(rng.integers(64, 146)), int(rng.integers(64, 175)), int(rng.integers(64, 146)))
+    X, Y, Z = dims
+    centre = ((X - 1) / 2.0, (Y - 1) / 2.0, (Z - 1) / 2.0)
+    brain = (X * 56.0 / 145.0, Y * 68.0 / 174.0, Z * 52.0 / 145.0)
+    ratio = tuple(d / float(c) for d, c in zip(dims, CFG2_DIMS))
+    n_target = float(rng.uniform(5000, 45000))
+    mask_vol = 4.0 / 3.0 * math.pi * brain[0] * brain[1] * brain[2]
+    base_vol = 2 * 4.0 / 3.0 * math.pi * CFG2_ROI_SEMI[0] * CFG2_ROI_SEMI[1] * CFG2_ROI_SEMI[2]
+    f = min(n_target, 0.3 * mask_vol) / base_vol
+    semi = tuple(a * f ** (1.0 / 3.0) for a in CFG2_ROI_SEMI)
+    centres = [tuple(centre[i] + (rc[i] - CFG2_CENTRE[i]) * ratio[i] for i in range(3)) for rc in CFG2_ROI_CENTRES]
+    M = int(rng.choice([70, 180, 360]))
+    return volumes_subject(dims, centre, brain, semi, centres, M, 3.0, rng)
+
+
+def make_batch_subject(k: int, seed: int = 4, device="cpu", S: Optional[int] = None,
+                       vols: Optional[Volumes] = None) -> Workload:
+    """Streamlines of batched subject k: S drawn in [100k, 2M] (unless given), lengths as in the
+    1.25 mm recipe, walks stopping at the brain mask."""
+    vols = vols or volumes_batch_subject(k, seed)
+    if S is None:
+        S = int(np.random.default_rng([seed * 1000 + k, 2]).integers(100_000, 2_000_001))
+    return make_subject_walks(vols, seed * 1000 + k, S, 150.0, 20, 600, device, f"batch{k}")

@@ -77,3 +77,25 @@ def test_volume_create_rejects_bad_args(lib):
     assert lib.fastcod_volume_create(16, 16, d, 3, 2, None, None) == fastcod.EINVAL
     assert lib.fastcod_volume_count(None, 16, 16, 1, 16, None, None) == fastcod.EINVAL
     assert lib.fastcod_volume_destroy(None) == fastcod.OK
+
+
+def test_plan_create_rejects_bad_subjects(lib):
+    h = ctypes.c_void_p()
+    assert lib.fastcod_plan_create(None, 0, 0, None, None, ctypes.byref(h)) == fastcod.EINVAL
+    u = fastcod.Subject()
+    u.points, u.offsets, u.n_streamlines = 16, 16, 1
+    u.roi_index_vol, u.target_label_vol = 16, 16
+    u.dims[0], u.dims[1], u.dims[2] = 4, 4, 4
+    u.N, u.M, u.scale, u.C_out = 3, 2, 1.0, 16
+    arr = (fastcod.Subject * 2)(u, u)
+    arr[1].N = 0
+    assert lib.fastcod_plan_create(arr, 2, 0, None, None, ctypes.byref(h)) == fastcod.EINVAL
+    assert b"subject 1" in lib.fastcod_last_error()
+    arr[1].N = 3
+    arr[1].scale = -1.0
+    assert lib.fastcod_plan_create(arr, 2, 0, None, None, ctypes.byref(h)) == fastcod.EINVAL
+    arr[1].scale = 1.0
+    arr[1].dims[0], arr[1].dims[1], arr[1].dims[2] = 1 << 24, 1, 1    # too thin for the compact volume
+    assert lib.fastcod_plan_create(arr, 2, 0, None, None, ctypes.byref(h)) == fastcod.EINVAL
+    assert lib.fastcod_plan_destroy(None) == fastcod.OK
+    assert lib.fastcod_plan_launch(None, None) == fastcod.EINVAL
