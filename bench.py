@@ -92,6 +92,10 @@ def main():
                     help="plain: the 0.7 mm subject (default); batched: many subjects in one graph launch; "
                          "served: Poisson request stream")
     ap.add_argument("--subjects", type=int, default=32)
+    ap.add_argument("--served-subjects", type=int, default=8, help="resident subjects per request shape")
+    ap.add_argument("--served-requests", type=int, default=200, help="requests per Poisson rate")
+    ap.add_argument("--rates", default="0.1,0.25,0.5,0.75,0.9,1.0,1.2",
+                    help="Poisson rates as fractions of the measured saturation throughput")
     ap.add_argument("--tune-cache", default=None)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -116,8 +120,7 @@ def main():
     if args.form == "batched":
         return bench_batched(args)
     if args.form == "served":
-        import serve_bench
-        return serve_bench.main(args)
+        return bench_served(args)
     t0 = time.time()
     vols = synth.volumes_07mm()
     log(f"volumes: N={vols.N} M={vols.M} dims={vols.dims} ({time.time() - t0:.1f}s)")
@@ -250,9 +253,12 @@ def bench_batched(args):
         hip.hipEventRecord(b, stream.cuda_stream)
         plain_ms += ev.elapsed_ms(a, b) / args.steps
     identical = all(torch.equal(c, o) for c, o in zip(batched_C, outs))
+    pairs = sum(int(c.sum(dtype=torch.int64).item()) for c in batched_C)
+    sched = plan.schedule
     for v in vols:
         v.close()
     plan.close()
+    alg_bytes = 12 * P + 8 * (S + len(subs)) + 4 * pairs
     log(f"batched {batched_ms:.3f} ms per launch, plain sum {plain_ms:.3f} ms, identical={identical}")
     out = {
         "metric": "batched streamline points/s (all subjects, one graph launch) vs the plain per-subject path",
@@ -260,9 +266,132 @@ def bench_batched(args):
         "warmup": args.warmup, "ms_per_step": batched_ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{len(subs)} subjects, grids between 64^3 and 145x174x145, N 5k-45k, "
-                               f"M in {{70,180,360}}, S 100k-2M", "S": S, "P": P, "schedule": plan.schedule},
+                               f"M in {{70,180,360}}, S 100k-2M", "S": S, "P": P, "pairs": pairs,
+                   "schedule": sched},
+        "algorithmic_GBps": alg_bytes / (batched_ms * 1e-3) / 1e9,
         "plain_value": P / (plain_ms * 1e-3), "plain_ms": plain_ms,
         "batched_over_plain": plain_ms / batched_ms, "bit_identical": identical,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_served(args):
+    """Served form: a request server with resident volumes receives a Poisson stream of requests --
+    37.5% 64^3-grid subjects (10k streamlines), 37.5% 1.25 mm-grid subjects (1M streamlines), 25%
+    super-resolution jobs (1.25 mm streamlines scaled by fl32(1.25/0.7) onto the 0.7 mm volumes).
+    Streamlines of `served_subjects` subjects per shape are resident on the device; C goes to pinned
+    host memory.  Latency = time C is in host memory minus the scheduled arrival.  Every result is
+    compared with the same subject counted alone by the plain path."""
+    import threading
+    import numpy as np
+    import torch
+    from paper_2302_09247_amd import fastcod, synth
+    t0 = time.time()
+    ns = args.served_subjects
+    vA, vB, vC = synth.volumes_tiny64(), synth.volumes_125mm(2), synth.volumes_07mm(3)
+    subs = {"64^3": [synth.make_tiny64(seed=5000 + k, S=10_000, device="cuda") for k in range(ns)],
+            "1.25mm": [synth.make_125mm(seed=5100 + k, S=1_000_000, device="cuda", vols=vB) for k in range(ns)]}
+    torch.cuda.synchronize()
+    log(f"served workload generated in {time.time() - t0:.0f}s")
+    vols = {"64^3": (vA, 1.0), "1.25mm": (vB, 1.0), "sr": (vC, synth.SR_SCALE)}
+    srv = fastcod.Server(memory_budget=48 << 30)
+    vid = {k: srv.add_volume(v.roi, v.lab, v.N, v.M) for k, (v, _) in vols.items()}
+    # solo results (plain path) and pinned host offsets
+    solo, offs = {}, {}
+    dev_vol = {k: (torch.from_numpy(v.roi).cuda(), torch.from_numpy(v.lab).cuda()) for k, (v, _) in vols.items()}
+    for kind in ("64^3", "1.25mm", "sr"):
+        src = "1.25mm" if kind == "sr" else kind
+        v, scale = vols[kind]
+        for k in range(ns):
+            w = subs[src][k]
+            C = fastcod.count(w.points, w.offsets, dev_vol[kind][0], dev_vol[kind][1], v.N, v.M, scale=scale)
+            solo[(kind, k)] = C.cpu().numpy()
+            if (src, k) not in offs:
+                o = torch.empty(w.offsets.shape, dtype=torch.int64, pin_memory=True)
+                o.copy_(w.offsets)
+                offs[(src, k)] = o
+    del dev_vol
+    pts_per = {kind: float(np.mean([subs["1.25mm" if kind == "sr" else kind][k].P for k in range(ns)]))
+               for kind in vols}
+    pools = {kind: [] for kind in vols}
+
+    def run(rate, nreq, seed):
+        """nreq requests at Poisson `rate` (requests/s; None = all at once).  Returns per-request records."""
+        rng = np.random.default_rng(seed)
+        kinds = rng.choice(["64^3", "1.25mm", "sr"], size=nreq, p=[0.375, 0.375, 0.25])
+        subj = rng.integers(0, ns, size=nreq)
+        gaps = rng.exponential(1.0 / rate, size=nreq) if rate else np.zeros(nreq)
+        arrive = np.cumsum(gaps) - gaps[0]
+        need = {kind: int((kinds == kind).sum()) for kind in vols}
+        for kind, n in need.items():   # pinned result buffers, one per request of the run
+            v = vols[kind][0]
+            while len(pools[kind]) < n:
+                pools[kind].append(torch.empty((v.N, v.M), dtype=torch.int32, pin_memory=True))
+        used = {kind: 0 for kind in vols}
+        outs = []
+        for i in range(nreq):
+            outs.append(pools[kinds[i]][used[kinds[i]]])
+            used[kinds[i]] += 1
+        recs = [None] * nreq
+        rids = [None] * nreq
+        ready = threading.Semaphore(0)
+
+        def collect():
+            for i in range(nreq):
+                ready.acquire()
+                info = srv.wait(rids[i])
+                recs[i] = (info, bool(np.array_equal(outs[i].numpy(), solo[(kinds[i], int(subj[i]))])))
+
+        th = threading.Thread(target=collect)
+        th.start()
+        start = time.monotonic_ns() + 2_000_000
+        for i in range(nreq):
+            due = start + int(arrive[i] * 1e9)
+            while True:
+                now = time.monotonic_ns()
+                if now >= due:
+                    break
+                time.sleep(min(0.001, (due - now) / 1e9))
+            src = "1.25mm" if kinds[i] == "sr" else kinds[i]
+            w = subs[src][subj[i]]
+            rids[i] = srv.submit(vid[kinds[i]], w.points, offs[(src, int(subj[i]))], outs[i], scale=vols[kinds[i]][1])
+            ready.release()
+        th.join()
+        lat = np.array([(r[0]["t_done_ns"] - (start + int(a * 1e9))) / 1e6 for r, a in zip(recs, arrive)])
+        span = (max(r[0]["t_done_ns"] for r in recs) - start) / 1e9
+        ok = all(r[0]["status"] == 0 for r in recs)
+        exact = all(r[1] for r in recs)
+        pts = sum(pts_per[k] for k in kinds)
+        return {"lat": lat, "span_s": span, "ok": ok, "exact": exact, "points": pts}
+
+    run(None, 24, 99)   # warm-up: builds every volume
+    burst = run(None, args.served_requests, 1)
+    sat = args.served_requests / burst["span_s"]
+    log(f"saturation: {sat:.1f} requests/s ({burst['points'] / burst['span_s']:.3e} points/s), "
+        f"exact={burst['exact']} ok={burst['ok']}")
+    sweep = []
+    exact = burst["exact"] and burst["ok"]
+    for j, frac in enumerate(float(x) for x in args.rates.split(",")):
+        r = run(frac * sat, args.served_requests, 10 + j)
+        exact &= r["exact"] and r["ok"]
+        row = {"rate_frac": frac, "rate": frac * sat, "p50_ms": float(np.percentile(r["lat"], 50)),
+               "p99_ms": float(np.percentile(r["lat"], 99)),
+               "throughput": args.served_requests / r["span_s"], "exact": r["exact"] and r["ok"]}
+        sweep.append(row)
+        log(f"rate {frac:.2f}x = {row['rate']:.1f}/s: p50 {row['p50_ms']:.2f} ms p99 {row['p99_ms']:.2f} ms, "
+            f"{row['throughput']:.1f} req/s, exact={row['exact']}")
+    st = srv.stats()
+    srv.close()
+    out = {
+        "metric": "served requests/s at saturation (Poisson request stream, resident volumes, C to pinned host); "
+                  "p50/p99 latency per rate",
+        "value": sat, "unit": "requests/s", "n_gpus": 1, "steps": args.served_requests, "warmup": 24,
+        "ms_per_step": 1e3 / sat, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"37.5% 64^3 (S=10k), 37.5% 1.25 mm (S=1M), 25% SR 1.25->0.7 mm; "
+                               f"{ns} resident subjects per shape", "requests_per_rate": args.served_requests},
+        "points_per_s_at_saturation": burst["points"] / burst["span_s"],
+        "sweep": sweep, "bit_identical": exact, "server": st,
     }
     print(json.dumps(out), flush=True)
 

@@ -174,6 +174,100 @@ int fastcod_plan_destroy(fastcod_plan *plan);
 int fastcod_count_batched(const fastcod_subject *subjects, int32_t n, void *stream);
 
 /*
+ * Served form: a server that keeps volume pairs resident on one device and counts requests as
+ * they arrive, each request's C identical to fastcod_count_ex on the same inputs (C is a sum of
+ * exact per-streamline terms, Section 2, so cutting a request into streamline ranges and
+ * interleaving them with other requests changes nothing).
+ *
+ * The server takes one device allocation of memory_budget bytes at creation and places in it the
+ * compact volumes and every admitted request's device data: its offsets, its points unless they
+ * are already on the device, and its C unless C_out is on the device.  Requests are admitted
+ * first come, first served when their bytes (plus their volume's compact form and build scratch,
+ * if the volume is not resident) fit; idle volumes are evicted least recently used first to make
+ * room, and rebuilt from the server's host copy when needed again.  A request that could never
+ * fit is refused at submission with FASTCOD_ENOMEM.  Admitted requests are counted by one launch
+ * at a time that takes the next streamline range of every active request (about tick_points
+ * points in all), so a new request starts counting at the next launch.  Host points are uploaded
+ * in pieces of about chunk_points points that overlap the counting.  A scheduler thread owned by
+ * the server issues all device work on its own streams; the calls below only touch host state
+ * and may come from any thread.
+ */
+typedef struct fastcod_server fastcod_server;
+
+typedef struct fastcod_server_config {
+    uint64_t memory_budget;  /* device bytes for volumes and requests; 0 = 80% of the free memory     */
+    int64_t tick_points;     /* points per counting launch over all active requests; 0 = 2^25         */
+    int64_t chunk_points;    /* host upload piece and smallest per-request share of a launch; 0 = 2^20 */
+    int32_t max_active;      /* requests admitted at once, 1..1024; 0 = 64                             */
+    int32_t reserved;        /* must be 0                                                              */
+} fastcod_server_config;
+
+#define FASTCOD_REQ_DEVICE_POINTS 1u  /* request.points is a device pointer (else host)             */
+#define FASTCOD_REQ_DEVICE_C 2u       /* request.C_out is a device pointer (else host)              */
+
+typedef struct fastcod_request {
+    int32_t volume_id;         /* from fastcod_server_add_volume                                    */
+    uint32_t flags;            /* FASTCOD_REQ_*                                                     */
+    const float *points;       /* [P][3] float32, HOST unless FASTCOD_REQ_DEVICE_POINTS             */
+    const int64_t *offsets;    /* [S+1] int64, HOST; offsets[0] = 0, nondecreasing, P = offsets[S]  */
+    int64_t n_streamlines;     /* S, 0 <= S <= INT32_MAX                                            */
+    float scale;               /* coordinate scale, finite and > 0 (1.0f = none)                    */
+    int32_t *C_out;            /* [N][M] int32 of the volume, HOST unless FASTCOD_REQ_DEVICE_C;     */
+                               /* overwritten with the result when the request finishes             */
+} fastcod_request;
+
+typedef struct fastcod_request_info {
+    int32_t status;            /* FASTCOD_OK, FASTCOD_ECANCELED, or the error that failed the server */
+    int64_t t_submit_ns;       /* CLOCK_MONOTONIC times: submission, admission, result in C_out     */
+    int64_t t_admit_ns;
+    int64_t t_done_ns;
+    int64_t chunks;            /* counting launches that took part of the request                   */
+    int64_t device_bytes;      /* device bytes the request held while admitted (volume excluded)    */
+} fastcod_request_info;
+
+typedef struct fastcod_server_stats {
+    uint64_t budget_bytes;     /* arena size                                                        */
+    uint64_t used_bytes;       /* arena bytes in use (resident volumes + admitted requests)         */
+    int64_t pending, active;   /* requests waiting for admission / admitted and unfinished          */
+    int64_t completed;         /* requests finished (any status)                                    */
+    int64_t launches;          /* counting launches issued                                          */
+    int64_t volume_builds;     /* compact volume builds (first use and rebuilds after eviction)     */
+    int64_t evictions;         /* volumes evicted to make room                                      */
+    int32_t failed;            /* 0, or the error status that stopped the server                    */
+    int32_t reserved;
+} fastcod_server_stats;
+
+/* Creates a server on the current device (synchronous).  NULL cfg = defaults.
+ * Errors: EINVAL (bad config), ENOMEM (the budget cannot be allocated), EHIP. */
+int fastcod_server_create(const fastcod_server_config *cfg, fastcod_server **out);
+/* Registers a volume pair from HOST memory (int32 [Z][Y][X], copied by the server, so the caller's
+ * arrays may be freed on return).  The compact form is built on the device at the first request
+ * that needs it.  Errors: EINVAL (as fastcod_count_ex's volume arguments, or a grid too thin for
+ * the compact volume), ENOMEM (the volume alone exceeds the budget). */
+int fastcod_server_add_volume(fastcod_server *srv, const int32_t *roi_index_vol_host,
+                              const int32_t *target_label_vol_host, const int32_t dims[3], int32_t N,
+                              int32_t M, int32_t *volume_id);
+/* Queues a request.  Its points, offsets and C_out must stay valid and unchanged until it has
+ * finished (fastcod_server_wait returned its status).  The offsets are checked here: ERANGE if
+ * offsets[0] != 0 or they decrease.  Errors: EINVAL, ERANGE, ENOMEM (can never fit the budget),
+ * EBUSY (server shutting down), or the status that failed the server. */
+int fastcod_server_submit(fastcod_server *srv, const fastcod_request *req, uint64_t *request_id);
+/* Waits up to timeout_us microseconds (< 0: no limit) for a request to finish.  Returns its
+ * status (FASTCOD_OK: C_out holds the result) and fills *info (may be NULL); the request's record
+ * is then dropped, so each id is waited for once.  FASTCOD_ETIMEDOUT: still running (not an error
+ * of the request); FASTCOD_EINVAL: unknown id. */
+int fastcod_server_wait(fastcod_server *srv, uint64_t request_id, int64_t timeout_us,
+                        fastcod_request_info *info);
+/* Cancels a request.  A pending one finishes at once; an admitted one takes no further launches
+ * and finishes with FASTCOD_ECANCELED once its issued device work has drained (C_out is then
+ * unspecified; one whose result copy was already issued may still finish with FASTCOD_OK).
+ * FASTCOD_EINVAL if the id is unknown or already finished. */
+int fastcod_server_cancel(fastcod_server *srv, uint64_t request_id);
+int fastcod_server_get_stats(fastcod_server *srv, fastcod_server_stats *out);
+/* Cancels every unfinished request, waits for the device work to drain and frees the server. */
+int fastcod_server_destroy(fastcod_server *srv);
+
+/*
  * Input check (synchronous): offsets[0] == 0 and nondecreasing, ROI values < N and label
  * values < M wherever they are >= 0.  Returns FASTCOD_OK or FASTCOD_ERANGE (detail in
  * fastcod_last_error).

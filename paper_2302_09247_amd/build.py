@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = [os.path.join(CSRC, f) for f in ("kernels.hip", "api.hip")]
+SOURCES = [os.path.join(CSRC, f) for f in ("kernels.hip", "api.hip", "server.hip")]
 LIB = os.path.join(HERE, "libfastcod.so")
 ARCH = "gfx950"
 

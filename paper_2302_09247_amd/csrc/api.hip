@@ -13,74 +13,12 @@
 #include <utility>
 
 #include "fastcod.h"
+#include "host.h"
 #include "internal.h"
 
+using namespace fch;
+
 namespace {
-
-thread_local std::string g_last_error;
-
-int fail(int status, const std::string &msg) {
-    g_last_error = msg;
-    return status;
-}
-
-int hip_fail(hipError_t e, const char *what) {
-    return fail(FASTCOD_EHIP, std::string(what) + ": " + hipGetErrorString(e));
-}
-
-#define FC_HIP(call)                                          \
-    do {                                                      \
-        hipError_t e_ = (call);                               \
-        if (e_ != hipSuccess) return hip_fail(e_, #call);     \
-    } while (0)
-
-// smallest float >= n
-float float_bound(int32_t n) {
-    float f = (float)n;
-    if ((double)f < (double)n) f = nextafterf(f, INFINITY);
-    return f;
-}
-
-int bit_width(uint32_t v) {
-    int b = 0;
-    while (v) {
-        ++b;
-        v >>= 1;
-    }
-    return b;
-}
-
-// Device buffer that only grows.  Growth frees the old buffer (hipFree waits for the device).
-struct DevBuf {
-    void *p = nullptr;
-    size_t n = 0;
-    hipError_t ensure(size_t bytes, bool zero) {
-        if (bytes <= n && p) return hipSuccess;
-        if (p) {
-            hipError_t e = hipFree(p);
-            p = nullptr;
-            n = 0;
-            if (e != hipSuccess) return e;
-        }
-        size_t want = bytes < 256 ? 256 : bytes;
-        hipError_t e = hipMalloc(&p, want);
-        if (e != hipSuccess) {
-            p = nullptr;
-            return e;
-        }
-        n = want;
-        if (zero) {
-            e = hipMemset(p, 0, want);
-            if (e == hipSuccess) e = hipDeviceSynchronize();
-        }
-        return e;
-    }
-    void release() {
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        n = 0;
-    }
-};
 
 struct Workspace {
     std::mutex mu;      // held for the whole enqueue of one call
@@ -95,123 +33,12 @@ struct Workspace {
 std::mutex g_ws_mu;
 std::map<std::pair<int, hipStream_t>, Workspace *> g_ws;
 
-int current_device(int *dev) {
-    hipError_t e = hipGetDevice(dev);
-    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-    return FASTCOD_OK;
-}
 
 Workspace *workspace_for(int dev, hipStream_t st) {
     std::lock_guard<std::mutex> g(g_ws_mu);
     auto &w = g_ws[{dev, st}];
     if (!w) w = new Workspace();
     return w;
-}
-
-int cu_count(int dev) {
-    static std::mutex mu;
-    static std::map<int, int> cache;
-    std::lock_guard<std::mutex> g(mu);
-    auto it = cache.find(dev);
-    if (it != cache.end()) return it->second;
-    int n = 0;
-    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
-    cache[dev] = n;
-    return n;
-}
-
-// ---- compact volume layout ----
-constexpr int32_t kMaxCoarseWords = 8192;   // 32 KB of LDS per counting workgroup
-struct CompactLayout {
-    int32_t SBX, SBY, SBZ;
-    int64_t W;        // words
-    int64_t ntiles;
-    int64_t nvox;
-    bool packed;
-    int32_t rbits;
-    int32_t cs, CBX, CBY, CBZ, ncoarse_words;
-    size_t off_mb, off_tiles, off_coarse, off_codes, bytes;
-};
-
-bool compact_layout(const int32_t dims[3], int32_t N, int32_t M, CompactLayout &L,
-                    int32_t max_coarse_words = kMaxCoarseWords) {
-    L.SBX = (dims[0] + 15) / 16;
-    L.SBY = (dims[1] + 7) / 8;
-    L.SBZ = (dims[2] + 7) / 8;
-    L.W = (int64_t)L.SBX * L.SBY * L.SBZ * 32;
-    L.nvox = (int64_t)dims[0] * dims[1] * dims[2];
-    // word indices are uint32 and padding must stay modest (thin grids use raster lookups)
-    if (L.W >= (int64_t(1) << 31) || L.W * 32 > 8 * L.nvox + (int64_t(1) << 22)) return false;
-    if ((int64_t)L.SBX * L.SBY >= (int64_t(1) << 31)) return false;
-    L.ntiles = (L.W + fc::kScanTile - 1) / fc::kScanTile;
-    const int rb = bit_width((uint32_t)N), lb = bit_width((uint32_t)M);
-    L.packed = rb + lb <= 32;
-    L.rbits = rb;
-    // buffer-resource offsets are 32-bit: occupancy pairs and codes must stay below 4 GB
-    if (8 * L.W >= (int64_t(1) << 32) || (L.packed ? 4 : 8) * L.nvox >= (int64_t(1) << 32)) return false;
-    // coarse occupancy (kept in LDS by the counting kernel): smallest block side 8, 16 or 32 whose
-    // bit map fits kMaxCoarseWords
-    for (L.cs = 3; L.cs <= 5; ++L.cs) {
-        const int32_t c = 1 << L.cs;
-        L.CBX = (dims[0] + c - 1) / c;
-        L.CBY = (dims[1] + c - 1) / c;
-        L.CBZ = (dims[2] + c - 1) / c;
-        const int64_t ncb = (int64_t)L.CBX * L.CBY * L.CBZ;
-        L.ncoarse_words = (int32_t)(2 * ((ncb + 63) / 64));
-        if (L.ncoarse_words <= max_coarse_words) break;
-    }
-    if (L.cs > 5) return false;
-    auto align = [](size_t v) { return (v + 255) & ~size_t(255); };
-    L.off_mb = 0;
-    L.off_tiles = align(L.off_mb + 8 * (size_t)L.W);
-    L.off_coarse = align(L.off_tiles + 4 * (size_t)L.ntiles);
-    L.off_codes = align(L.off_coarse + 4 * (size_t)L.ncoarse_words);
-    L.bytes = L.off_codes + (L.packed ? 4 : 8) * (size_t)L.nvox;   // at most every voxel occupied
-    return true;
-}
-
-fc::CompactVol compact_view(void *buf, const CompactLayout &L, int32_t N, int32_t M) {
-    char *b = static_cast<char *>(buf);
-    fc::CompactVol cv;
-    cv.mb = reinterpret_cast<const uint2 *>(b + L.off_mb);
-    cv.coarse = reinterpret_cast<const uint32_t *>(b + L.off_coarse);
-    cv.cs = L.cs;
-    cv.CBX = L.CBX;
-    cv.CBXY = L.CBX * L.CBY;
-    cv.ncoarse_words = L.ncoarse_words;
-    cv.codes32 = reinterpret_cast<const uint32_t *>(b + L.off_codes);
-    cv.codes64 = reinterpret_cast<const int2 *>(b + L.off_codes);
-    cv.SBX = L.SBX;
-    cv.SBXY = L.SBX * L.SBY;
-    cv.rbits = L.rbits;
-    cv.rmask = L.rbits >= 32 ? 0xFFFFFFFFu : ((1u << L.rbits) - 1u);
-    cv.N = N;
-    cv.M = M;
-    cv.packed = L.packed ? 1 : 0;
-    cv.W = L.W;
-    cv.ncodes = L.nvox;
-    return cv;
-}
-
-fc::Grid make_grid(const int32_t dims[3]) {
-    fc::Grid g;
-    g.X = dims[0];
-    g.Y = dims[1];
-    g.Z = dims[2];
-    g.Xf = float_bound(dims[0]);
-    g.Yf = float_bound(dims[1]);
-    g.Zf = float_bound(dims[2]);
-    return g;
-}
-
-int check_volume_args(const int32_t *roi, const int32_t *lab, const int32_t dims[3], int32_t N, int32_t M) {
-    if (!dims) return fail(FASTCOD_EINVAL, "dims is NULL");
-    if (dims[0] < 1 || dims[1] < 1 || dims[2] < 1) return fail(FASTCOD_EINVAL, "dims must be >= 1");
-    if ((int64_t)dims[0] * dims[1] * dims[2] >= (int64_t(1) << 31)) return fail(FASTCOD_EINVAL, "X*Y*Z must be < 2^31");
-    if (N < 1 || M < 1) return fail(FASTCOD_EINVAL, "N and M must be >= 1");
-    if ((int64_t)N * M >= (int64_t(1) << 31)) return fail(FASTCOD_EINVAL, "N*M must be < 2^31");
-    if (!roi || !lab) return fail(FASTCOD_EINVAL, "volume pointer is NULL");
-    return FASTCOD_OK;
 }
 
 int check_stream_args(const float *points, const int64_t *offsets, int64_t S, int32_t *C, const fastcod_opts &o) {
@@ -330,7 +157,6 @@ int enqueue_count(Workspace &ws, int dev, const float *points, const int64_t *of
 }
 
 // ---- batched plans ----
-constexpr int32_t kBatchedCoarseWords = 512;   // per-wavefront LDS coarse map of the batched kernel (2 KB)
 
 struct PlanSched {
     int batch = 4, blocks_per_cu = 0, items_per_wave = 4;
@@ -478,11 +304,11 @@ int plan_check(const fastcod_subject *subjects, int32_t n) {
     for (int32_t k = 0; k < n; ++k) {
         const fastcod_subject &u = subjects[k];
         int rc = check_volume_args(u.roi_index_vol, u.target_label_vol, u.dims, u.N, u.M);
-        if (rc) return fail(rc, "subject " + std::to_string(k) + ": " + g_last_error);
+        if (rc) return fail(rc, "subject " + std::to_string(k) + ": " + last_error());
         fastcod_opts o = fastcod_default_opts();
         o.scale = u.scale;
         rc = check_stream_args(u.points, u.offsets, u.n_streamlines, u.C_out, o);
-        if (rc) return fail(rc, "subject " + std::to_string(k) + ": " + g_last_error);
+        if (rc) return fail(rc, "subject " + std::to_string(k) + ": " + last_error());
         CompactLayout L;
         if (!compact_layout(u.dims, u.N, u.M, L, kBatchedCoarseWords))
             return fail(FASTCOD_EINVAL, "subject " + std::to_string(k) + ": grid too thin for the compact volume");
@@ -511,11 +337,11 @@ int plan_build(const fastcod_subject *subjects, int32_t n, uint32_t flags, const
     for (int32_t k = 0; k < n; ++k) {
         const fastcod_subject &u = subjects[k];
         rc = check_volume_args(u.roi_index_vol, u.target_label_vol, u.dims, u.N, u.M);
-        if (rc) return fail(rc, "subject " + std::to_string(k) + ": " + g_last_error);
+        if (rc) return fail(rc, "subject " + std::to_string(k) + ": " + last_error());
         fastcod_opts o = fastcod_default_opts();
         o.scale = u.scale;
         rc = check_stream_args(u.points, u.offsets, u.n_streamlines, u.C_out, o);
-        if (rc) return fail(rc, "subject " + std::to_string(k) + ": " + g_last_error);
+        if (rc) return fail(rc, "subject " + std::to_string(k) + ": " + last_error());
         CompactLayout L;
         if (!compact_layout(u.dims, u.N, u.M, L, kBatchedCoarseWords))
             return fail(FASTCOD_EINVAL, "subject " + std::to_string(k) + ": grid too thin for the compact volume");
@@ -528,11 +354,7 @@ int plan_build(const fastcod_subject *subjects, int32_t n, uint32_t flags, const
             if (e != hipSuccess) return fail(FASTCOD_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
             pl->volumes.push_back(buf);
             cv = compact_view(buf, L, u.N, u.M);
-            char *b = static_cast<char *>(buf);
-            FC_HIP(fc::launch_compact_build(u.roi_index_vol, u.target_label_vol, make_grid(u.dims), u.N, u.M, cv,
-                                            reinterpret_cast<uint32_t *>(b + L.off_mb), b + L.off_codes,
-                                            reinterpret_cast<uint32_t *>(b + L.off_tiles),
-                                            reinterpret_cast<uint32_t *>(b + L.off_coarse), L.W, cus, st));
+            FC_HIP(enqueue_compact_build(u.roi_index_vol, u.target_label_vol, u.dims, u.N, u.M, L, buf, cus, st));
             built[key] = cv;
         } else {
             cv = it->second;
@@ -541,6 +363,7 @@ int plan_build(const fastcod_subject *subjects, int32_t n, uint32_t flags, const
         ss.pts = u.points;
         ss.offsets = u.offsets;
         ss.S = u.n_streamlines;
+        ss.s_begin = 0;
         ss.g = make_grid(u.dims);
         ss.scale = u.scale;
         ss.cv = cv;
@@ -675,11 +498,11 @@ const char *fastcod_strerror(int status) {
     }
 }
 
-const char *fastcod_last_error(void) { return g_last_error.c_str(); }
+const char *fastcod_last_error(void) { return last_error().c_str(); }
 
 int fastcod_count_ex(const float *points, const int64_t *offsets, int64_t S, const int32_t *roi, const int32_t *lab,
                      const int32_t dims[3], int32_t N, int32_t M, int32_t *C, const fastcod_opts *opts, void *stream) {
-    g_last_error.clear();
+    last_error().clear();
     const fastcod_opts o = opts ? *opts : fastcod_default_opts();
     int rc = check_volume_args(roi, lab, dims, N, M);
     if (rc) return rc;
@@ -706,10 +529,7 @@ int fastcod_count_ex(const float *points, const int64_t *offsets, int64_t S, con
     }
     FC_HIP(ws.compact.ensure(L.bytes, false));
     fc::CompactVol cv = compact_view(ws.compact.p, L, N, M);
-    char *b = static_cast<char *>(ws.compact.p);
-    FC_HIP(fc::launch_compact_build(roi, lab, g, N, M, cv, reinterpret_cast<uint32_t *>(b + L.off_mb), b + L.off_codes,
-                                    reinterpret_cast<uint32_t *>(b + L.off_tiles),
-                                    reinterpret_cast<uint32_t *>(b + L.off_coarse), L.W, cu_count(dev), st));
+    FC_HIP(enqueue_compact_build(roi, lab, dims, N, M, L, ws.compact.p, cu_count(dev), st));
     return enqueue_count(ws, dev, points, offsets, S, g, N, M, nullptr, &cv, C, o, st);
 }
 
@@ -720,7 +540,7 @@ int fastcod_count(const float *points, const int64_t *offsets, int64_t S, const 
 
 int fastcod_volume_create(const int32_t *roi, const int32_t *lab, const int32_t dims[3], int32_t N, int32_t M,
                           void *stream, fastcod_volume **out) {
-    g_last_error.clear();
+    last_error().clear();
     if (!out) return fail(FASTCOD_EINVAL, "out is NULL");
     *out = nullptr;
     int rc = check_volume_args(roi, lab, dims, N, M);
@@ -742,15 +562,10 @@ int fastcod_volume_create(const int32_t *roi, const int32_t *lab, const int32_t 
     v->L = L;
     v->buf = buf;
     v->ready = nullptr;
-    const fc::Grid g = make_grid(dims);
-    fc::CompactVol cv = compact_view(buf, L, N, M);
-    char *b = static_cast<char *>(buf);
     {
         Workspace &ws = *workspace_for(dev, st);
         std::lock_guard<std::mutex> lock(ws.mu);
-        e = fc::launch_compact_build(roi, lab, g, N, M, cv, reinterpret_cast<uint32_t *>(b + L.off_mb), b + L.off_codes,
-                                     reinterpret_cast<uint32_t *>(b + L.off_tiles),
-                                     reinterpret_cast<uint32_t *>(b + L.off_coarse), L.W, cu_count(dev), st);
+        e = enqueue_compact_build(roi, lab, dims, N, M, L, buf, cu_count(dev), st);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&v->ready, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventRecord(v->ready, st);
     }
@@ -768,7 +583,7 @@ size_t fastcod_volume_bytes(const fastcod_volume *vol) { return vol ? vol->L.byt
 
 int fastcod_volume_count(const fastcod_volume *vol, const float *points, const int64_t *offsets, int64_t S,
                          int32_t *C, const fastcod_opts *opts, void *stream) {
-    g_last_error.clear();
+    last_error().clear();
     if (!vol) return fail(FASTCOD_EINVAL, "vol is NULL");
     const fastcod_opts o = opts ? *opts : fastcod_default_opts();
     int rc = check_stream_args(points, offsets, S, C, o);
@@ -789,7 +604,7 @@ int fastcod_volume_count(const fastcod_volume *vol, const float *points, const i
 }
 
 int fastcod_volume_destroy(fastcod_volume *vol) {
-    g_last_error.clear();
+    last_error().clear();
     if (!vol) return FASTCOD_OK;
     int prev = 0;
     (void)hipGetDevice(&prev);
@@ -805,7 +620,7 @@ int fastcod_volume_destroy(fastcod_volume *vol) {
 
 int fastcod_validate(const int64_t *offsets, int64_t S, const int32_t *roi, const int32_t *lab, const int32_t dims[3],
                      int32_t N, int32_t M, void *stream) {
-    g_last_error.clear();
+    last_error().clear();
     int rc = check_volume_args(roi, lab, dims, N, M);
     if (rc) return rc;
     if (S < 0 || S > INT32_MAX || !offsets) return fail(FASTCOD_EINVAL, "bad offsets / n_streamlines");
@@ -819,7 +634,7 @@ int fastcod_validate(const int64_t *offsets, int64_t S, const int32_t *roi, cons
 }
 
 int fastcod_release(void) {
-    g_last_error.clear();
+    last_error().clear();
     std::lock_guard<std::mutex> g(g_ws_mu);
     int prev = 0;
     (void)hipGetDevice(&prev);
@@ -842,7 +657,7 @@ int fastcod_release(void) {
 
 int fastcod_plan_create(const fastcod_subject *subjects, int32_t n, uint32_t flags, const char *tune_cache,
                         void *stream, fastcod_plan **out) {
-    g_last_error.clear();
+    last_error().clear();
     if (!out) return fail(FASTCOD_EINVAL, "out is NULL");
     *out = nullptr;
     if (n < 1 || !subjects) return fail(FASTCOD_EINVAL, "need at least one subject");
@@ -851,7 +666,7 @@ int fastcod_plan_create(const fastcod_subject *subjects, int32_t n, uint32_t fla
     fastcod_plan *pl = new fastcod_plan();
     const int rc = plan_build(subjects, n, flags, tune_cache, static_cast<hipStream_t>(stream), pl);
     if (rc) {
-        const std::string msg = g_last_error;
+        const std::string msg = last_error();
         (void)hipDeviceSynchronize();
         plan_free(pl);
         return fail(rc, msg);
@@ -861,7 +676,7 @@ int fastcod_plan_create(const fastcod_subject *subjects, int32_t n, uint32_t fla
 }
 
 int fastcod_plan_launch(fastcod_plan *plan, void *stream) {
-    g_last_error.clear();
+    last_error().clear();
     if (!plan || !plan->exec) return fail(FASTCOD_EINVAL, "plan is NULL");
     int dev;
     const int rc = current_device(&dev);
@@ -872,7 +687,7 @@ int fastcod_plan_launch(fastcod_plan *plan, void *stream) {
 }
 
 int fastcod_plan_get_schedule(const fastcod_plan *plan, fastcod_schedule *out) {
-    g_last_error.clear();
+    last_error().clear();
     if (!plan || !out) return fail(FASTCOD_EINVAL, "NULL argument");
     out->batch = plan->sched.batch;
     out->blocks_per_cu = plan->blocks / std::max(1, cu_count(plan->device));
@@ -882,7 +697,7 @@ int fastcod_plan_get_schedule(const fastcod_plan *plan, fastcod_schedule *out) {
 }
 
 int fastcod_plan_destroy(fastcod_plan *plan) {
-    g_last_error.clear();
+    last_error().clear();
     if (!plan) return FASTCOD_OK;
     int prev = 0;
     (void)hipGetDevice(&prev);
@@ -903,7 +718,7 @@ int fastcod_count_batched(const fastcod_subject *subjects, int32_t n, void *stre
         const hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
         if (e != hipSuccess) rc = hip_fail(e, "hipStreamSynchronize");
     }
-    const std::string msg = g_last_error;
+    const std::string msg = last_error();
     fastcod_plan_destroy(pl);
     if (rc) return fail(rc, msg);
     return FASTCOD_OK;

@@ -78,10 +78,13 @@ struct CountArgs {
 
 // Everything the flat-stream kernels need about one subject (also a device-side descriptor of the
 // batched form).
+// One subject of the batched kernels: streamlines [s_begin, S) of (pts, offsets) are counted into C.
+// s_begin > 0 lets a caller count one streamline range of a larger set (offsets stay absolute).
 struct StreamSubject {
     const float *pts;
     const int64_t *offsets;
     int64_t S;
+    int64_t s_begin;
     Grid g;
     float scale;
     CompactVol cv;

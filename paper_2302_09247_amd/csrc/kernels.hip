@@ -996,6 +996,7 @@ static StreamSubject stream_subject(const CountArgs &a, const CompactVol &cv) {
     s.pts = a.pts;
     s.offsets = a.offsets;
     s.S = a.S;
+    s.s_begin = 0;
     s.g = a.g;
     s.scale = a.scale;
     s.cv = cv;
@@ -1129,8 +1130,9 @@ __global__ void __launch_bounds__(kBlock) k_fallback_batched(const StreamSubject
 // batched form: work items, zero fill of every C, launchers
 // ---------------------------------------------------------------------------------------------
 
-// items[i] = (subject, first streamline at or after point floor(j * P_s / n_s)) for the j-th of the
-// subject's n_s items; item_base[s] .. item_base[s+1] are subject s's items.
+// items[i] = (subject, first streamline of [s_begin, S) at or after point P0 + floor(j * (P - P0) / n_s))
+// for the j-th of the subject's n_s items (P0 = offsets[s_begin], P = offsets[S]); item_base[s] ..
+// item_base[s+1] are subject s's items.
 __global__ void k_partition_batched(const StreamSubject *__restrict__ subs, const int64_t *__restrict__ item_base,
                                     int32_t nsub, int2 *__restrict__ items) {
     const int64_t n = item_base[nsub];
@@ -1144,10 +1146,12 @@ __global__ void k_partition_batched(const StreamSubject *__restrict__ subs, cons
         }
         const StreamSubject &sub = subs[lo];
         const int64_t j = i - item_base[lo], ns = item_base[lo + 1] - item_base[lo];
+        const int64_t sb = clamp64(sub.s_begin, 0, sub.S);
+        const int64_t P0 = sub.offsets[sb];
         int64_t P = sub.offsets[sub.S];
-        if (P < 0) P = 0;
-        const int64_t target = (int64_t)(((__int128)j * P) / ns);
-        int64_t a = 0, b = sub.S;
+        if (P < P0) P = P0;
+        const int64_t target = P0 + (int64_t)(((__int128)j * (P - P0)) / ns);
+        int64_t a = sb, b = sub.S;
         while (a < b) {
             const int64_t mid = (a + b) >> 1;
             if (sub.offsets[mid] < target) a = mid + 1;

@@ -1,0 +1,421 @@
+// Request server: the HIP executor of the scheduling core (server_core.h) and the
+// fastcod_server_* entry points declared in include/fastcod.h.
+//
+// Device work runs on three streams owned by the server, all at the default priority:
+//   compute  volume builds, request set-up (zero C, offsets upload), counting launches;
+//   copy     uploads of host points (pieces of about chunk_points points);
+//   out      result copies of C to host memory, each after an event of the compute stream.
+// A counting launch ("tick") is the batched kernel over a descriptor table with one entry per
+// active request: streamlines [s0, s1) of that request, its device arrays, volume, scale and C.
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <algorithm>
+#include <memory>
+#include <thread>
+#include <vector>
+
+#include "fastcod.h"
+#include "host.h"
+#include "internal.h"
+#include "server_core.h"
+
+using namespace fch;
+
+namespace {
+
+constexpr int kTickSlots = 4;            // descriptor tables in rotation (> ticks in flight)
+constexpr int kItemsPerWave = 4;         // work items per wavefront of a full launch
+constexpr int64_t kMinItemPoints = 256;  // smaller launches get fewer, larger items
+
+class HipExecutor final : public fcs::Executor {
+  public:
+    ~HipExecutor() override { teardown(); }
+
+    int init(int dev, const fcs::Config &cfg) {
+        dev_ = dev;
+        cfg_ = cfg;
+        cus_ = cu_count(dev);
+        blocks_ = cus_ * fc::count_batched_blocks_per_cu(4, kBatchedCoarseWords);
+        items_full_ = (int64_t)blocks_ * fc::kWavesPerBlock * kItemsPerWave;
+        hipError_t e = hipMalloc(&base_, cfg.budget);
+        if (e != hipSuccess) {
+            base_ = nullptr;
+            return fail(FASTCOD_ENOMEM, std::string("server budget allocation: ") + hipGetErrorString(e));
+        }
+        FC_HIP(hipStreamCreateWithFlags(&comp_, hipStreamNonBlocking));
+        FC_HIP(hipStreamCreateWithFlags(&copy_, hipStreamNonBlocking));
+        FC_HIP(hipStreamCreateWithFlags(&out_, hipStreamNonBlocking));
+        const int64_t nsub = cfg.max_active;
+        for (Slot &s : slots_) {
+            FC_HIP(hipHostMalloc(reinterpret_cast<void **>(&s.h_subs), sizeof(fc::StreamSubject) * nsub,
+                                 hipHostMallocDefault));
+            FC_HIP(hipHostMalloc(reinterpret_cast<void **>(&s.h_base), 8 * (nsub + 1), hipHostMallocDefault));
+            FC_HIP(s.d_subs.ensure(sizeof(fc::StreamSubject) * nsub, false));
+            FC_HIP(s.d_base.ensure(8 * (nsub + 1), false));
+            FC_HIP(s.d_items.ensure(8 * (size_t)(items_full_ + nsub + 1), false));
+            FC_HIP(hipEventCreateWithFlags(&s.last, hipEventDisableTiming));
+            FC_HIP(hipEventRecord(s.last, comp_));
+        }
+        FC_HIP(d_ovf_.ensure(256 + 8 * (size_t)cfg.tick_streamlines, false));
+        ovf_.count = static_cast<unsigned long long *>(d_ovf_.p);
+        ovf_.work = ovf_.count + 1;
+        ovf_.list = reinterpret_cast<int64_t *>(static_cast<char *>(d_ovf_.p) + 256);
+        ovf_.cap = cfg.tick_streamlines;
+        return FASTCOD_OK;
+    }
+
+    std::string detail() const override { return err_; }
+
+    int volume_bytes(const fcs::Volume &v, uint64_t *bytes, uint64_t *tmp_bytes) override {
+        CompactLayout L;
+        if (!compact_layout(v.dims, v.N, v.M, L, kBatchedCoarseWords))
+            return err(FASTCOD_EINVAL, "grid too thin for the compact volume");
+        // codes only for the occupied voxels, counted on the host copy with the build's own test
+        int64_t occ = 0;
+        for (int64_t i = 0; i < L.nvox; ++i)
+            occ += (int)((uint32_t)v.roi[i] < (uint32_t)v.N) | (int)((uint32_t)v.lab[i] < (uint32_t)v.M);
+        compact_layout_fit(L, occ);
+        layouts_[v.id] = L;
+        *bytes = L.bytes;
+        *tmp_bytes = 2 * fcs::Arena::round(4 * (uint64_t)L.nvox);
+        return FASTCOD_OK;
+    }
+
+    int build_volume(const fcs::Volume &v, fcs::Token *t) override {
+        const CompactLayout &L = layouts_.at(v.id);
+        char *roi = base_ + v.tmp_off;
+        char *lab = roi + fcs::Arena::round(4 * (uint64_t)L.nvox);
+        if (hip(hipMemcpyAsync(roi, v.roi.data(), 4 * (size_t)L.nvox, hipMemcpyHostToDevice, comp_), "volume upload") ||
+            hip(hipMemcpyAsync(lab, v.lab.data(), 4 * (size_t)L.nvox, hipMemcpyHostToDevice, comp_), "volume upload") ||
+            hip(enqueue_compact_build(reinterpret_cast<const int32_t *>(roi), reinterpret_cast<const int32_t *>(lab),
+                                      v.dims, v.N, v.M, L, base_ + v.off, cus_, comp_),
+                "compact build"))
+            return FASTCOD_EHIP;
+        return record(comp_, t);
+    }
+
+    int begin_request(const fcs::Request &r, fcs::Token *t) override {
+        if (hip(fc::launch_fill_i32(device_C(r), (int64_t)r.N * r.M, 0, cus_, comp_), "zero fill") ||
+            hip(hipMemcpyAsync(base_ + r.off_offsets, r.offsets, 8 * (size_t)(r.S + 1), hipMemcpyHostToDevice, comp_),
+                "offsets upload"))
+            return FASTCOD_EHIP;
+        return record(comp_, t);
+    }
+
+    int upload(const fcs::Request &r, int64_t s0, int64_t s1, fcs::Token *t) override {
+        const int64_t p0 = r.offsets[s0], p1 = r.offsets[s1];
+        if (p1 > p0 && hip(hipMemcpyAsync(base_ + r.off_points + 12 * p0, r.points + 3 * p0, 12 * (size_t)(p1 - p0),
+                                          hipMemcpyHostToDevice, copy_),
+                           "points upload"))
+            return FASTCOD_EHIP;
+        return record(copy_, t);
+    }
+
+    int launch_tick(const std::vector<fcs::Chunk> &chunks, fcs::Token *t) override {
+        const int32_t n = (int32_t)chunks.size();
+        if (n < 1 || n > cfg_.max_active) return err(FASTCOD_EINVAL, "launch of an unexpected size");
+        Slot &s = slots_[next_slot_++ % kTickSlots];
+        if (hip(hipEventSynchronize(s.last), "descriptor slot")) return FASTCOD_EHIP;
+        // fallback scratch for the largest volume of this launch
+        int32_t maxN = 1, maxM = 1;
+        for (const fcs::Chunk &c : chunks) {
+            maxN = std::max(maxN, c.vol->N);
+            maxM = std::max(maxM, c.vol->M);
+        }
+        if (int rc = ensure_fallback(maxN, maxM)) return rc;
+        int64_t total = 0;
+        for (const fcs::Chunk &c : chunks) total += c.req->offsets[c.s1] - c.req->offsets[c.s0];
+        const int64_t want = std::max<int64_t>(1, std::min<int64_t>(items_full_, total / kMinItemPoints));
+        s.h_base[0] = 0;
+        for (int32_t k = 0; k < n; ++k) {
+            const fcs::Chunk &c = chunks[k];
+            const fcs::Request &r = *c.req;
+            const fcs::Volume &v = *c.vol;
+            fc::StreamSubject &ss = s.h_subs[k];
+            ss.pts = (r.flags & FASTCOD_REQ_DEVICE_POINTS) ? r.points
+                                                           : reinterpret_cast<const float *>(base_ + r.off_points);
+            ss.offsets = reinterpret_cast<const int64_t *>(base_ + r.off_offsets);
+            ss.S = c.s1;
+            ss.s_begin = c.s0;
+            ss.g = make_grid(v.dims);
+            ss.scale = r.scale;
+            ss.cv = compact_view(base_ + v.off, layouts_.at(v.id), v.N, v.M);
+            ss.C = device_C(r);
+            ss.si = (uint32_t)v.M;
+            ss.sm = 1u;
+            const int64_t pts = r.offsets[c.s1] - r.offsets[c.s0];
+            int64_t ni = total > 0 ? (int64_t)((double)want * (double)pts / (double)total + 0.5) : 1;
+            ni = std::max<int64_t>(1, std::min<int64_t>(ni, c.s1 - c.s0));
+            s.h_base[k + 1] = s.h_base[k] + ni;
+        }
+        const int64_t nitems = s.h_base[n];
+        if (nitems + 1 > (int64_t)(s.d_items.n / 8)) return err(FASTCOD_EINVAL, "work item table overflow");
+        const auto *subs = static_cast<const fc::StreamSubject *>(s.d_subs.p);
+        if (hip(hipMemcpyAsync(s.d_subs.p, s.h_subs, sizeof(fc::StreamSubject) * n, hipMemcpyHostToDevice, comp_),
+                "descriptor upload") ||
+            hip(hipMemcpyAsync(s.d_base.p, s.h_base, 8 * (size_t)(n + 1), hipMemcpyHostToDevice, comp_),
+                "descriptor upload") ||
+            hip(fc::launch_fill_u64(ovf_.count, 2, cus_, comp_), "counter reset") ||
+            hip(fc::launch_partition_batched(subs, static_cast<const int64_t *>(s.d_base.p), n, nitems,
+                                             static_cast<int2 *>(s.d_items.p), cus_, comp_),
+                "partition") ||
+            hip(fc::launch_count_batched(subs, static_cast<const int2 *>(s.d_items.p), nitems, ovf_,
+                                         kBatchedCoarseWords, blocks_, 4, comp_),
+                "count") ||
+            hip(fc::launch_fallback_batched(subs, n, ovf_, fs_, comp_), "fallback") ||
+            hip(hipEventRecord(s.last, comp_), "hipEventRecord"))
+            return FASTCOD_EHIP;
+        return record(comp_, t);
+    }
+
+    int finalize(const fcs::Request &r, fcs::Token *t) override {
+        if (r.flags & FASTCOD_REQ_DEVICE_C) return record(comp_, t);
+        TokenRec *rec = nullptr;
+        if (int rc = take(&rec, t)) return rc;
+        if (hip(hipEventRecord(rec->link, comp_), "hipEventRecord") ||
+            hip(hipStreamWaitEvent(out_, rec->link, 0), "hipStreamWaitEvent") ||
+            hip(hipMemcpyAsync(r.C_out, base_ + r.off_C, 4 * (size_t)r.N * r.M, hipMemcpyDeviceToHost, out_),
+                "result copy") ||
+            hip(hipEventRecord(rec->ev, out_), "hipEventRecord"))
+            return FASTCOD_EHIP;
+        return FASTCOD_OK;
+    }
+
+    int query(fcs::Token t) override {
+        if (t == 0 || t > toks_.size()) return err(FASTCOD_EINVAL, "unknown token");
+        const hipError_t e = hipEventQuery(toks_[t - 1].ev);
+        if (e == hipSuccess) return 1;
+        if (e == hipErrorNotReady) return 0;
+        return err(FASTCOD_EHIP, std::string("hipEventQuery: ") + hipGetErrorString(e));
+    }
+
+    void release(fcs::Token t) override {
+        if (t >= 1 && t <= toks_.size()) free_toks_.push_back(t);
+    }
+
+    void pause() override { std::this_thread::sleep_for(std::chrono::microseconds(10)); }
+
+  private:
+    struct TokenRec {
+        hipEvent_t ev = nullptr, link = nullptr;
+    };
+    struct Slot {
+        fc::StreamSubject *h_subs = nullptr;
+        int64_t *h_base = nullptr;
+        DevBuf d_subs, d_base, d_items;
+        hipEvent_t last = nullptr;
+    };
+
+    int err(int rc, const std::string &m) {
+        err_ = m;
+        return rc;
+    }
+    // true on failure
+    bool hip(hipError_t e, const char *what) {
+        if (e == hipSuccess) return false;
+        err_ = std::string(what) + ": " + hipGetErrorString(e);
+        return true;
+    }
+
+    int32_t *device_C(const fcs::Request &r) const {
+        return (r.flags & FASTCOD_REQ_DEVICE_C) ? r.C_out : reinterpret_cast<int32_t *>(base_ + r.off_C);
+    }
+
+    int take(TokenRec **rec, fcs::Token *t) {
+        if (free_toks_.empty()) {
+            TokenRec tr;
+            if (hip(hipEventCreateWithFlags(&tr.ev, hipEventDisableTiming), "hipEventCreate") ||
+                hip(hipEventCreateWithFlags(&tr.link, hipEventDisableTiming), "hipEventCreate"))
+                return FASTCOD_EHIP;
+            toks_.push_back(tr);
+            free_toks_.push_back(toks_.size());
+        }
+        *t = free_toks_.back();
+        free_toks_.pop_back();
+        *rec = &toks_[*t - 1];
+        return FASTCOD_OK;
+    }
+
+    int record(hipStream_t st, fcs::Token *t) {
+        TokenRec *rec = nullptr;
+        if (int rc = take(&rec, t)) return rc;
+        if (hip(hipEventRecord(rec->ev, st), "hipEventRecord")) return FASTCOD_EHIP;
+        return FASTCOD_OK;
+    }
+
+    int ensure_fallback(int32_t N, int32_t M) {
+        if (N <= fbN_ && M <= fbM_) return FASTCOD_OK;
+        fbN_ = std::max(fbN_, N);
+        fbM_ = std::max(fbM_, M);
+        fs_.nwordsN = (fbN_ + 31) / 32;
+        fs_.nwordsM = (fbM_ + 31) / 32;
+        fs_.stride = ((int64_t)fs_.nwordsN + fs_.nwordsM + fbM_ + 63) & ~int64_t(63);
+        int64_t blocks = (int64_t(64) << 20) / (4 * fs_.stride);   // <= 64 MiB of scratch
+        fs_.blocks = (int32_t)std::max<int64_t>(1, std::min<int64_t>(64, blocks));
+        // earlier launches may still read the old scratch: the growth waits for the device
+        if (hip(hipDeviceSynchronize(), "hipDeviceSynchronize") ||
+            hip(d_fb_.ensure((size_t)(4 * fs_.stride * fs_.blocks), true), "fallback scratch"))
+            return FASTCOD_EHIP;
+        fs_.words = static_cast<uint32_t *>(d_fb_.p);
+        return FASTCOD_OK;
+    }
+
+    void teardown() {
+        int prev = 0;
+        (void)hipGetDevice(&prev);
+        (void)hipSetDevice(dev_);
+        for (hipStream_t st : {comp_, copy_, out_})
+            if (st) (void)hipStreamSynchronize(st);
+        for (TokenRec &tr : toks_) {
+            if (tr.ev) (void)hipEventDestroy(tr.ev);
+            if (tr.link) (void)hipEventDestroy(tr.link);
+        }
+        toks_.clear();
+        for (Slot &s : slots_) {
+            if (s.h_subs) (void)hipHostFree(s.h_subs);
+            if (s.h_base) (void)hipHostFree(s.h_base);
+            if (s.last) (void)hipEventDestroy(s.last);
+            s.h_subs = nullptr;
+            s.h_base = nullptr;
+            s.last = nullptr;
+            s.d_subs.release();
+            s.d_base.release();
+            s.d_items.release();
+        }
+        d_ovf_.release();
+        d_fb_.release();
+        if (base_) (void)hipFree(base_);
+        base_ = nullptr;
+        for (hipStream_t *st : {&comp_, &copy_, &out_})
+            if (*st) {
+                (void)hipStreamDestroy(*st);
+                *st = nullptr;
+            }
+        (void)hipSetDevice(prev);
+    }
+
+    int dev_ = 0, cus_ = 256, blocks_ = 256;
+    int64_t items_full_ = 0;
+    fcs::Config cfg_;
+    char *base_ = nullptr;
+    hipStream_t comp_ = nullptr, copy_ = nullptr, out_ = nullptr;
+    Slot slots_[kTickSlots];
+    uint64_t next_slot_ = 0;
+    std::vector<TokenRec> toks_;
+    std::vector<fcs::Token> free_toks_;
+    std::map<int32_t, CompactLayout> layouts_;
+    DevBuf d_ovf_, d_fb_;
+    fc::Overflow ovf_{};
+    fc::FallbackScratch fs_{};
+    int32_t fbN_ = 0, fbM_ = 0;
+    std::string err_;
+};
+
+}  // namespace
+
+struct fastcod_server {
+    int device = 0;
+    std::unique_ptr<fcs::Service> svc;
+};
+
+extern "C" {
+
+int fastcod_server_create(const fastcod_server_config *cfg_in, fastcod_server **out) {
+    last_error().clear();
+    if (!out) return fail(FASTCOD_EINVAL, "out is NULL");
+    *out = nullptr;
+    fastcod_server_config c{};
+    if (cfg_in) c = *cfg_in;
+    if (c.tick_points < 0 || c.chunk_points < 0 || c.max_active < 0 || c.max_active > 1024 || c.reserved != 0)
+        return fail(FASTCOD_EINVAL, "bad server configuration");
+    int dev;
+    int rc = current_device(&dev);
+    if (rc) return rc;
+    fcs::Config cfg;
+    cfg.budget = c.memory_budget;
+    if (cfg.budget == 0) {
+        size_t fr = 0, tot = 0;
+        FC_HIP(hipMemGetInfo(&fr, &tot));
+        cfg.budget = (uint64_t)((double)fr * 0.8);
+    }
+    cfg.budget &= ~uint64_t(255);
+    if (cfg.budget < (1u << 20)) return fail(FASTCOD_EINVAL, "memory_budget must be at least 1 MiB");
+    if (c.tick_points) cfg.tick_points = c.tick_points;
+    if (c.chunk_points) cfg.chunk_points = c.chunk_points;
+    if (c.max_active) cfg.max_active = c.max_active;
+    auto ex = std::make_unique<HipExecutor>();
+    rc = ex->init(dev, cfg);
+    if (rc) return rc;   // ex's destructor frees what init took
+    fastcod_server *s = new fastcod_server();
+    s->device = dev;
+    s->svc = std::make_unique<fcs::Service>(cfg, std::move(ex), [dev]() { (void)hipSetDevice(dev); });
+    *out = s;
+    return FASTCOD_OK;
+}
+
+int fastcod_server_add_volume(fastcod_server *srv, const int32_t *roi, const int32_t *lab, const int32_t dims[3],
+                              int32_t N, int32_t M, int32_t *volume_id) {
+    last_error().clear();
+    if (!srv || !volume_id) return fail(FASTCOD_EINVAL, "NULL argument");
+    int rc = check_volume_args(roi, lab, dims, N, M);
+    if (rc) return rc;
+    std::string msg;
+    rc = srv->svc->add_volume(roi, lab, dims, N, M, volume_id, &msg);
+    return rc ? fail(rc, msg) : FASTCOD_OK;
+}
+
+int fastcod_server_submit(fastcod_server *srv, const fastcod_request *req, uint64_t *request_id) {
+    last_error().clear();
+    if (!srv || !req || !request_id) return fail(FASTCOD_EINVAL, "NULL argument");
+    std::string msg;
+    const int rc = srv->svc->submit(*req, request_id, &msg);
+    return rc ? fail(rc, msg) : FASTCOD_OK;
+}
+
+int fastcod_server_wait(fastcod_server *srv, uint64_t request_id, int64_t timeout_us, fastcod_request_info *info) {
+    last_error().clear();
+    if (!srv) return fail(FASTCOD_EINVAL, "srv is NULL");
+    const int rc = srv->svc->wait(request_id, timeout_us, info);
+    if (rc == FASTCOD_EINVAL) return fail(rc, "unknown request id");
+    if (rc != FASTCOD_OK && rc != FASTCOD_ETIMEDOUT && rc != FASTCOD_ECANCELED)
+        return fail(rc, srv->svc->locked([](fcs::Core &c) { return c.fail_message(); }));
+    return rc;
+}
+
+int fastcod_server_cancel(fastcod_server *srv, uint64_t request_id) {
+    last_error().clear();
+    if (!srv) return fail(FASTCOD_EINVAL, "srv is NULL");
+    const int rc = srv->svc->cancel(request_id);
+    return rc ? fail(rc, "unknown or finished request id") : FASTCOD_OK;
+}
+
+int fastcod_server_get_stats(fastcod_server *srv, fastcod_server_stats *out) {
+    last_error().clear();
+    if (!srv || !out) return fail(FASTCOD_EINVAL, "NULL argument");
+    srv->svc->locked([out](fcs::Core &c) {
+        memset(out, 0, sizeof(*out));
+        out->budget_bytes = c.arena().size();
+        out->used_bytes = c.arena().used();
+        out->pending = (int64_t)c.pending_count();
+        out->active = (int64_t)c.active_count();
+        out->completed = (int64_t)c.completed();
+        out->launches = (int64_t)c.ticks_launched();
+        out->volume_builds = (int64_t)c.volume_builds();
+        out->evictions = (int64_t)c.evictions();
+        out->failed = c.failed();
+        return 0;
+    });
+    return FASTCOD_OK;
+}
+
+int fastcod_server_destroy(fastcod_server *srv) {
+    last_error().clear();
+    if (!srv) return FASTCOD_OK;
+    srv->svc->shutdown();
+    srv->svc.reset();   // frees the executor's device memory, streams and events
+    delete srv;
+    return FASTCOD_OK;
+}
+
+}  // extern "C"

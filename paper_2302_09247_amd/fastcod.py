@@ -26,8 +26,11 @@ EXPORTS = (
     "fastcod_strerror", "fastcod_last_error", "fastcod_release",
     "fastcod_plan_create", "fastcod_plan_launch", "fastcod_plan_get_schedule", "fastcod_plan_destroy",
     "fastcod_count_batched",
+    "fastcod_server_create", "fastcod_server_add_volume", "fastcod_server_submit", "fastcod_server_wait",
+    "fastcod_server_cancel", "fastcod_server_get_stats", "fastcod_server_destroy",
 )
 PLAN_TUNE = 1
+REQ_DEVICE_POINTS, REQ_DEVICE_C = 1, 2
 
 
 class FastcodError(RuntimeError):
@@ -52,6 +55,29 @@ class Subject(ctypes.Structure):
 class Schedule(ctypes.Structure):
     _fields_ = [("batch", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32), ("items_per_wave", ctypes.c_int32),
                 ("tuned_ms", ctypes.c_float)]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("memory_budget", ctypes.c_uint64), ("tick_points", ctypes.c_int64), ("chunk_points", ctypes.c_int64),
+                ("max_active", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("volume_id", ctypes.c_int32), ("flags", ctypes.c_uint32), ("points", ctypes.c_void_p),
+                ("offsets", ctypes.c_void_p), ("n_streamlines", ctypes.c_int64), ("scale", ctypes.c_float),
+                ("C_out", ctypes.c_void_p)]
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("t_submit_ns", ctypes.c_int64), ("t_admit_ns", ctypes.c_int64),
+                ("t_done_ns", ctypes.c_int64), ("chunks", ctypes.c_int64), ("device_bytes", ctypes.c_int64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_uint64), ("used_bytes", ctypes.c_uint64), ("pending", ctypes.c_int64),
+                ("active", ctypes.c_int64), ("completed", ctypes.c_int64), ("launches", ctypes.c_int64),
+                ("volume_builds", ctypes.c_int64), ("evictions", ctypes.c_int64), ("failed", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 _lib = None
@@ -84,10 +110,19 @@ def load(path: str = LIB_PATH):
     lib.fastcod_plan_get_schedule.argtypes = [_vp, ctypes.POINTER(Schedule)]
     lib.fastcod_plan_destroy.argtypes = [_vp]
     lib.fastcod_count_batched.argtypes = [ctypes.POINTER(Subject), i32, _vp]
+    lib.fastcod_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(_vp)]
+    lib.fastcod_server_add_volume.argtypes = [_vp, _vp, _vp, _vp, i32, i32, ctypes.POINTER(i32)]
+    lib.fastcod_server_submit.argtypes = [_vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
+    lib.fastcod_server_wait.argtypes = [_vp, ctypes.c_uint64, i64, ctypes.POINTER(RequestInfo)]
+    lib.fastcod_server_cancel.argtypes = [_vp, ctypes.c_uint64]
+    lib.fastcod_server_get_stats.argtypes = [_vp, ctypes.POINTER(ServerStats)]
+    lib.fastcod_server_destroy.argtypes = [_vp]
     for name in ("fastcod_count", "fastcod_count_ex", "fastcod_volume_create", "fastcod_volume_count",
                  "fastcod_volume_destroy", "fastcod_validate", "fastcod_release", "fastcod_plan_create",
                  "fastcod_plan_launch", "fastcod_plan_get_schedule", "fastcod_plan_destroy",
-                 "fastcod_count_batched"):
+                 "fastcod_count_batched", "fastcod_server_create", "fastcod_server_add_volume",
+                 "fastcod_server_submit", "fastcod_server_wait", "fastcod_server_cancel",
+                 "fastcod_server_get_stats", "fastcod_server_destroy"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -315,3 +350,100 @@ def count_batched(subjects, stream=None) -> None:
                                                    d["C"], d.get("scale", 1.0)) for d in subjects])
     with torch.cuda.device(subjects[0]["points"].device):
         _check(lib.fastcod_count_batched(arr, len(subjects), _stream_ptr(stream)))
+
+
+class Server:
+    """Request server (fastcod_server_*) on the current device.
+
+    Volumes are registered from host arrays; requests bring points (host or device tensor),
+    host int64 offsets and a C destination (host or device int32 [N, M]).  The server keeps a
+    reference to every submitted array until the request has been waited for.  Host arrays
+    should be pinned (``torch.empty(..., pin_memory=True)``) for the copies to overlap."""
+
+    def __init__(self, memory_budget: int = 0, tick_points: int = 0, chunk_points: int = 0, max_active: int = 0):
+        lib = load()
+        cfg = ServerConfig(int(memory_budget), int(tick_points), int(chunk_points), int(max_active), 0)
+        h = _vp()
+        _check(lib.fastcod_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self._keep = {}
+        self._vols = {}
+
+    def add_volume(self, roi, lab, N: int, M: int) -> int:
+        """Registers a [Z,Y,X] int32 volume pair (numpy arrays or CPU tensors); returns its id."""
+        roi = _host_i32(roi, "roi")
+        lab = _host_i32(lab, "lab")
+        if roi.dim() != 3 or roi.shape != lab.shape:
+            raise ValueError("roi and lab must be [Z,Y,X] volumes of one shape")
+        dims = (ctypes.c_int32 * 3)(int(roi.shape[2]), int(roi.shape[1]), int(roi.shape[0]))
+        vid = ctypes.c_int32()
+        _check(load().fastcod_server_add_volume(self._h, roi.data_ptr(), lab.data_ptr(), dims, int(N), int(M),
+                                                ctypes.byref(vid)))
+        self._vols[vid.value] = (int(N), int(M))
+        return vid.value
+
+    def submit(self, volume_id: int, points: torch.Tensor, offsets, out: torch.Tensor, scale: float = 1.0) -> int:
+        """Queues a request; ``out`` ([N, M] int32, host or device) receives C.  Returns its id."""
+        if not isinstance(points, torch.Tensor) or points.dtype != torch.float32 or not points.is_contiguous() \
+                or points.dim() != 2 or points.shape[1] != 3:
+            raise TypeError("points must be a contiguous float32 [P, 3] tensor")
+        offsets = _host_i64(offsets, "offsets")
+        if not isinstance(out, torch.Tensor) or out.dtype != torch.int32 or not out.is_contiguous():
+            raise TypeError("out must be a contiguous int32 tensor")
+        N, M = self._vols.get(volume_id, (None, None))
+        if N is not None and tuple(out.shape) != (N, M):
+            raise ValueError(f"out must be [{N}, {M}]")
+        flags = (REQ_DEVICE_POINTS if points.is_cuda else 0) | (REQ_DEVICE_C if out.is_cuda else 0)
+        pts_ptr = _points_ptr(points) if points.is_cuda else (points.data_ptr() if points.numel() else None)
+        r = Request(int(volume_id), flags, pts_ptr, offsets.data_ptr(), int(offsets.shape[0]) - 1, float(scale),
+                    out.data_ptr())
+        rid = ctypes.c_uint64()
+        _check(load().fastcod_server_submit(self._h, ctypes.byref(r), ctypes.byref(rid)))
+        self._keep[rid.value] = (points, offsets, out)
+        return rid.value
+
+    def wait(self, request_id: int, timeout: Optional[float] = None) -> dict:
+        """Waits for a request; returns its info dict (``status`` 0 = C written).  Raises
+        FastcodError(ETIMEDOUT) if it is still running after ``timeout`` seconds."""
+        info = RequestInfo()
+        us = -1 if timeout is None else int(timeout * 1e6)
+        rc = load().fastcod_server_wait(self._h, int(request_id), us, ctypes.byref(info))
+        if rc in (ETIMEDOUT, EINVAL):
+            _check(rc)
+        self._keep.pop(int(request_id), None)
+        return {"status": rc, "t_submit_ns": info.t_submit_ns, "t_admit_ns": info.t_admit_ns,
+                "t_done_ns": info.t_done_ns, "chunks": info.chunks, "device_bytes": info.device_bytes}
+
+    def cancel(self, request_id: int) -> None:
+        _check(load().fastcod_server_cancel(self._h, int(request_id)))
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(load().fastcod_server_get_stats(self._h, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_ if k != "reserved"}
+
+    def close(self) -> None:
+        if self._h is not None and self._h.value:
+            _check(load().fastcod_server_destroy(self._h))
+        self._h = None
+        self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _host_i32(a, name):
+    t = torch.as_tensor(a)
+    if t.is_cuda or t.dtype != torch.int32:
+        raise TypeError(f"{name} must be a host int32 array")
+    return t.contiguous()
+
+
+def _host_i64(a, name):
+    t = torch.as_tensor(a)
+    if t.is_cuda or t.dtype != torch.int64 or t.dim() != 1 or t.shape[0] < 1:
+        raise TypeError(f"{name} must be a host int64 [S+1] array")
+    return t.contiguous()

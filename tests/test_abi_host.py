@@ -99,3 +99,25 @@ def test_plan_create_rejects_bad_subjects(lib):
     assert lib.fastcod_plan_create(arr, 2, 0, None, None, ctypes.byref(h)) == fastcod.EINVAL
     assert lib.fastcod_plan_destroy(None) == fastcod.OK
     assert lib.fastcod_plan_launch(None, None) == fastcod.EINVAL
+
+
+def test_server_rejects_bad_arguments(lib):
+    """Server entry points check their arguments before any HIP call."""
+    import ctypes
+    out = ctypes.c_void_p()
+    bad = fastcod.ServerConfig(0, -1, 0, 0, 0)
+    assert lib.fastcod_server_create(ctypes.byref(bad), ctypes.byref(out)) == fastcod.EINVAL
+    bad = fastcod.ServerConfig(0, 0, 0, 5000, 0)
+    assert lib.fastcod_server_create(ctypes.byref(bad), ctypes.byref(out)) == fastcod.EINVAL
+    bad = fastcod.ServerConfig(0, 0, 0, 0, 1)
+    assert lib.fastcod_server_create(ctypes.byref(bad), ctypes.byref(out)) == fastcod.EINVAL
+    assert lib.fastcod_server_create(None, None) == fastcod.EINVAL
+    vid = ctypes.c_int32()
+    dims = (ctypes.c_int32 * 3)(4, 4, 4)
+    assert lib.fastcod_server_add_volume(None, None, None, dims, 1, 1, ctypes.byref(vid)) == fastcod.EINVAL
+    rid = ctypes.c_uint64()
+    assert lib.fastcod_server_submit(None, None, ctypes.byref(rid)) == fastcod.EINVAL
+    assert lib.fastcod_server_wait(None, 1, 0, None) == fastcod.EINVAL
+    assert lib.fastcod_server_cancel(None, 1) == fastcod.EINVAL
+    assert lib.fastcod_server_get_stats(None, None) == fastcod.EINVAL
+    assert lib.fastcod_server_destroy(None) == fastcod.OK
