@@ -20,7 +20,7 @@ import subprocess
 
 import numpy as np
 
-from .brute import brute_count, brute_voxel  # noqa: F401
+from .brute import brute_count, brute_count_ends, brute_voxel  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
@@ -47,12 +47,15 @@ def _load():
         lib = ctypes.CDLL(_LIB)
         lib.oracle_voxel.restype = ctypes.c_int64
         lib.oracle_voxel.argtypes = [ctypes.c_float] * 4 + [ctypes.c_void_p]
+        common = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                  ctypes.c_int32, ctypes.c_int32, ctypes.c_float]
         lib.oracle_count.restype = ctypes.c_int
-        lib.oracle_count.argtypes = [
-            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
-            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-            ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_void_p,
-        ]
+        lib.oracle_count.argtypes = common + [ctypes.c_void_p]
+        lib.oracle_count_endpoint.restype = ctypes.c_int
+        lib.oracle_count_endpoint.argtypes = common + [ctypes.c_int, ctypes.c_void_p]
+        lib.oracle_count_seed_endpoint.restype = ctypes.c_int
+        lib.oracle_count_seed_endpoint.argtypes = common + [ctypes.c_void_p]
         _lib = lib
     return _lib
 
@@ -76,10 +79,19 @@ def voxel(p, dims, scale: float = 1.0) -> int:
                                     float(np.float32(scale)), _ptr(d)))
 
 
-def count(points, offsets, roi, lab, N: int, M: int, scale: float = 1.0) -> np.ndarray:
-    """C[N, M] (int64) of the pass-through definition.
+# the counting modes of the library (same numbering as its mode option)
+MODE_PASSTHROUGH, MODE_END, MODE_BOTH_ENDS, MODE_SEED_END = 0, 1, 2, 3
+
+
+def count(points, offsets, roi, lab, N: int, M: int, scale: float = 1.0, mode: int = MODE_PASSTHROUGH) -> np.ndarray:
+    """C[N, M] (int64).
 
     points [P,3] float32, offsets [S+1] int64, roi/lab [Z,Y,X] int32.
+    mode 0: pass-through (rows and labels passed through, oracle_count);
+    mode 1: rows passed through x label of the last point (oracle_count_endpoint);
+    mode 2: rows passed through x labels of the first and last points;
+    mode 3: one count per streamline at (row of its first point, label of its last point)
+            (oracle_count_seed_endpoint).
     """
     pts = _np(points, np.float32).reshape(-1, 3)
     off = _np(offsets, np.int64).reshape(-1)
@@ -92,15 +104,23 @@ def count(points, offsets, roi, lab, N: int, M: int, scale: float = 1.0) -> np.n
         raise ValueError("offsets must start at 0, be nondecreasing and end at P")
     dims = np.array(roi.shape[::-1], dtype=np.int32)
     C = np.zeros((N, M), dtype=np.int64)
-    rc = _load().oracle_count(_ptr(pts), _ptr(off), S, _ptr(roi), _ptr(lab), _ptr(dims),
-                              int(N), int(M), float(np.float32(scale)), _ptr(C))
+    lib = _load()
+    args = (_ptr(pts), _ptr(off), S, _ptr(roi), _ptr(lab), _ptr(dims), int(N), int(M), float(np.float32(scale)))
+    if mode == MODE_PASSTHROUGH:
+        rc = lib.oracle_count(*args, _ptr(C))
+    elif mode in (MODE_END, MODE_BOTH_ENDS):
+        rc = lib.oracle_count_endpoint(*args, 1 if mode == MODE_BOTH_ENDS else 0, _ptr(C))
+    elif mode == MODE_SEED_END:
+        rc = lib.oracle_count_seed_endpoint(*args, _ptr(C))
+    else:
+        raise ValueError(f"unknown mode {mode}")
     if rc != 0:
-        raise RuntimeError(f"oracle_count failed ({rc})")
+        raise RuntimeError(f"oracle count (mode {mode}) failed ({rc})")
     return C
 
 
 def count_chunked(points, offsets, roi, lab, N: int, M: int, scale: float = 1.0,
-                  streamlines_per_chunk: int = 1 << 18, workers: int = 1) -> np.ndarray:
+                  streamlines_per_chunk: int = 1 << 18, workers: int = 1, mode: int = MODE_PASSTHROUGH) -> np.ndarray:
     """The same matrix, computed as a sum of ``count`` over streamline ranges.
 
     C is a sum over streamlines, so it is additive over any split of the
@@ -121,13 +141,13 @@ def count_chunked(points, offsets, roi, lab, N: int, M: int, scale: float = 1.0,
         jobs.append((pts[pa:pb], off[a:b + 1] - off[a]))
     if workers <= 1:
         for p, o in jobs:
-            C += count(p, o, roi, lab, N, M, scale)
+            C += count(p, o, roi, lab, N, M, scale, mode)
         return C
     import concurrent.futures as cf
     roi_np, lab_np = _np(roi, np.int32), _np(lab, np.int32)
     # ctypes releases the GIL during the call, so threads run the C oracle in parallel.
     with cf.ThreadPoolExecutor(max_workers=workers) as ex:
-        futs = [ex.submit(count, _np(p, np.float32), o, roi_np, lab_np, N, M, scale) for p, o in jobs]
+        futs = [ex.submit(count, _np(p, np.float32), o, roi_np, lab_np, N, M, scale, mode) for p, o in jobs]
         for f in futs:
             C += f.result()
     return C

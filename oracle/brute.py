@@ -44,3 +44,33 @@ def brute_count(points, offsets, roi, lab, N: int, M: int, scale: float = 1.0) -
         g[m[(m >= 0) & (m < M)]] = 1
         C += np.outer(h, g)
     return C
+
+
+def brute_count_ends(points, offsets, roi, lab, N: int, M: int, scale: float = 1.0, mode: int = 1) -> np.ndarray:
+    """The endpoint modes as dense outer products, for tiny inputs.
+
+    mode 1 (Alg. 2 as printed): h_l = ROI rows passed through, g_l = one-hot label of the last point.
+    mode 2: g_l = labels of the first and the last point (0/1 entries, so a shared label counts once).
+    mode 3 (Alg. 1's count): h_l = one-hot row of the first point (the seed), g_l as in mode 1.
+    """
+    points = np.asarray(points, dtype=np.float32).reshape(-1, 3)
+    offsets = np.asarray(offsets, dtype=np.int64)
+    roi = np.asarray(roi, dtype=np.int32)
+    lab = np.asarray(lab, dtype=np.int32)
+    Z, Y, X = roi.shape
+    C = np.zeros((N, M), dtype=np.int64)
+    for s in range(offsets.shape[0] - 1):
+        seg = points[offsets[s]:offsets[s + 1]]
+        if seg.shape[0] == 0:
+            continue
+        v, inside = brute_voxel(seg, (X, Y, Z), scale)
+        r = np.where(inside, roi[v[:, 2], v[:, 1], v[:, 0]], -1)
+        m = np.where(inside, lab[v[:, 2], v[:, 1], v[:, 0]], -1)
+        h = np.zeros(N, dtype=np.int64)
+        g = np.zeros(M, dtype=np.int64)
+        rows = r[:1] if mode == 3 else r
+        h[rows[(rows >= 0) & (rows < N)]] = 1
+        ends = m[[0, -1]] if mode == 2 else m[-1:]
+        g[ends[(ends >= 0) & (ends < M)]] = 1
+        C += np.outer(h, g)
+    return C

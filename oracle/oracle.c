@@ -26,6 +26,11 @@
  * "Super-resolving connectivity features"), every coordinate is first replaced
  * by fl32(p * s); s = 1 leaves the points unchanged.
  *
+ * Two variants follow the same conventions: oracle_count_endpoint (Alg. 2 as
+ * printed, the target label read at the streamline's last point only) and
+ * oracle_count_seed_endpoint (Alg. 1's count, one per streamline at its seed
+ * row and end label).
+ *
  * Readings taken where the paper is silent (rounding, out-of-grid points,
  * repeated visits, values outside [0,N) / [0,M)) are listed in the design notes
  * of the repository; each one is exercised by a test.
@@ -134,5 +139,103 @@ int oracle_count(const float *points, const int64_t *offsets, int64_t S,
     }
     free(I);
     free(L);
+    return 0;
+}
+
+/* Row of the voxel holding one point, or -1 (no voxel, or an ROI value outside [0, N)). */
+static int32_t row_at(const float *p, float scale, const int32_t *roi, const int32_t dims[3], int32_t N)
+{
+    int64_t lin = oracle_voxel(p[0], p[1], p[2], scale, dims);
+    if (lin < 0)
+        return -1;
+    return (roi[lin] >= 0 && roi[lin] < N) ? roi[lin] : -1;
+}
+
+/* Label of the voxel holding one point (loc2region), or -1 (no voxel, or a value outside [0, M)). */
+static int32_t label_at(const float *p, float scale, const int32_t *lab, const int32_t dims[3], int32_t M)
+{
+    int64_t lin = oracle_voxel(p[0], p[1], p[2], scale, dims);
+    if (lin < 0)
+        return -1;
+    return (lab[lin] >= 0 && lab[lin] < M) ? lab[lin] : -1;
+}
+
+/*
+ * Endpoint-label matrix: Alg. 2 as printed, where loc2region reads only the
+ * last point p^T of the streamline while passthrough reads all of them.
+ *   I_l     = the ROI rows passed through, as in oracle_count;
+ *   E_l     = { label of p^T }, empty when p^T has no voxel or no label;
+ *             with both_ends, E_l also holds the label of the first point p^1
+ *             (a set: a label at both ends is counted once);
+ *   C[i][m] = #{ l : i in I_l and m in E_l }.
+ * Arguments as oracle_count.
+ */
+int oracle_count_endpoint(const float *points, const int64_t *offsets, int64_t S,
+                          const int32_t *roi, const int32_t *lab, const int32_t dims[3],
+                          int32_t N, int32_t M, float scale, int both_ends, int64_t *C)
+{
+    if (S < 0 || N < 1 || M < 1 || !C || !dims)
+        return -1;
+    memset(C, 0, sizeof(int64_t) * (size_t)N * (size_t)M);
+    int64_t cap = 0;
+    int32_t *I = NULL;
+    for (int64_t s = 0; s < S; ++s) {
+        int64_t a = offsets[s], b = offsets[s + 1];
+        if (b <= a)
+            continue;
+        int32_t e_last = label_at(points + 3 * (b - 1), scale, lab, dims, M);
+        int32_t e_first = both_ends ? label_at(points + 3 * a, scale, lab, dims, M) : -1;
+        if (e_first == e_last)
+            e_first = -1;                   /* the set E_l holds a shared label once */
+        if (e_last < 0 && e_first < 0)
+            continue;
+        if (b - a > cap) {
+            free(I);
+            cap = b - a;
+            I = (int32_t *)malloc(sizeof(int32_t) * (size_t)cap);
+            if (!I)
+                return -1;
+        }
+        int64_t nI = 0;
+        for (int64_t j = a; j < b; ++j) {
+            int32_t r = row_at(points + 3 * j, scale, roi, dims, N);
+            if (r >= 0)
+                I[nI++] = r;
+        }
+        nI = sort_unique(I, nI);
+        for (int64_t x = 0; x < nI; ++x) {
+            if (e_last >= 0)
+                C[(int64_t)I[x] * M + e_last] += 1;
+            if (e_first >= 0)
+                C[(int64_t)I[x] * M + e_first] += 1;
+        }
+    }
+    free(I);
+    return 0;
+}
+
+/*
+ * Seed-to-endpoint counting, the analogue of Alg. 1 on the same streamlines:
+ * the streamline grown from a seed in voxel v_i adds one to C(v_i,
+ * loc2region(p^T)).  The seed is the streamline's first point p^1:
+ *   C[i][m] = #{ l : row of p^1 is i and label of p^T is m }.
+ * Arguments as oracle_count.
+ */
+int oracle_count_seed_endpoint(const float *points, const int64_t *offsets, int64_t S,
+                               const int32_t *roi, const int32_t *lab, const int32_t dims[3],
+                               int32_t N, int32_t M, float scale, int64_t *C)
+{
+    if (S < 0 || N < 1 || M < 1 || !C || !dims)
+        return -1;
+    memset(C, 0, sizeof(int64_t) * (size_t)N * (size_t)M);
+    for (int64_t s = 0; s < S; ++s) {
+        int64_t a = offsets[s], b = offsets[s + 1];
+        if (b <= a)
+            continue;
+        int32_t seed_row = row_at(points + 3 * a, scale, roi, dims, N);
+        int32_t end_label = label_at(points + 3 * (b - 1), scale, lab, dims, M);
+        if (seed_row >= 0 && end_label >= 0)
+            C[(int64_t)seed_row * M + end_label] += 1;
+    }
     return 0;
 }

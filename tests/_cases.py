@@ -32,8 +32,11 @@ def load_golden(name: str):
         pts.append(arr)
         off.append(off[-1] + arr.shape[0])
     points = np.concatenate(pts) if pts else np.zeros((0, 3), np.float32)
-    return dict(points=points, offsets=np.array(off, dtype=np.int64), roi=roi, lab=lab,
-                N=g["N"], M=g["M"], C=np.array(g["C"], dtype=np.int64))
+    out = dict(points=points, offsets=np.array(off, dtype=np.int64), roi=roi, lab=lab, N=g["N"], M=g["M"])
+    for k, v in g.items():
+        if k == "C" or k.startswith("C_"):
+            out[k] = np.array(v, dtype=np.int64)
+    return out
 
 
 def identity_volumes(dims, M, label_of):

@@ -37,6 +37,23 @@ MUTANTS = {
     "first_label_only": ("for (int64_t y = 0; y < nL; ++y)", "for (int64_t y = 0; y < nL && y < 1; ++y)"),
     "ignores_scale": ("float q = p[k] * scale;", "float q = p[k];"),
     "uses_x_bound_everywhere": ("!((double)f < (double)dims[k])", "!((double)f < (double)dims[0])"),
+    # endpoint modes (oracle_count_endpoint, oracle_count_seed_endpoint)
+    "end_label_from_first_point": ("int32_t e_last = label_at(points + 3 * (b - 1),",
+                                   "int32_t e_last = label_at(points + 3 * a,"),
+    "shared_end_label_counted_twice": ("if (e_first == e_last)\n            e_first = -1;",
+                                       "if (0)\n            e_first = -1;"),
+    "end_mode_no_row_dedupe": ("nI = sort_unique(I, nI);\n        for (int64_t x = 0; x < nI; ++x) {\n            if (e_last",
+                               "(void)0;\n        for (int64_t x = 0; x < nI; ++x) {\n            if (e_last"),
+    "end_mode_skips_first_point_rows": ("for (int64_t j = a; j < b; ++j) {\n            int32_t r = row_at(",
+                                        "for (int64_t j = a + 1; j < b; ++j) {\n            int32_t r = row_at("),
+    "seed_row_from_last_point": ("int32_t seed_row = row_at(points + 3 * a,",
+                                 "int32_t seed_row = row_at(points + 3 * (b - 1),"),
+    "seed_end_label_from_first_point": ("int32_t end_label = label_at(points + 3 * (b - 1),",
+                                        "int32_t end_label = label_at(points + 3 * a,"),
+    "label_at_drops_label_zero": ("return (lab[lin] >= 0 && lab[lin] < M) ? lab[lin] : -1;",
+                                  "return (lab[lin] > 0 && lab[lin] < M) ? lab[lin] : -1;"),
+    "row_at_drops_row_zero": ("return (roi[lin] >= 0 && roi[lin] < N) ? roi[lin] : -1;",
+                              "return (roi[lin] > 0 && roi[lin] < N) ? roi[lin] : -1;"),
 }
 
 
@@ -49,13 +66,17 @@ def _build(src_text, tmp_path, name):
     lib.oracle_voxel.restype = ctypes.c_int64
     lib.oracle_voxel.argtypes = [ctypes.c_float] * 4 + [ctypes.c_void_p]
     lib.oracle_count.restype = ctypes.c_int
-    lib.oracle_count.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
-                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
-                                 ctypes.c_float, ctypes.c_void_p]
+    common = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+              ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_float]
+    lib.oracle_count.argtypes = common + [ctypes.c_void_p]
+    lib.oracle_count_endpoint.restype = ctypes.c_int
+    lib.oracle_count_endpoint.argtypes = common + [ctypes.c_int, ctypes.c_void_p]
+    lib.oracle_count_seed_endpoint.restype = ctypes.c_int
+    lib.oracle_count_seed_endpoint.argtypes = common + [ctypes.c_void_p]
     return lib
 
 
-def _count(lib, points, offsets, roi, lab, N, M, scale=1.0):
+def _count(lib, points, offsets, roi, lab, N, M, scale=1.0, mode=0):
     p = np.ascontiguousarray(points, np.float32)
     o = np.ascontiguousarray(offsets, np.int64)
     r = np.ascontiguousarray(roi, np.int32)
@@ -63,8 +84,14 @@ def _count(lib, points, offsets, roi, lab, N, M, scale=1.0):
     d = np.array(r.shape[::-1], np.int32)
     C = np.zeros((N, M), np.int64)
     ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)   # noqa: E731
-    assert lib.oracle_count(ptr(p), ptr(o), o.shape[0] - 1, ptr(r), ptr(lb), ptr(d), N, M,
-                            float(np.float32(scale)), ptr(C)) == 0
+    args = (ptr(p), ptr(o), o.shape[0] - 1, ptr(r), ptr(lb), ptr(d), N, M, float(np.float32(scale)))
+    if mode == 0:
+        rc = lib.oracle_count(*args, ptr(C))
+    elif mode in (1, 2):
+        rc = lib.oracle_count_endpoint(*args, mode - 1, ptr(C))
+    else:
+        rc = lib.oracle_count_seed_endpoint(*args, ptr(C))
+    assert rc == 0
     return C
 
 
@@ -98,6 +125,17 @@ def _battery(lib):
         for scale in (1.0, 1.7857143):
             if not np.array_equal(_count(lib, *args, scale=scale), brute.brute_count(*args, scale=scale)):
                 failed.append(f"brute {seed} {scale}")
+    # endpoint modes: the hand-worked case and the dense brute force
+    g = _cases.load_golden("toy_endpoints.json")
+    for mode, key in ((1, "C_end"), (2, "C_both_ends"), (3, "C_seed_end")):
+        if not np.array_equal(_count(lib, g["points"], g["offsets"], g["roi"], g["lab"], g["N"], g["M"], mode=mode),
+                              g[key]):
+            failed.append(f"golden endpoints mode {mode}")
+        for seed in range(4):
+            w = synth.random_small(seed, N=(None if seed % 2 else 6), bad_values=True)
+            args = (w.points.numpy(), w.offsets.numpy(), w.roi.numpy(), w.lab.numpy(), w.N, w.M)
+            if not np.array_equal(_count(lib, *args, mode=mode), brute.brute_count_ends(*args, mode=mode)):
+                failed.append(f"brute ends {seed} mode {mode}")
     return failed
 
 
