@@ -62,6 +62,14 @@ extern "C" {
 #define FASTCOD_VARIANT_WAVE 1   /* one wavefront per streamline, raster volume lookups            */
 #define FASTCOD_VARIANT_STREAM 2 /* flat point stream split at streamline starts, compact volume   */
 
+/* fastcod_opts.mode: which target labels a streamline contributes (Section 2; Alg. 1 and 2).
+ * Rows are always I_l, the ROI rows the streamline passes through, except in SEED_END. */
+#define FASTCOD_MODE_PASSTHROUGH 0 /* labels of every point: C(i, m) for m passed through (default)  */
+#define FASTCOD_MODE_END 1         /* Alg. 2 as printed: loc2region of the last point p^T only       */
+#define FASTCOD_MODE_BOTH_ENDS 2   /* labels of the first and the last point (a shared one once)     */
+#define FASTCOD_MODE_SEED_END 3    /* Alg. 1's count: C(row of p^1, label of p^T) += 1 per streamline; */
+                                   /* the seed is the first point                                      */
+
 typedef struct fastcod_opts {
     float scale;        /* coordinate scale s applied before voxelisation; 1.0f = none              */
     int32_t upsample;   /* must be 1 (points are used as given)                                     */
@@ -71,9 +79,10 @@ typedef struct fastcod_opts {
     void *event_end;    /* optional hipEvent_t, recorded on `stream` just after it                  */
     int32_t batch;      /* flat-stream schedule: 64-point windows per pipelined batch, 2 or 4; 0 = 4 */
     int32_t blocks_per_cu; /* flat-stream schedule: resident workgroups per CU, 0 = occupancy limit */
+    int32_t mode;       /* FASTCOD_MODE_*; the batched and served forms count FASTCOD_MODE_PASSTHROUGH */
 } fastcod_opts;
 
-/* Default options: {1.0f, 1, 0, FASTCOD_VARIANT_AUTO, NULL, NULL, 0, 0}. */
+/* Default options: {1.0f, 1, 0, FASTCOD_VARIANT_AUTO, NULL, NULL, 0, 0, FASTCOD_MODE_PASSTHROUGH}. */
 fastcod_opts fastcod_default_opts(void);
 
 /*

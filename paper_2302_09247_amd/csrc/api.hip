@@ -28,6 +28,7 @@ struct Workspace {
     DevBuf fallback;    // fallback scratch (all-zero between launches)
     DevBuf flags;       // validation flags
     DevBuf ct;          // transposed accumulation copy of C
+    DevBuf ends;        // per-streamline end labels of the endpoint modes
 };
 
 std::mutex g_ws_mu;
@@ -51,6 +52,7 @@ int check_stream_args(const float *points, const int64_t *offsets, int64_t S, in
     if (o.variant < FASTCOD_VARIANT_AUTO || o.variant > FASTCOD_VARIANT_STREAM) return fail(FASTCOD_EINVAL, "unknown variant");
     if (o.batch != 0 && o.batch != 2 && o.batch != 4) return fail(FASTCOD_EINVAL, "batch must be 0, 2 or 4");
     if (o.blocks_per_cu < 0) return fail(FASTCOD_EINVAL, "blocks_per_cu must be >= 0");
+    if (o.mode < FASTCOD_MODE_PASSTHROUGH || o.mode > FASTCOD_MODE_SEED_END) return fail(FASTCOD_EINVAL, "unknown mode");
     return FASTCOD_OK;
 }
 
@@ -94,6 +96,23 @@ int enqueue_count(Workspace &ws, int dev, const float *points, const int64_t *of
                   const fc::Grid &g, int32_t N, int32_t M, const fc::RasterVol *rv, const fc::CompactVol *cv,
                   int32_t *C, const fastcod_opts &o, hipStream_t st) {
     const int cus = cu_count(dev);
+    if (o.mode == FASTCOD_MODE_SEED_END) {
+        // Alg. 1's count: one update per streamline, straight into C
+        if (!(o.flags & FASTCOD_ACCUMULATE)) FC_HIP(fc::launch_fill_i32(C, (int64_t)N * M, 0, cus, st));
+        fc::CountArgs a{};
+        a.pts = points;
+        a.offsets = offsets;
+        a.S = S;
+        a.g = g;
+        a.scale = o.scale;
+        a.C = C;
+        a.si = (uint32_t)M;
+        a.sm = 1u;
+        if (o.event_begin) FC_HIP(hipEventRecord((hipEvent_t)o.event_begin, st));
+        FC_HIP(fc::launch_count_seed_end(a, rv, cv, cus, st));
+        if (o.event_end) FC_HIP(hipEventRecord((hipEvent_t)o.event_end, st));
+        return FASTCOD_OK;
+    }
     // The flat-stream path accumulates into a transposed workspace copy CT[M][N]: the rows of one
     // streamline are neighbouring ROI indices, so its pair updates share memory lines there.
     const bool transposed = cv != nullptr && S > 0 && M > 1 && N >= 64;
@@ -120,6 +139,15 @@ int enqueue_count(Workspace &ws, int dev, const float *points, const int64_t *of
         a.sm = (uint32_t)N;
         FC_HIP(fc::launch_fill_i32(a.C, (int64_t)N * M, 0, cus, st));
     }
+    a.ends = fc::EndLabels{0, nullptr, nullptr};
+    if (o.mode == FASTCOD_MODE_END || o.mode == FASTCOD_MODE_BOTH_ENDS) {
+        const int nl = o.mode == FASTCOD_MODE_BOTH_ENDS ? 2 : 1;
+        FC_HIP(ws.ends.ensure(4 * (size_t)S * nl, false));
+        int32_t *last = static_cast<int32_t *>(ws.ends.p);
+        int32_t *first = nl == 2 ? last + S : nullptr;
+        a.ends = fc::EndLabels{o.mode, last, first};
+        FC_HIP(fc::launch_end_labels(a, rv, cv, o.mode, last, first, cus, st));
+    }
     a.ovf.count = static_cast<unsigned long long *>(ws.ovf.p);
     a.ovf.list = reinterpret_cast<int64_t *>(static_cast<char *>(ws.ovf.p) + 256);
     a.ovf.cap = S;
@@ -131,7 +159,7 @@ int enqueue_count(Workspace &ws, int dev, const float *points, const int64_t *of
     const int64_t resident = (int64_t)cus * kBlocksPerCU;
     if (cv) {
         const int batch = o.batch == 2 ? 2 : 4;
-        int per_cu = fc::count_stream_blocks_per_cu(o.scale != 1.0f, cv->packed != 0, batch,
+        int per_cu = fc::count_stream_blocks_per_cu(o.scale != 1.0f, cv->packed != 0, batch, a.ends.mode != 0,
                                                     4 * (size_t)cv->ncoarse_words);
         if (o.blocks_per_cu > 0 && o.blocks_per_cu < per_cu) per_cu = o.blocks_per_cu;
         const int64_t blocks = (int64_t)cus * per_cu;
@@ -370,6 +398,7 @@ int plan_build(const fastcod_subject *subjects, int32_t n, uint32_t flags, const
         ss.C = u.C_out;
         ss.si = (uint32_t)u.M;
         ss.sm = 1u;
+        ss.ends = fc::EndLabels{0, nullptr, nullptr};
         pl->subs.push_back(ss);
         pl->sizes.push_back((int64_t)u.N * u.M);
         total_s += u.n_streamlines;
@@ -481,6 +510,7 @@ fastcod_opts fastcod_default_opts(void) {
     o.event_end = nullptr;
     o.batch = 0;
     o.blocks_per_cu = 0;
+    o.mode = FASTCOD_MODE_PASSTHROUGH;
     return o;
 }
 
@@ -648,6 +678,7 @@ int fastcod_release(void) {
         w->fallback.release();
         w->flags.release();
         w->ct.release();
+        w->ends.release();
         delete w;
     }
     g_ws.clear();

@@ -65,6 +65,15 @@ struct FallbackScratch {
 
 // C is addressed as C[i * si + m * sm]: row-major [N][M] (si = M, sm = 1) or the transposed
 // accumulation layout [M][N] (si = 1, sm = N); N * M < 2^31.
+// Target labels of the endpoint modes.  mode 0: every point's label (pass-through); mode 1: the
+// label of each streamline's last point only; mode 2: the labels of its first and last points.
+// last[s] / first[s]: those labels per streamline (-1 = none), computed before the count.
+struct EndLabels {
+    int32_t mode;
+    const int32_t *last;
+    const int32_t *first;
+};
+
 struct CountArgs {
     const float *pts;
     const int64_t *offsets;
@@ -74,12 +83,12 @@ struct CountArgs {
     int32_t *C;
     uint32_t si, sm;
     Overflow ovf;
+    EndLabels ends;
 };
 
-// Everything the flat-stream kernels need about one subject (also a device-side descriptor of the
-// batched form).
-// One subject of the batched kernels: streamlines [s_begin, S) of (pts, offsets) are counted into C.
-// s_begin > 0 lets a caller count one streamline range of a larger set (offsets stay absolute).
+// Everything the flat-stream kernels need about one subject (also the device-side descriptor of
+// the batched form): streamlines [s_begin, S) of (pts, offsets) are counted into C.  s_begin > 0
+// lets a caller count one streamline range of a larger set (offsets stay absolute).
 struct StreamSubject {
     const float *pts;
     const int64_t *offsets;
@@ -90,6 +99,7 @@ struct StreamSubject {
     CompactVol cv;
     int32_t *C;
     uint32_t si, sm;
+    EndLabels ends;
 };
 
 // ---- launchers (kernels.hip); every launcher returns the hipError_t of its launch ----
@@ -106,9 +116,16 @@ hipError_t launch_compact_build(const int32_t *roi, const int32_t *lab, Grid g, 
 hipError_t launch_partition(const int64_t *offsets, int64_t S, int64_t nparts, int32_t *first, int cus,
                             hipStream_t st);
 // resident 256-thread workgroups per CU of the flat-stream kernel
-int count_stream_blocks_per_cu(bool scaled, bool packed, int batch, size_t dyn_lds);
+int count_stream_blocks_per_cu(bool scaled, bool packed, int batch, bool ends, size_t dyn_lds);
 
 hipError_t launch_count_wave(const CountArgs &a, const RasterVol &rv, int blocks, hipStream_t st);
+// endpoint modes: last[s] (and, mode 2, first[s]) = label of streamline s's last (first) point,
+// looked up in the raster volume when rv is given, else in the compact volume cv
+hipError_t launch_end_labels(const CountArgs &a, const RasterVol *rv, const CompactVol *cv, int mode, int32_t *last,
+                             int32_t *first, int cus, hipStream_t st);
+// Alg. 1's count: C(row of the first point, label of the last point) += 1 for every streamline
+hipError_t launch_count_seed_end(const CountArgs &a, const RasterVol *rv, const CompactVol *cv, int cus,
+                                 hipStream_t st);
 // wavefronts take the nparts ranges of `first` from ovf.work; batch: 64-point windows per
 // pipelined batch (2 or 4)
 hipError_t launch_count_stream(const CountArgs &a, const CompactVol &cv, const int32_t *first, int64_t nparts,

@@ -256,6 +256,18 @@ struct DeferredSet {
     }
     __device__ bool has_state() const { return (nR | nL) != 0 || skip; }
 
+    // Endpoint modes: the open streamline's labels are its end labels (ml, mf; -1 = none) instead of
+    // its points' labels (none were appended).  Nothing to do without rows.
+    __device__ void add_end_labels(int ml, int mf) {
+        if (skip || nR == 0) return;
+        const int addl = ml >= 0 ? 1 : 0, addf = (mf >= 0 && mf != ml) ? 1 : 0;
+        if (lane_id() == 0) {
+            if (addl) labs[nL] = (uint32_t)ml;
+            if (addf) labs[nL + addl] = (uint32_t)mf;
+        }
+        nL += addl + addf;
+    }
+
     // Appends the candidates of the lanes in cR (rows) and cM (labels); false when a list is full.
     __device__ bool append(uint64_t cR, int r, uint64_t cM, int m) {
         const int addR = __popcll(cR), addM = __popcll(cM);
@@ -580,6 +592,7 @@ __global__ void __launch_bounds__(kBlock) k_count_wave(CountArgs a, RasterVol rv
     DirectSink sink{a.C};
     const int64_t Ptot = a.offsets[a.S] > 0 ? a.offsets[a.S] : 0;
     const int64_t nw = (int64_t)gridDim.x * kWavesPerBlock;
+    const bool endmode = a.ends.mode != 0;   // endpoint modes: labels come from a.ends at the close
     for (int64_t s = (int64_t)blockIdx.x * kWavesPerBlock + wv; s < a.S; s += nw) {
         const int64_t b0 = clamp64(a.offsets[s], 0, Ptot);
         const int64_t b1 = clamp64(a.offsets[s + 1], b0, Ptot);
@@ -592,6 +605,7 @@ __global__ void __launch_bounds__(kBlock) k_count_wave(CountArgs a, RasterVol rv
                             z = load_stream(a.pts + 3 * p + 2);
                 int ix, iy, iz;
                 if (voxelise<SCALED>(x, y, z, a.scale, a.g, ix, iy, iz)) raster_get(rv, ix, iy, iz, r, m);
+                if (endmode) m = -1;
             }
             // drop a hit equal to the previous point's (same voxel row/label), then the LDS set
             int rp = __shfl_up(r, 1), mp = __shfl_up(m, 1);
@@ -605,6 +619,15 @@ __global__ void __launch_bounds__(kBlock) k_count_wave(CountArgs a, RasterVol rv
             last_m = __shfl(m, kWave - 1);
             if ((candR | candM) == 0ull || set.skip) continue;
             if (!set.add(candR, r, candM, m)) {
+                push_overflow(a.ovf, b0);
+                set.clear_entries();
+                set.skip = true;
+            }
+        }
+        if (endmode && !set.skip && set.nI > 0) {
+            const int ml = a.ends.last[s], mf = a.ends.mode == 2 ? a.ends.first[s] : -1;
+            const uint64_t cand = __ballot((lane == 0 && ml >= 0) || (lane == 1 && mf >= 0 && mf != ml));
+            if (cand && !set.add(0ull, 0, cand, lane == 0 ? ml : mf)) {
                 push_overflow(a.ovf, b0);
                 set.clear_entries();
                 set.skip = true;
@@ -668,7 +691,7 @@ using StreamSet = DeferredSet<kRCap, kLCap, kTCap>;
 // Counts streamlines [s0, s1) of one subject (whole streamlines only) into sub.C through `sink`.
 // `coarse` is the subject's coarse occupancy map in LDS.  PACKED: 0/1 = code width known at compile
 // time, 2 = read from cv.packed.
-template <bool SCALED, int PACKED, int kBatch>
+template <bool SCALED, int PACKED, int kBatch, bool kEnds>
 __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, int64_t s0, int64_t s1, int32_t subject,
                              const Overflow &ovf, StreamSet &set, BufferedSink &sink) {
     const int lane = lane_id();
@@ -687,6 +710,9 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
     const int64_t P0 = uniform64(clamp64(sub.offsets[s0], 0, Ptot));
     const int64_t P1 = uniform64(clamp64(sub.offsets[s1], P0, Ptot));
     if (P0 >= P1) return;
+    // endpoint modes (kEnds instantiations only): no point contributes its label; each closing
+    // streamline gets its end labels
+    const bool endmode = kEnds && uniform32(sub.ends.mode) != 0;
     // Starts of streamlines s0+1 .. s1-1, 64 at a time, one per lane (P1 = "no more starts");
     // k0 of them are consumed and `nxt` (uniform) is the next unconsumed start.
     int64_t vb = s0 + 1;
@@ -706,8 +732,9 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
             nxt = readlane64(voff, k0);
         }
     };
-    // starts in [wb, wend) (wend <= wb + 64) as lane bits relative to wb; consumes them
-    auto take_starts = [&](int64_t wb, int64_t wend) -> uint64_t {
+    // starts in [wb, wend) (wend <= wb + 64) as lane bits relative to wb; consumes them.  `mult`
+    // (endpoint modes) counts the streamlines starting at each lane: empty streamlines share a start.
+    auto take_starts = [&](int64_t wb, int64_t wend, int &mult) -> uint64_t {
         uint64_t starts = 0;
         while (nxt < wend) {
             const uint64_t inwin = __ballot(lane >= k0 && voff < wend);
@@ -717,7 +744,9 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
             while (it) {
                 const int k = __builtin_ctzll(it);
                 it &= it - 1ull;
-                starts |= 1ull << __builtin_amdgcn_readlane((int)qv, k);
+                const int q = __builtin_amdgcn_readlane((int)qv, k);
+                starts |= 1ull << q;
+                if (endmode) mult += lane == q ? 1 : 0;
             }
             consumed(inwin);
         }
@@ -727,6 +756,14 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
         while (nxt < limit) consumed(__ballot(lane >= k0 && voff < limit));
     };
     load_starts();
+    // the open streamline is vb - 1 + k0: the last one whose start has been consumed
+    auto close_open = [&](int64_t id) {
+        if (endmode) {
+            id = id < s0 ? s0 : (id >= s1 ? s1 - 1 : id);
+            set.add_end_labels(sub.ends.last[id], sub.ends.mode == 2 ? sub.ends.first[id] : -1);
+        }
+        set.close(sink, sub.si, sub.sm);
+    };
     int last_r = -1, last_m = -1;
     // points from `pbase` (re-based if a range ever passes 4 GB)
     int64_t pbase = P0;
@@ -845,7 +882,7 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
             // open streamline, whose hits all came earlier)
             const int64_t bend = (w0 + BW < P1) ? w0 + BW : P1;
             if (nxt < bend) {
-                if (set.has_state()) set.close(sink, sub.si, sub.sm);
+                if (set.has_state()) close_open(vb - 1 + k0);
                 skip_starts(bend);
             }
             last_r = last_m = -1;
@@ -857,13 +894,15 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
             if (wb >= P1) break;
             const int64_t wend = (wb + kWave < P1) ? wb + kWave : P1;
             // streamline starts inside this window -> bit q of `starts` for lane q
-            const uint64_t starts = (nxt < wend) ? take_starts(wb, wend) : 0ull;
+            const int64_t id0 = vb - 1 + k0;   // the streamline open at the window's first point
+            int mult = 0;
+            const uint64_t starts = (nxt < wend) ? take_starts(wb, wend, mult) : 0ull;
             if (fl[b] == 0ull) {
-                if (starts && set.has_state()) set.close(sink, sub.si, sub.sm);
+                if (starts && set.has_state()) close_open(id0);
                 last_r = last_m = -1;
                 continue;
             }
-            const int rb = r[b], mb = m[b];
+            const int rb = r[b], mb = endmode ? -1 : m[b];
             // previous point's row / label (lane 0: the last point of the previous window)
             int rp_ = __builtin_amdgcn_update_dpp(last_r, rb, 0x138, 0xF, 0xF, false);   // wave_shr:1
             int mp_ = __builtin_amdgcn_update_dpp(last_m, mb, 0x138, 0xF, 0xF, false);
@@ -881,6 +920,7 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
                 continue;
             }
             int pos = 0;
+            int64_t id = id0;
             uint64_t st = starts;
             for (;;) {
                 const int end = st ? __builtin_ctzll(st) : kWave;
@@ -892,7 +932,8 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
                     set.skip = true;
                 }
                 if (!st) break;
-                set.close(sink, sub.si, sub.sm);
+                close_open(id);
+                if (endmode) id += __builtin_amdgcn_readlane(mult, end);
                 pos = end;
                 st &= st - 1ull;
             }
@@ -900,10 +941,10 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
     };
     load_batch(P0, ax, ay, az);
     for (int64_t w0 = P0; w0 < P1; w0 += BW) run_batch(w0, ax, ay, az);
-    set.close(sink, sub.si, sub.sm);
+    close_open(vb - 1 + k0);
 }
 
-template <bool SCALED, bool PACKED, int kBatch>
+template <bool SCALED, bool PACKED, int kBatch, bool kEnds>
 __global__ void __launch_bounds__(kBlock) k_count_stream(StreamSubject sub, Overflow ovf, const int32_t *__restrict__ first,
                                                          int64_t nparts) {
     __shared__ uint32_t s_set[kWavesPerBlock * kSetWords];
@@ -925,7 +966,7 @@ __global__ void __launch_bounds__(kBlock) k_count_stream(StreamSubject sub, Over
         const int64_t s0 = uniform64(clamp64(first[part], 0, sub.S));
         const int64_t s1 = uniform64(clamp64(first[part + 1], s0, sub.S));
         if (s0 >= s1) continue;
-        stream_range<SCALED, PACKED ? 1 : 0, kBatch>(sub, s_coarse, s0, s1, 0, ovf, set, sink);
+        stream_range<SCALED, PACKED ? 1 : 0, kBatch, kEnds>(sub, s_coarse, s0, s1, 0, ovf, set, sink);
     }
     sink.drain();
 }
@@ -968,27 +1009,28 @@ __global__ void __launch_bounds__(kBlock) k_count_batched(const StreamSubject *_
             loaded = subject;
         }
         sink.C = sub.C;
-        stream_range<true, 2, kBatch>(sub, coarse, s0, s1, subject, ovf, set, sink);
+        stream_range<true, 2, kBatch, false>(sub, coarse, s0, s1, subject, ovf, set, sink);
         sink.drain();   // the next item may belong to another subject's C
     }
 }
 
-template <bool SCALED, bool PACKED, int B>
+template <bool SCALED, bool PACKED, int B, bool E>
 static int blocks_per_cu_of(size_t dyn) {
     int n = 0;
     const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &n, reinterpret_cast<const void *>(&k_count_stream<SCALED, PACKED, B>), kBlock, dyn);
+        &n, reinterpret_cast<const void *>(&k_count_stream<SCALED, PACKED, B, E>), kBlock, dyn);
     return (e == hipSuccess && n > 0) ? n : 4;
 }
 
-template <int B>
+template <int B, bool E>
 static int blocks_per_cu_b(bool scaled, bool packed, size_t dyn) {
-    if (scaled) return packed ? blocks_per_cu_of<true, true, B>(dyn) : blocks_per_cu_of<true, false, B>(dyn);
-    return packed ? blocks_per_cu_of<false, true, B>(dyn) : blocks_per_cu_of<false, false, B>(dyn);
+    if (scaled) return packed ? blocks_per_cu_of<true, true, B, E>(dyn) : blocks_per_cu_of<true, false, B, E>(dyn);
+    return packed ? blocks_per_cu_of<false, true, B, E>(dyn) : blocks_per_cu_of<false, false, B, E>(dyn);
 }
 
-int count_stream_blocks_per_cu(bool scaled, bool packed, int batch, size_t dyn) {
-    return batch == 2 ? blocks_per_cu_b<2>(scaled, packed, dyn) : blocks_per_cu_b<4>(scaled, packed, dyn);
+int count_stream_blocks_per_cu(bool scaled, bool packed, int batch, bool ends, size_t dyn) {
+    if (ends) return batch == 2 ? blocks_per_cu_b<2, true>(scaled, packed, dyn) : blocks_per_cu_b<4, true>(scaled, packed, dyn);
+    return batch == 2 ? blocks_per_cu_b<2, false>(scaled, packed, dyn) : blocks_per_cu_b<4, false>(scaled, packed, dyn);
 }
 
 static StreamSubject stream_subject(const CountArgs &a, const CompactVol &cv) {
@@ -1003,25 +1045,32 @@ static StreamSubject stream_subject(const CountArgs &a, const CompactVol &cv) {
     s.C = a.C;
     s.si = a.si;
     s.sm = a.sm;
+    s.ends = a.ends;
     return s;
 }
 
-template <int B>
+template <int B, bool E>
 static void launch_stream_b(const CountArgs &a, const CompactVol &cv, const int32_t *first, int64_t nparts, int blocks,
                             hipStream_t st) {
     const bool scaled = a.scale != 1.0f;
     const size_t dyn = 4 * (size_t)cv.ncoarse_words;
     const StreamSubject sub = stream_subject(a, cv);
-    if (scaled && cv.packed) k_count_stream<true, true, B><<<blocks, kBlock, dyn, st>>>(sub, a.ovf, first, nparts);
-    else if (scaled) k_count_stream<true, false, B><<<blocks, kBlock, dyn, st>>>(sub, a.ovf, first, nparts);
-    else if (cv.packed) k_count_stream<false, true, B><<<blocks, kBlock, dyn, st>>>(sub, a.ovf, first, nparts);
-    else k_count_stream<false, false, B><<<blocks, kBlock, dyn, st>>>(sub, a.ovf, first, nparts);
+    if (scaled && cv.packed) k_count_stream<true, true, B, E><<<blocks, kBlock, dyn, st>>>(sub, a.ovf, first, nparts);
+    else if (scaled) k_count_stream<true, false, B, E><<<blocks, kBlock, dyn, st>>>(sub, a.ovf, first, nparts);
+    else if (cv.packed) k_count_stream<false, true, B, E><<<blocks, kBlock, dyn, st>>>(sub, a.ovf, first, nparts);
+    else k_count_stream<false, false, B, E><<<blocks, kBlock, dyn, st>>>(sub, a.ovf, first, nparts);
 }
 
 hipError_t launch_count_stream(const CountArgs &a, const CompactVol &cv, const int32_t *first, int64_t nparts,
                                int blocks, int batch, hipStream_t st) {
-    if (batch == 2) launch_stream_b<2>(a, cv, first, nparts, blocks, st);
-    else launch_stream_b<4>(a, cv, first, nparts, blocks, st);
+    const bool ends = a.ends.mode != 0;
+    if (batch == 2) {
+        if (ends) launch_stream_b<2, true>(a, cv, first, nparts, blocks, st);
+        else launch_stream_b<2, false>(a, cv, first, nparts, blocks, st);
+    } else {
+        if (ends) launch_stream_b<4, true>(a, cv, first, nparts, blocks, st);
+        else launch_stream_b<4, false>(a, cv, first, nparts, blocks, st);
+    }
     return hipGetLastError();
 }
 
@@ -1035,7 +1084,7 @@ template <typename Lookup, bool SCALED>
 __device__ void fallback_streamline(const float *__restrict__ pts, const int64_t *__restrict__ offsets, int64_t S,
                                     const Grid &g, float scale, const Lookup &lk, int32_t *__restrict__ C, uint32_t si,
                                     uint32_t sm, int64_t p, uint32_t *bmN, uint32_t *bmM, uint32_t *labels,
-                                    int *s_nlab) {
+                                    int *s_nlab, const EndLabels &ends) {
     const int64_t Ptot = offsets[S] > 0 ? offsets[S] : 0;
     // streamline containing point p: last s with offsets[s] <= p
     int64_t lo = 0, hi = S;  // answer in [0, S-1]
@@ -1048,8 +1097,16 @@ __device__ void fallback_streamline(const float *__restrict__ pts, const int64_t
     const int64_t b1 = clamp64(offsets[lo + 1], b0, Ptot);
     if (threadIdx.x == 0) *s_nlab = 0;
     __syncthreads();
+    // endpoint modes: the labels are the streamline's end labels
+    if (ends.mode != 0 && threadIdx.x == 0) {
+        const int ml = ends.last[lo], mf = ends.mode == 2 ? ends.first[lo] : -1;
+        int n = 0;
+        if (ml >= 0) atomicExch(&labels[n++], (uint32_t)ml);
+        if (mf >= 0 && mf != ml) atomicExch(&labels[n++], (uint32_t)mf);
+        *s_nlab = n;
+    }
     // distinct labels
-    for (int64_t j = b0 + threadIdx.x; j < b1; j += blockDim.x) {
+    for (int64_t j = b0 + threadIdx.x; ends.mode == 0 && j < b1; j += blockDim.x) {
         int ix, iy, iz, r, m;
         if (!voxelise<SCALED>(pts[3 * j], pts[3 * j + 1], pts[3 * j + 2], scale, g, ix, iy, iz)) continue;
         lk.get(ix, iy, iz, r, m);
@@ -1104,7 +1161,7 @@ __global__ void __launch_bounds__(kBlock) k_fallback(CountArgs a, Lookup lk, Fal
     const int64_t nq_c = nq < a.ovf.cap ? nq : a.ovf.cap;
     for (int64_t q = blockIdx.x; q < nq_c; q += gridDim.x)
         fallback_streamline<Lookup, SCALED>(a.pts, a.offsets, a.S, a.g, a.scale, lk, a.C, a.si, a.sm,
-                                            a.ovf.list[q] & kPointMask, bmN, bmM, labels, &s_nlab);
+                                            a.ovf.list[q] & kPointMask, bmN, bmM, labels, &s_nlab, a.ends);
 }
 
 // Batched fallback: the queue entry names its subject.
@@ -1122,8 +1179,89 @@ __global__ void __launch_bounds__(kBlock) k_fallback_batched(const StreamSubject
         subject = subject < 0 ? 0 : (subject >= nsub ? nsub - 1 : subject);
         const StreamSubject &sub = subs[subject];
         fallback_streamline<CompactLookup, true>(sub.pts, sub.offsets, sub.S, sub.g, sub.scale, CompactLookup{sub.cv},
-                                                 sub.C, sub.si, sub.sm, e & kPointMask, bmN, bmM, labels, &s_nlab);
+                                                 sub.C, sub.si, sub.sm, e & kPointMask, bmN, bmM, labels, &s_nlab,
+                                                 sub.ends);
     }
+}
+
+// ---------------------------------------------------------------------------------------------
+// endpoint modes: per-streamline end labels; Alg. 1's seed-to-endpoint count
+// ---------------------------------------------------------------------------------------------
+
+template <typename Lookup, bool SCALED>
+__device__ __forceinline__ void lookup_point(const float *p, float scale, const Grid &g, const Lookup &lk, int &r,
+                                             int &m) {
+    int ix, iy, iz;
+    r = m = -1;
+    if (voxelise<SCALED>(p[0], p[1], p[2], scale, g, ix, iy, iz)) lk.get(ix, iy, iz, r, m);
+}
+
+// last[s] = label of streamline s's last point, first[s] (mode 2) = label of its first point; -1
+// for an empty streamline or a point without a label.  One thread per streamline.
+template <typename Lookup, bool SCALED>
+__global__ void k_end_labels(CountArgs a, Lookup lk, int32_t mode, int32_t *__restrict__ last,
+                             int32_t *__restrict__ first) {
+    const int64_t Ptot = a.offsets[a.S] > 0 ? a.offsets[a.S] : 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < a.S; s += stride) {
+        const int64_t b0 = clamp64(a.offsets[s], 0, Ptot);
+        const int64_t b1 = clamp64(a.offsets[s + 1], b0, Ptot);
+        int r, ml = -1, mf = -1;
+        if (b1 > b0) {
+            lookup_point<Lookup, SCALED>(a.pts + 3 * (b1 - 1), a.scale, a.g, lk, r, ml);
+            if (mode == 2) lookup_point<Lookup, SCALED>(a.pts + 3 * b0, a.scale, a.g, lk, r, mf);
+        }
+        last[s] = ml;
+        if (mode == 2) first[s] = mf;
+    }
+}
+
+// C(row of the first point, label of the last point) += 1 per streamline (the seed is the first
+// point).  One thread per streamline.
+template <typename Lookup, bool SCALED>
+__global__ void k_count_seed_end(CountArgs a, Lookup lk) {
+    const int64_t Ptot = a.offsets[a.S] > 0 ? a.offsets[a.S] : 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < a.S; s += stride) {
+        const int64_t b0 = clamp64(a.offsets[s], 0, Ptot);
+        const int64_t b1 = clamp64(a.offsets[s + 1], b0, Ptot);
+        if (b1 <= b0) continue;
+        int r, m, r2, m2;
+        lookup_point<Lookup, SCALED>(a.pts + 3 * b0, a.scale, a.g, lk, r, m);
+        lookup_point<Lookup, SCALED>(a.pts + 3 * (b1 - 1), a.scale, a.g, lk, r2, m2);
+        if (r >= 0 && m2 >= 0) atomicAdd(a.C + (uint32_t)r * a.si + (uint32_t)m2 * a.sm, 1);
+    }
+}
+
+template <typename Lookup>
+static void launch_end_labels_l(const CountArgs &a, const Lookup &lk, int mode, int32_t *last, int32_t *first,
+                                int cus, hipStream_t st) {
+    const unsigned blocks = fill_blocks(a.S, cus);
+    if (a.scale != 1.0f) k_end_labels<Lookup, true><<<blocks, kBlock, 0, st>>>(a, lk, mode, last, first);
+    else k_end_labels<Lookup, false><<<blocks, kBlock, 0, st>>>(a, lk, mode, last, first);
+}
+
+hipError_t launch_end_labels(const CountArgs &a, const RasterVol *rv, const CompactVol *cv, int mode, int32_t *last,
+                             int32_t *first, int cus, hipStream_t st) {
+    if (a.S <= 0) return hipSuccess;
+    if (rv) launch_end_labels_l(a, RasterLookup{*rv}, mode, last, first, cus, st);
+    else launch_end_labels_l(a, CompactLookup{*cv}, mode, last, first, cus, st);
+    return hipGetLastError();
+}
+
+template <typename Lookup>
+static void launch_seed_end_l(const CountArgs &a, const Lookup &lk, int cus, hipStream_t st) {
+    const unsigned blocks = fill_blocks(a.S, cus);
+    if (a.scale != 1.0f) k_count_seed_end<Lookup, true><<<blocks, kBlock, 0, st>>>(a, lk);
+    else k_count_seed_end<Lookup, false><<<blocks, kBlock, 0, st>>>(a, lk);
+}
+
+hipError_t launch_count_seed_end(const CountArgs &a, const RasterVol *rv, const CompactVol *cv, int cus,
+                                 hipStream_t st) {
+    if (a.S <= 0) return hipSuccess;
+    if (rv) launch_seed_end_l(a, RasterLookup{*rv}, cus, st);
+    else launch_seed_end_l(a, CompactLookup{*cv}, cus, st);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------------------------
