@@ -56,6 +56,9 @@ def _load():
         lib.oracle_count_endpoint.argtypes = common + [ctypes.c_int, ctypes.c_void_p]
         lib.oracle_count_seed_endpoint.restype = ctypes.c_int
         lib.oracle_count_seed_endpoint.argtypes = common + [ctypes.c_void_p]
+        lib.oracle_parcellate.restype = ctypes.c_int
+        lib.oracle_parcellate.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         _lib = lib
     return _lib
 
@@ -151,3 +154,18 @@ def count_chunked(points, offsets, roi, lab, N: int, M: int, scale: float = 1.0,
         for f in futs:
             C += f.result()
     return C
+
+
+def parcellate(C):
+    """(label [N] int32, frac [N, M] float32, sums [N] int64) of a connectivity matrix (oracle_parcellate):
+    label = lowest argmax of each row or -1 without a positive entry; frac = row fractions taken in
+    double and rounded to float (0 for a row whose sum is not positive)."""
+    C = _np(C, np.int64)
+    N, M = C.shape
+    label = np.zeros(N, np.int32)
+    frac = np.zeros((N, M), np.float32)
+    sums = np.zeros(N, np.int64)
+    rc = _load().oracle_parcellate(_ptr(C), int(N), int(M), _ptr(label), _ptr(frac), _ptr(sums))
+    if rc != 0:
+        raise RuntimeError(f"oracle_parcellate failed ({rc})")
+    return label, frac, sums

@@ -239,3 +239,36 @@ int oracle_count_seed_endpoint(const float *points, const int64_t *offsets, int6
     }
     return 0;
 }
+
+/*
+ * Parcellation outputs of a connectivity matrix (Section 3, "Pie-glyphs"): the
+ * "single colour" map shows, for each source voxel (row i), the target region
+ * it is most strongly connected to, and a pie-glyph shows its relative
+ * connection strength to every region.
+ *   sums[i]    = sum over m of C[i][m]  (int64)
+ *   label[i]   = the smallest m with C[i][m] equal to the row's maximum, or -1
+ *                when no entry of the row is positive
+ *   frac[i][m] = C[i][m] / sums[i], the quotient of the two integers taken in
+ *                double and rounded to float; 0 when sums[i] <= 0
+ * C is [N][M] int64; label [N], frac [N][M] and sums [N] are written.
+ */
+int oracle_parcellate(const int64_t *C, int32_t N, int32_t M, int32_t *label, float *frac, int64_t *sums)
+{
+    if (N < 0 || M < 1 || !C || !label || !frac || !sums)
+        return -1;
+    for (int64_t i = 0; i < N; ++i) {
+        const int64_t *row = C + i * M;
+        int64_t total = 0;
+        int32_t best = -1;
+        for (int32_t m = 0; m < M; ++m) {
+            total += row[m];
+            if (row[m] > 0 && (best < 0 || row[m] > row[best]))
+                best = m;
+        }
+        sums[i] = total;
+        label[i] = best;
+        for (int32_t m = 0; m < M; ++m)
+            frac[i * M + m] = total > 0 ? (float)((double)row[m] / (double)total) : 0.0f;
+    }
+    return 0;
+}

@@ -54,6 +54,13 @@ MUTANTS = {
                                   "return (lab[lin] > 0 && lab[lin] < M) ? lab[lin] : -1;"),
     "row_at_drops_row_zero": ("return (roi[lin] >= 0 && roi[lin] < N) ? roi[lin] : -1;",
                               "return (roi[lin] > 0 && roi[lin] < N) ? roi[lin] : -1;"),
+    # parcellation outputs (oracle_parcellate)
+    "argmax_highest_on_tie": ("(best < 0 || row[m] > row[best])", "(best < 0 || row[m] >= row[best])"),
+    "empty_row_gets_label_zero": ("if (row[m] > 0 && (best < 0 ||", "if ((best < 0 ||"),
+    "fraction_in_float": ("(float)((double)row[m] / (double)total)", "((float)row[m] / (float)total)"),
+    "fraction_over_M": ("(float)((double)row[m] / (double)total)", "(float)((double)row[m] / (double)M)"),
+    "row_sum_skips_last": ("for (int32_t m = 0; m < M; ++m) {\n            total += row[m];",
+                           "for (int32_t m = 0; m < M - 1; ++m) {\n            total += row[m];"),
 }
 
 
@@ -73,6 +80,9 @@ def _build(src_text, tmp_path, name):
     lib.oracle_count_endpoint.argtypes = common + [ctypes.c_int, ctypes.c_void_p]
     lib.oracle_count_seed_endpoint.restype = ctypes.c_int
     lib.oracle_count_seed_endpoint.argtypes = common + [ctypes.c_void_p]
+    lib.oracle_parcellate.restype = ctypes.c_int
+    lib.oracle_parcellate.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_void_p]
     return lib
 
 
@@ -136,6 +146,40 @@ def _battery(lib):
             args = (w.points.numpy(), w.offsets.numpy(), w.roi.numpy(), w.lab.numpy(), w.N, w.M)
             if not np.array_equal(_count(lib, *args, mode=mode), brute.brute_count_ends(*args, mode=mode)):
                 failed.append(f"brute ends {seed} mode {mode}")
+    failed += _battery_parcellate(lib)
+    return failed
+
+
+def _battery_parcellate(lib):
+    """Hand-worked rows and exact-rational fractions (counts up to 2^26)."""
+    from tests import test_oracle_parcellate as tp
+    failed = []
+    ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)   # noqa: E731
+
+    def run(C):
+        C = np.ascontiguousarray(C, np.int64)
+        N, M = C.shape
+        lab, frac, sums = np.zeros(N, np.int32), np.zeros((N, M), np.float32), np.zeros(N, np.int64)
+        assert lib.oracle_parcellate(ptr(C), N, M, ptr(lab), ptr(frac), ptr(sums)) == 0
+        return lab, frac, sums
+
+    import json
+    from fractions import Fraction
+    g = json.load(open(tp.GOLDEN))
+    lab, frac, sums = run(np.array(g["C"]))
+    if not (np.array_equal(lab, g["labels"]) and np.array_equal(sums, g["sums"])):
+        failed.append("parcellation golden labels/sums")
+    for i, row in enumerate(g["fractions"]):
+        if not all(tp._close_to_rational(frac[i, m], Fraction(t)) for m, t in enumerate(row)):
+            failed.append(f"parcellation golden fractions row {i}")
+    rng = np.random.default_rng(3)
+    C = rng.integers(1 << 24, 1 << 26, size=(8, 5)).astype(np.int64)
+    lab, frac, sums = run(C)
+    for i in range(C.shape[0]):
+        s = int(C[i].sum())
+        if sums[i] != s or not all(tp._close_to_rational(frac[i, m], Fraction(int(C[i, m]), s)) for m in range(5)):
+            failed.append(f"parcellation large counts row {i}")
+            break
     return failed
 
 
