@@ -162,6 +162,21 @@ def main():
     log(f"step {ms_per_step:.3f} ms, {KERNEL_NAME} avg {k_ms:.3f} ms (min {min(kernel_ms):.3f}), "
         f"{achieved:.0f} GB/s algorithmic, pairs {pair_total}")
 
+    # the parcellation outputs of this C (single-colour labels, pie-glyph fractions, row sums)
+    pa = []
+    for i in range(6):
+        a, b = ev.create(), ev.create()
+        fastcod.parcellate(C, stream=stream, events=(a, b))
+        if i >= 2:
+            pa.append(ev.elapsed_ms(a, b))
+        ev.destroy(a)
+        ev.destroy(b)
+    p_ms = sum(pa) / len(pa)
+    p_bytes = 8 * w.N * w.M + 12 * w.N
+    parcellate = {"kernel": "k_parcellate", "ms": p_ms, "bytes": p_bytes, "GBps": p_bytes / (p_ms * 1e-3) / 1e9,
+                  "frac_of_peak": p_bytes / (p_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS}
+    log(f"parcellate: {p_ms * 1e3:.1f} us, {parcellate['GBps']:.0f} GB/s")
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -200,6 +215,7 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic_per_launch(),
                      "kernel_ms": k_ms, "algorithmic_bytes": alg_bytes},
         "cpu_baseline": cpu,
+        "parcellate": parcellate,
     }
     print(json.dumps(out), flush=True)
 

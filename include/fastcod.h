@@ -277,6 +277,22 @@ int fastcod_server_get_stats(fastcod_server *srv, fastcod_server_stats *out);
 int fastcod_server_destroy(fastcod_server *srv);
 
 /*
+ * Parcellation outputs of a connectivity matrix (Section 3, "Pie-glyphs": the single-colour map
+ * shows each source voxel's most strongly connected region; a pie-glyph shows its relative
+ * connectivity to every region).  For each row i of C:
+ *   label_out[i]   = the lowest m with C[i][m] equal to the row maximum; -1 when no entry of the
+ *                    row is positive
+ *   frac_out[i][m] = C[i][m] / sum_m C[i][m], the quotient of the two integers taken in double and
+ *                    rounded to float; 0 for a row whose sum is not positive
+ *   sums_out[i]    = sum_m C[i][m] (int64)
+ *   C [N][M] int32, label_out [N] int32, frac_out [N][M] float32, sums_out [N] int64: all device;
+ *   any output may be NULL.  Asynchronous on `stream`.
+ * Errors: EINVAL (N < 0, M < 1, N*M >= 2^31, C NULL with N > 0), EHIP.
+ */
+int fastcod_parcellate(const int32_t *C, int32_t N, int32_t M, int32_t *label_out, float *frac_out,
+                       int64_t *sums_out, void *stream);
+
+/*
  * Input check (synchronous): offsets[0] == 0 and nondecreasing, ROI values < N and label
  * values < M wherever they are >= 0.  Returns FASTCOD_OK or FASTCOD_ERANGE (detail in
  * fastcod_last_error).

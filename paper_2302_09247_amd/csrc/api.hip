@@ -663,6 +663,20 @@ int fastcod_validate(const int64_t *offsets, int64_t S, const int32_t *roi, cons
     return run_validate(ws, offsets, S, roi, lab, dims, N, M, st, dev);
 }
 
+int fastcod_parcellate(const int32_t *C, int32_t N, int32_t M, int32_t *label_out, float *frac_out,
+                       int64_t *sums_out, void *stream) {
+    last_error().clear();
+    if (N < 0 || M < 1) return fail(FASTCOD_EINVAL, "need N >= 0 and M >= 1");
+    if ((int64_t)N * M >= (int64_t(1) << 31)) return fail(FASTCOD_EINVAL, "N*M must be < 2^31");
+    if (N > 0 && !C) return fail(FASTCOD_EINVAL, "C is NULL");
+    int dev;
+    const int rc = current_device(&dev);
+    if (rc) return rc;
+    FC_HIP(fc::launch_parcellate(C, N, M, label_out, frac_out, sums_out, cu_count(dev),
+                                 static_cast<hipStream_t>(stream)));
+    return FASTCOD_OK;
+}
+
 int fastcod_release(void) {
     last_error().clear();
     std::lock_guard<std::mutex> g(g_ws_mu);

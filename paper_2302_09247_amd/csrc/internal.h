@@ -123,6 +123,9 @@ hipError_t launch_count_wave(const CountArgs &a, const RasterVol &rv, int blocks
 // looked up in the raster volume when rv is given, else in the compact volume cv
 hipError_t launch_end_labels(const CountArgs &a, const RasterVol *rv, const CompactVol *cv, int mode, int32_t *last,
                              int32_t *first, int cus, hipStream_t st);
+// parcellation outputs of C [N][M]: label [N], frac [N][M], sums [N] (each may be null)
+hipError_t launch_parcellate(const int32_t *C, int32_t N, int32_t M, int32_t *label, float *frac, int64_t *sums,
+                             int cus, hipStream_t st);
 // Alg. 1's count: C(row of the first point, label of the last point) += 1 for every streamline
 hipError_t launch_count_seed_end(const CountArgs &a, const RasterVol *rv, const CompactVol *cv, int cus,
                                  hipStream_t st);

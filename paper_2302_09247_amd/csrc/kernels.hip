@@ -1265,6 +1265,59 @@ hipError_t launch_count_seed_end(const CountArgs &a, const RasterVol *rv, const 
 }
 
 // ---------------------------------------------------------------------------------------------
+// parcellation outputs of C: one wavefront per row
+// ---------------------------------------------------------------------------------------------
+
+// label[i] = lowest m holding the row's maximum (-1 when no entry is positive), sums[i] = row sum,
+// frac[i][m] = C[i][m] / sums[i] taken in double and rounded to float (0 when the sum is not
+// positive).  Any output may be null.
+__global__ void __launch_bounds__(kBlock) k_parcellate(const int32_t *__restrict__ C, int32_t N, int32_t M,
+                                                       int32_t *__restrict__ label, float *__restrict__ frac,
+                                                       int64_t *__restrict__ sums) {
+    const int lane = lane_id();
+    const int64_t nw = (int64_t)gridDim.x * kWavesPerBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6); i < N; i += nw) {
+        const int32_t *row = C + i * (int64_t)M;
+        long long total = 0;
+        int best = 0, bidx = -1;   // largest positive value seen and its lowest column
+        for (int m = lane; m < M; m += kWave) {
+            const int v = row[m];
+            total += v;
+            if (v > best) {
+                best = v;
+                bidx = m;
+            }
+        }
+        for (int off = kWave / 2; off > 0; off >>= 1) {
+            total += __shfl_xor(total, off);
+            const int ob = __shfl_xor(best, off), oi = __shfl_xor(bidx, off);
+            if (ob > best || (ob == best && ob > 0 && oi < bidx)) {
+                best = ob;
+                bidx = oi;
+            }
+        }
+        if (lane == 0) {
+            if (label) label[i] = bidx;
+            if (sums) sums[i] = total;
+        }
+        if (frac) {
+            const double d = (double)total;
+            for (int m = lane; m < M; m += kWave)
+                frac[i * (int64_t)M + m] = total > 0 ? (float)((double)row[m] / d) : 0.0f;
+        }
+    }
+}
+
+hipError_t launch_parcellate(const int32_t *C, int32_t N, int32_t M, int32_t *label, float *frac, int64_t *sums,
+                             int cus, hipStream_t st) {
+    if (N <= 0) return hipSuccess;
+    int64_t blocks = ((int64_t)N + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (blocks > (int64_t)cus * 8) blocks = (int64_t)cus * 8;
+    k_parcellate<<<(unsigned)blocks, kBlock, 0, st>>>(C, N, M, label, frac, sums);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------------
 // batched form: work items, zero fill of every C, launchers
 // ---------------------------------------------------------------------------------------------
 

@@ -29,6 +29,7 @@ EXPORTS = (
     "fastcod_count_batched",
     "fastcod_server_create", "fastcod_server_add_volume", "fastcod_server_submit", "fastcod_server_wait",
     "fastcod_server_cancel", "fastcod_server_get_stats", "fastcod_server_destroy",
+    "fastcod_parcellate",
 )
 PLAN_TUNE = 1
 REQ_DEVICE_POINTS, REQ_DEVICE_C = 1, 2
@@ -118,12 +119,13 @@ def load(path: str = LIB_PATH):
     lib.fastcod_server_cancel.argtypes = [_vp, ctypes.c_uint64]
     lib.fastcod_server_get_stats.argtypes = [_vp, ctypes.POINTER(ServerStats)]
     lib.fastcod_server_destroy.argtypes = [_vp]
+    lib.fastcod_parcellate.argtypes = [_vp, i32, i32, _vp, _vp, _vp, _vp]
     for name in ("fastcod_count", "fastcod_count_ex", "fastcod_volume_create", "fastcod_volume_count",
                  "fastcod_volume_destroy", "fastcod_validate", "fastcod_release", "fastcod_plan_create",
                  "fastcod_plan_launch", "fastcod_plan_get_schedule", "fastcod_plan_destroy",
                  "fastcod_count_batched", "fastcod_server_create", "fastcod_server_add_volume",
                  "fastcod_server_submit", "fastcod_server_wait", "fastcod_server_cancel",
-                 "fastcod_server_get_stats", "fastcod_server_destroy"):
+                 "fastcod_server_get_stats", "fastcod_server_destroy", "fastcod_parcellate"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -264,6 +266,33 @@ class Volume:
             self.close()
         except Exception:
             pass
+
+
+def parcellate(C: torch.Tensor, labels: bool = True, fractions: bool = True, sums: bool = True, stream=None,
+               events=None):
+    """Parcellation outputs of C [N, M] int32 (fastcod_parcellate): (label [N] int32, frac [N, M]
+    float32, sums [N] int64), each None when not asked for.  ``events`` = (begin, end) hipEvents
+    recorded around the launch on ``stream``."""
+    lib = load()
+    _dev(C, torch.int32, "C")
+    if C.dim() != 2:
+        raise ValueError("C must be [N, M]")
+    N, M = int(C.shape[0]), int(C.shape[1])
+    lab = torch.empty(N, dtype=torch.int32, device=C.device) if labels else None
+    frac = torch.empty((N, M), dtype=torch.float32, device=C.device) if fractions else None
+    sm = torch.empty(N, dtype=torch.int64, device=C.device) if sums else None
+    ptr = lambda t: t.data_ptr() if t is not None and t.numel() else None   # noqa: E731
+    with torch.cuda.device(C.device):
+        st = _stream_ptr(stream)
+        hip = None
+        if events is not None:
+            hip = ctypes.CDLL("libamdhip64.so")
+            hip.hipEventRecord.argtypes = [_vp, _vp]
+            hip.hipEventRecord(events[0], st)
+        _check(lib.fastcod_parcellate(ptr(C), N, M, ptr(lab), ptr(frac), ptr(sm), st))
+        if hip is not None:
+            hip.hipEventRecord(events[1], st)
+    return lab, frac, sm
 
 
 def validate(offsets: torch.Tensor, roi: torch.Tensor, lab: torch.Tensor, N: int, M: int, stream=None) -> None:

@@ -121,3 +121,10 @@ def test_server_rejects_bad_arguments(lib):
     assert lib.fastcod_server_cancel(None, 1) == fastcod.EINVAL
     assert lib.fastcod_server_get_stats(None, None) == fastcod.EINVAL
     assert lib.fastcod_server_destroy(None) == fastcod.OK
+
+
+def test_parcellate_rejects_bad_arguments(lib):
+    assert lib.fastcod_parcellate(None, -1, 3, None, None, None, None) == fastcod.EINVAL
+    assert lib.fastcod_parcellate(None, 3, 0, None, None, None, None) == fastcod.EINVAL
+    assert lib.fastcod_parcellate(None, 1 << 20, 1 << 12, None, None, None, None) == fastcod.EINVAL
+    assert lib.fastcod_parcellate(None, 5, 3, None, None, None, None) == fastcod.EINVAL
