@@ -56,6 +56,8 @@ def _load():
         lib.oracle_count_endpoint.argtypes = common + [ctypes.c_int, ctypes.c_void_p]
         lib.oracle_count_seed_endpoint.restype = ctypes.c_int
         lib.oracle_count_seed_endpoint.argtypes = common + [ctypes.c_void_p]
+        lib.oracle_count_upsampled.restype = ctypes.c_int
+        lib.oracle_count_upsampled.argtypes = common + [ctypes.c_int32, ctypes.c_void_p]
         lib.oracle_parcellate.restype = ctypes.c_int
         lib.oracle_parcellate.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
@@ -86,7 +88,8 @@ def voxel(p, dims, scale: float = 1.0) -> int:
 MODE_PASSTHROUGH, MODE_END, MODE_BOTH_ENDS, MODE_SEED_END = 0, 1, 2, 3
 
 
-def count(points, offsets, roi, lab, N: int, M: int, scale: float = 1.0, mode: int = MODE_PASSTHROUGH) -> np.ndarray:
+def count(points, offsets, roi, lab, N: int, M: int, scale: float = 1.0, mode: int = MODE_PASSTHROUGH,
+          upsample: int = 1) -> np.ndarray:
     """C[N, M] (int64).
 
     points [P,3] float32, offsets [S+1] int64, roi/lab [Z,Y,X] int32.
@@ -95,6 +98,8 @@ def count(points, offsets, roi, lab, N: int, M: int, scale: float = 1.0, mode: i
     mode 2: rows passed through x labels of the first and last points;
     mode 3: one count per streamline at (row of its first point, label of its last point)
             (oracle_count_seed_endpoint).
+    upsample u > 1 (pass-through only): u - 1 evenly spaced points inserted between neighbouring
+            points before counting (oracle_count_upsampled).
     """
     pts = _np(points, np.float32).reshape(-1, 3)
     off = _np(offsets, np.int64).reshape(-1)
@@ -109,7 +114,11 @@ def count(points, offsets, roi, lab, N: int, M: int, scale: float = 1.0, mode: i
     C = np.zeros((N, M), dtype=np.int64)
     lib = _load()
     args = (_ptr(pts), _ptr(off), S, _ptr(roi), _ptr(lab), _ptr(dims), int(N), int(M), float(np.float32(scale)))
-    if mode == MODE_PASSTHROUGH:
+    if upsample != 1:
+        if mode != MODE_PASSTHROUGH or upsample < 1:
+            raise ValueError("upsampling is defined for the pass-through mode, u >= 1")
+        rc = lib.oracle_count_upsampled(*args, int(upsample), _ptr(C))
+    elif mode == MODE_PASSTHROUGH:
         rc = lib.oracle_count(*args, _ptr(C))
     elif mode in (MODE_END, MODE_BOTH_ENDS):
         rc = lib.oracle_count_endpoint(*args, 1 if mode == MODE_BOTH_ENDS else 0, _ptr(C))
@@ -123,7 +132,8 @@ def count(points, offsets, roi, lab, N: int, M: int, scale: float = 1.0, mode: i
 
 
 def count_chunked(points, offsets, roi, lab, N: int, M: int, scale: float = 1.0,
-                  streamlines_per_chunk: int = 1 << 18, workers: int = 1, mode: int = MODE_PASSTHROUGH) -> np.ndarray:
+                  streamlines_per_chunk: int = 1 << 18, workers: int = 1, mode: int = MODE_PASSTHROUGH,
+                  upsample: int = 1) -> np.ndarray:
     """The same matrix, computed as a sum of ``count`` over streamline ranges.
 
     C is a sum over streamlines, so it is additive over any split of the
@@ -144,13 +154,14 @@ def count_chunked(points, offsets, roi, lab, N: int, M: int, scale: float = 1.0,
         jobs.append((pts[pa:pb], off[a:b + 1] - off[a]))
     if workers <= 1:
         for p, o in jobs:
-            C += count(p, o, roi, lab, N, M, scale, mode)
+            C += count(p, o, roi, lab, N, M, scale, mode, upsample)
         return C
     import concurrent.futures as cf
     roi_np, lab_np = _np(roi, np.int32), _np(lab, np.int32)
     # ctypes releases the GIL during the call, so threads run the C oracle in parallel.
     with cf.ThreadPoolExecutor(max_workers=workers) as ex:
-        futs = [ex.submit(count, _np(p, np.float32), o, roi_np, lab_np, N, M, scale, mode) for p, o in jobs]
+        futs = [ex.submit(count, _np(p, np.float32), o, roi_np, lab_np, N, M, scale, mode, upsample)
+                for p, o in jobs]
         for f in futs:
             C += f.result()
     return C

@@ -74,3 +74,29 @@ def brute_count_ends(points, offsets, roi, lab, N: int, M: int, scale: float = 1
         g[ends[(ends >= 0) & (ends < M)]] = 1
         C += np.outer(h, g)
     return C
+
+
+def brute_upsample(points, offsets, scale: float, u: int):
+    """Scaled, upsampled streamlines as (points [P', 3] float32, offsets): u - 1 points
+    q_k + a_t (q_{k+1} - q_k), a_t = t/u, inserted between neighbours, every step a float32
+    operation of numpy (no fused multiply-add).  Count the result with scale 1."""
+    points = np.asarray(points, dtype=np.float32).reshape(-1, 3)
+    offsets = np.asarray(offsets, dtype=np.int64)
+    out, off = [], [0]
+    err = np.seterr(invalid="ignore", over="ignore")   # NaN / inf coordinates stay NaN / inf
+    for s in range(offsets.shape[0] - 1):
+        q = points[offsets[s]:offsets[s + 1]] * np.float32(scale)
+        seq = []
+        for k in range(q.shape[0]):
+            seq.append(q[k])
+            if k + 1 < q.shape[0]:
+                d = q[k + 1] - q[k]
+                for t in range(1, u):
+                    a = np.float32(t) / np.float32(u)
+                    seq.append(q[k] + a * d)
+        arr = np.array(seq, dtype=np.float32).reshape(-1, 3)
+        out.append(arr)
+        off.append(off[-1] + arr.shape[0])
+    np.seterr(**err)
+    pts = np.concatenate(out) if out else np.zeros((0, 3), np.float32)
+    return pts, np.array(off, dtype=np.int64)

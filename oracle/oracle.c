@@ -272,3 +272,88 @@ int oracle_parcellate(const int64_t *C, int32_t N, int32_t M, int32_t *label, fl
     }
     return 0;
 }
+
+/*
+ * Pass-through matrix of upsampled streamlines (Section 3, "Super-resolving
+ * connectivity features": evenly spaced points are inserted between every two
+ * neighbouring points of a streamline, so that the spacing falls below half a
+ * voxel of the grid where connectivity is computed).  With the scaled points
+ * q_k = fl32(p_k * s) and a factor u >= 1, a streamline is counted as
+ *   q_1, y_{1,1} .. y_{1,u-1}, q_2, y_{2,1} .. y_{2,u-1}, q_3, ..., q_T
+ *   y_{k,t} = fl32(q_k + fl32(a_t * fl32(q_{k+1} - q_k))),   a_t = fl32(t / u),
+ * every operation rounded to float on its own (no fused multiply-add), per
+ * coordinate.  Then I_l, M_l and C exactly as in oracle_count; u = 1 is
+ * oracle_count itself.
+ */
+int oracle_count_upsampled(const float *points, const int64_t *offsets, int64_t S,
+                           const int32_t *roi, const int32_t *lab, const int32_t dims[3],
+                           int32_t N, int32_t M, float scale, int32_t u, int64_t *C)
+{
+    if (S < 0 || N < 1 || M < 1 || u < 1 || !C || !dims)
+        return -1;
+    memset(C, 0, sizeof(int64_t) * (size_t)N * (size_t)M);
+    int64_t cap = 0;
+    float *D = NULL;                        /* the upsampled streamline, scaled, [len][3] */
+    int32_t *I = NULL, *L = NULL;
+    for (int64_t s = 0; s < S; ++s) {
+        int64_t a = offsets[s], b = offsets[s + 1];
+        int64_t T = b - a;
+        if (T <= 0)
+            continue;
+        int64_t len = T + (T - 1) * (int64_t)(u - 1);
+        if (len > cap) {
+            free(D);
+            free(I);
+            free(L);
+            cap = len;
+            D = (float *)malloc(sizeof(float) * 3 * (size_t)cap);
+            I = (int32_t *)malloc(sizeof(int32_t) * (size_t)cap);
+            L = (int32_t *)malloc(sizeof(int32_t) * (size_t)cap);
+            if (!D || !I || !L) {
+                free(D);
+                free(I);
+                free(L);
+                return -1;
+            }
+        }
+        int64_t n = 0;
+        for (int64_t j = a; j < b; ++j) {
+            for (int k = 0; k < 3; ++k)
+                D[3 * n + k] = points[3 * j + k] * scale;              /* q_j */
+            ++n;
+            if (j + 1 == b)
+                break;                                              /* nothing after the last point */
+            for (int32_t t = 1; t < u; ++t) {
+                float at = (float)t / (float)u;                     /* a_t = fl32(t / u) */
+                for (int k = 0; k < 3; ++k) {
+                    float qk = points[3 * j + k] * scale;
+                    float qn = points[3 * (j + 1) + k] * scale;
+                    float d = qn - qk;
+                    float e = at * d;
+                    D[3 * n + k] = qk + e;
+                }
+                ++n;
+            }
+        }
+        /* the upsampled points are already scaled: look them up with scale 1 (exact) */
+        int64_t nI = 0, nL = 0;
+        for (int64_t j = 0; j < n; ++j) {
+            int64_t lin = oracle_voxel(D[3 * j], D[3 * j + 1], D[3 * j + 2], 1.0f, dims);
+            if (lin < 0)
+                continue;
+            if (roi[lin] >= 0 && roi[lin] < N)
+                I[nI++] = roi[lin];
+            if (lab[lin] >= 0 && lab[lin] < M)
+                L[nL++] = lab[lin];
+        }
+        nI = sort_unique(I, nI);
+        nL = sort_unique(L, nL);
+        for (int64_t x = 0; x < nI; ++x)
+            for (int64_t y = 0; y < nL; ++y)
+                C[(int64_t)I[x] * M + L[y]] += 1;
+    }
+    free(D);
+    free(I);
+    free(L);
+    return 0;
+}

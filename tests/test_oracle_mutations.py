@@ -61,6 +61,13 @@ MUTANTS = {
     "fraction_over_M": ("(float)((double)row[m] / (double)total)", "(float)((double)row[m] / (double)M)"),
     "row_sum_skips_last": ("for (int32_t m = 0; m < M; ++m) {\n            total += row[m];",
                            "for (int32_t m = 0; m < M - 1; ++m) {\n            total += row[m];"),
+    # upsampling (oracle_count_upsampled)
+    "upsample_wrong_spacing": ("float at = (float)t / (float)u;", "float at = (float)t / (float)(u + 1);"),
+    "upsample_inserts_nothing": ("for (int32_t t = 1; t < u; ++t) {", "for (int32_t t = 1; t < 1; ++t) {"),
+    "upsample_unscaled_neighbours": ("float qk = points[3 * j + k] * scale;\n                    float qn = points[3 * (j + 1) + k] * scale;",
+                                     "float qk = points[3 * j + k];\n                    float qn = points[3 * (j + 1) + k];"),
+    "upsample_drops_last_point": ("D[3 * n + k] = points[3 * j + k] * scale;              /* q_j */\n            ++n;\n            if (j + 1 == b)\n                break;",
+                                  "D[3 * n + k] = points[3 * j + k] * scale;              /* q_j */\n            if (j + 1 == b)\n                break;\n            ++n;"),
 }
 
 
@@ -83,6 +90,8 @@ def _build(src_text, tmp_path, name):
     lib.oracle_parcellate.restype = ctypes.c_int
     lib.oracle_parcellate.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.c_void_p]
+    lib.oracle_count_upsampled.restype = ctypes.c_int
+    lib.oracle_count_upsampled.argtypes = common + [ctypes.c_int32, ctypes.c_void_p]
     return lib
 
 
@@ -99,6 +108,8 @@ def _count(lib, points, offsets, roi, lab, N, M, scale=1.0, mode=0):
         rc = lib.oracle_count(*args, ptr(C))
     elif mode in (1, 2):
         rc = lib.oracle_count_endpoint(*args, mode - 1, ptr(C))
+    elif mode >= 10:   # upsampled pass-through, u = mode - 10
+        rc = lib.oracle_count_upsampled(*args, mode - 10, ptr(C))
     else:
         rc = lib.oracle_count_seed_endpoint(*args, ptr(C))
     assert rc == 0
@@ -147,6 +158,19 @@ def _battery(lib):
             if not np.array_equal(_count(lib, *args, mode=mode), brute.brute_count_ends(*args, mode=mode)):
                 failed.append(f"brute ends {seed} mode {mode}")
     failed += _battery_parcellate(lib)
+    # upsampling: the hand-worked case and the numpy densification
+    g = _cases.load_golden("toy_upsample.json")
+    for u in (2, 3, 4):
+        if not np.array_equal(_count(lib, g["points"], g["offsets"], g["roi"], g["lab"], g["N"], g["M"], mode=10 + u),
+                              g[f"C_u{u}"]):
+            failed.append(f"golden upsample {u}")
+    for seed in range(3):
+        w = synth.random_small(seed, N=(None if seed % 2 else 6), bad_values=True)
+        pts, off = brute.brute_upsample(w.points.numpy(), w.offsets.numpy(), 1.7857143, 3)
+        want = brute.brute_count(pts, off, w.roi.numpy(), w.lab.numpy(), w.N, w.M)
+        args = (w.points.numpy(), w.offsets.numpy(), w.roi.numpy(), w.lab.numpy(), w.N, w.M)
+        if not np.array_equal(_count(lib, *args, scale=1.7857143, mode=13), want):
+            failed.append(f"brute upsample {seed}")
     return failed
 
 
