@@ -88,7 +88,7 @@ def main():
     ap.add_argument("--cpu-sample-streamlines", type=int, default=1_500_000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (for rocprofv3 counter scaling)")
-    ap.add_argument("--form", choices=("plain", "batched", "served"), default="plain",
+    ap.add_argument("--form", choices=("plain", "batched", "served", "sr"), default="plain",
                     help="plain: the 0.7 mm subject (default); batched: many subjects in one graph launch; "
                          "served: Poisson request stream")
     ap.add_argument("--subjects", type=int, default=32)
@@ -121,6 +121,8 @@ def main():
         return bench_batched(args)
     if args.form == "served":
         return bench_served(args)
+    if args.form == "sr":
+        return bench_sr(args)
     t0 = time.time()
     vols = synth.volumes_07mm()
     log(f"volumes: N={vols.N} M={vols.M} dims={vols.dims} ({time.time() - t0:.1f}s)")
@@ -288,6 +290,48 @@ def bench_batched(args):
         "plain_value": P / (plain_ms * 1e-3), "plain_ms": plain_ms,
         "batched_over_plain": plain_ms / batched_ms, "bit_identical": identical,
     }
+    print(json.dumps(out), flush=True)
+
+
+def bench_sr(args):
+    """Super-resolution job (Section 3): 1.25 mm streamlines (S = 1M, 0.5-voxel steps) scaled by
+    fl32(1.25/0.7) onto the 0.7 mm volumes, counted as given (u = 1) and with one point inserted
+    between neighbours (u = 2, 0.45-voxel spacing on the fine grid).  HBM bytes per point are the
+    same 12 for both: the inserted points never leave registers."""
+    import torch
+    from paper_2302_09247_amd import fastcod, synth
+    w = synth.make_sr(S=1_000_000, device="cuda")
+    torch.cuda.synchronize()
+    ev = HipEvents()
+    stream = torch.cuda.current_stream()
+    C = torch.empty((w.N, w.M), dtype=torch.int32, device="cuda")
+    rows = []
+    for u in (1, 2):
+        for _ in range(args.warmup):
+            fastcod.count(w.points, w.offsets, w.roi, w.lab, w.N, w.M, scale=w.scale, upsample=u, out=C, stream=stream)
+        ks = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            a, b = ev.create(), ev.create()
+            fastcod.count(w.points, w.offsets, w.roi, w.lab, w.N, w.M, scale=w.scale, upsample=u, out=C,
+                          stream=stream, events=(a, b))
+            ks.append((a, b))
+        torch.cuda.synchronize()
+        step = (time.perf_counter() - t0) / args.steps
+        kms = sum(ev.elapsed_ms(a, b) for a, b in ks) / len(ks)
+        pairs = int(C.sum(dtype=torch.int64).item())
+        alg = 12 * w.P + 8 * (w.S + 1) + 4 * pairs
+        rows.append({"upsample": u, "ms_per_step": step * 1e3, "kernel_ms": kms, "points_per_s": w.P / step,
+                     "counted_points_per_s": (w.P + (u - 1) * (w.P - w.S)) / step, "pairs": pairs,
+                     "kernel_GBps": alg / (kms * 1e-3) / 1e9})
+        log(f"u={u}: step {step * 1e3:.3f} ms, kernel {kms:.3f} ms, {rows[-1]['kernel_GBps']:.0f} GB/s, pairs {pairs}")
+    out = {"metric": "super-resolution job streamline points/s (1.25 mm streamlines on the 0.7 mm grid)",
+           "value": rows[-1]["points_per_s"], "unit": "points/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": rows[-1]["ms_per_step"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "SR job: S=1M 1.25 mm walks x fl32(1.25/0.7) on 260x311x260, N=45.8k, M=180",
+                      "S": w.S, "P": w.P}, "rows": rows}
     print(json.dumps(out), flush=True)
 
 

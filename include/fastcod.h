@@ -72,7 +72,10 @@ extern "C" {
 
 typedef struct fastcod_opts {
     float scale;        /* coordinate scale s applied before voxelisation; 1.0f = none              */
-    int32_t upsample;   /* must be 1 (points are used as given)                                     */
+    int32_t upsample;   /* u in 1..4: u - 1 evenly spaced points inserted between neighbouring points */
+                        /* before counting (Section 3, super-resolving connectivity features):     */
+                        /* y = fl32(q_k + fl32(a_t * fl32(q_k+1 - q_k))), a_t = fl32(t/u), on the    */
+                        /* scaled points q, no FMA; u > 1 needs FASTCOD_MODE_PASSTHROUGH; 1 = none   */
     uint32_t flags;     /* FASTCOD_ACCUMULATE | FASTCOD_VALIDATE                                    */
     int32_t variant;    /* FASTCOD_VARIANT_*                                                        */
     void *event_begin;  /* optional hipEvent_t, recorded on `stream` just before the counting kernel */

@@ -47,7 +47,9 @@ int check_stream_args(const float *points, const int64_t *offsets, int64_t S, in
     if (!offsets) return fail(FASTCOD_EINVAL, "offsets is NULL");
     if (S > 0 && !points) return fail(FASTCOD_EINVAL, "points is NULL");
     if (!C) return fail(FASTCOD_EINVAL, "C_out is NULL");
-    if (o.upsample != 1) return fail(FASTCOD_EINVAL, "upsample must be 1");
+    if (o.upsample < 1 || o.upsample > 4) return fail(FASTCOD_EINVAL, "upsample must be 1, 2, 3 or 4");
+    if (o.upsample > 1 && o.mode != FASTCOD_MODE_PASSTHROUGH)
+        return fail(FASTCOD_EINVAL, "upsampling is available for the pass-through mode only");
     if (!(o.scale == o.scale) || o.scale <= 0.0f || isinf(o.scale)) return fail(FASTCOD_EINVAL, "scale must be finite and > 0");
     if (o.variant < FASTCOD_VARIANT_AUTO || o.variant > FASTCOD_VARIANT_STREAM) return fail(FASTCOD_EINVAL, "unknown variant");
     if (o.batch != 0 && o.batch != 2 && o.batch != 4) return fail(FASTCOD_EINVAL, "batch must be 0, 2 or 4");
@@ -139,6 +141,7 @@ int enqueue_count(Workspace &ws, int dev, const float *points, const int64_t *of
         a.sm = (uint32_t)N;
         FC_HIP(fc::launch_fill_i32(a.C, (int64_t)N * M, 0, cus, st));
     }
+    a.up = o.upsample;
     a.ends = fc::EndLabels{0, nullptr, nullptr};
     if (o.mode == FASTCOD_MODE_END || o.mode == FASTCOD_MODE_BOTH_ENDS) {
         const int nl = o.mode == FASTCOD_MODE_BOTH_ENDS ? 2 : 1;
@@ -160,7 +163,7 @@ int enqueue_count(Workspace &ws, int dev, const float *points, const int64_t *of
     if (cv) {
         const int batch = o.batch == 2 ? 2 : 4;
         int per_cu = fc::count_stream_blocks_per_cu(o.scale != 1.0f, cv->packed != 0, batch, a.ends.mode != 0,
-                                                    4 * (size_t)cv->ncoarse_words);
+                                                    a.up, 4 * (size_t)cv->ncoarse_words);
         if (o.blocks_per_cu > 0 && o.blocks_per_cu < per_cu) per_cu = o.blocks_per_cu;
         const int64_t blocks = (int64_t)cus * per_cu;
         const int64_t nparts = blocks * fc::kWavesPerBlock * kRangesPerWave;
@@ -399,6 +402,7 @@ int plan_build(const fastcod_subject *subjects, int32_t n, uint32_t flags, const
         ss.si = (uint32_t)u.M;
         ss.sm = 1u;
         ss.ends = fc::EndLabels{0, nullptr, nullptr};
+        ss.up = 1;
         pl->subs.push_back(ss);
         pl->sizes.push_back((int64_t)u.N * u.M);
         total_s += u.n_streamlines;

@@ -84,6 +84,7 @@ struct CountArgs {
     uint32_t si, sm;
     Overflow ovf;
     EndLabels ends;
+    int32_t up;   // upsampling factor: up - 1 points inserted between neighbouring points (1 = none)
 };
 
 // Everything the flat-stream kernels need about one subject (also the device-side descriptor of
@@ -100,6 +101,7 @@ struct StreamSubject {
     int32_t *C;
     uint32_t si, sm;
     EndLabels ends;
+    int32_t up;   // upsampling factor (1 = none)
 };
 
 // ---- launchers (kernels.hip); every launcher returns the hipError_t of its launch ----
@@ -116,7 +118,7 @@ hipError_t launch_compact_build(const int32_t *roi, const int32_t *lab, Grid g, 
 hipError_t launch_partition(const int64_t *offsets, int64_t S, int64_t nparts, int32_t *first, int cus,
                             hipStream_t st);
 // resident 256-thread workgroups per CU of the flat-stream kernel
-int count_stream_blocks_per_cu(bool scaled, bool packed, int batch, bool ends, size_t dyn_lds);
+int count_stream_blocks_per_cu(bool scaled, bool packed, int batch, bool ends, int up, size_t dyn_lds);
 
 hipError_t launch_count_wave(const CountArgs &a, const RasterVol &rv, int blocks, hipStream_t st);
 // endpoint modes: last[s] (and, mode 2, first[s]) = label of streamline s's last (first) point,

@@ -582,6 +582,8 @@ hipError_t launch_partition(const int64_t *offsets, int64_t S, int64_t nparts, i
 // count, variant 1: one wavefront per streamline, raster lookups
 // ---------------------------------------------------------------------------------------------
 
+constexpr int kMaxUp = 4;   // largest upsampling factor
+
 template <bool SCALED>
 __global__ void __launch_bounds__(kBlock) k_count_wave(CountArgs a, RasterVol rv) {
     __shared__ uint32_t s_tab[kWavesPerBlock * kSetCap];
@@ -593,35 +595,85 @@ __global__ void __launch_bounds__(kBlock) k_count_wave(CountArgs a, RasterVol rv
     const int64_t Ptot = a.offsets[a.S] > 0 ? a.offsets[a.S] : 0;
     const int64_t nw = (int64_t)gridDim.x * kWavesPerBlock;
     const bool endmode = a.ends.mode != 0;   // endpoint modes: labels come from a.ends at the close
+    const int up = a.up < 1 ? 1 : (a.up > kMaxUp ? kMaxUp : a.up);   // upsampling factor
     for (int64_t s = (int64_t)blockIdx.x * kWavesPerBlock + wv; s < a.S; s += nw) {
         const int64_t b0 = clamp64(a.offsets[s], 0, Ptot);
         const int64_t b1 = clamp64(a.offsets[s + 1], b0, Ptot);
         int last_r = -1, last_m = -1;
         for (int64_t w0 = b0; w0 < b1; w0 += kWave) {
             const int64_t p = w0 + lane;
-            int r = -1, m = -1;
-            if (p < b1) {
-                const float x = load_stream(a.pts + 3 * p), y = load_stream(a.pts + 3 * p + 1),
-                            z = load_stream(a.pts + 3 * p + 2);
-                int ix, iy, iz;
-                if (voxelise<SCALED>(x, y, z, a.scale, a.g, ix, iy, iz)) raster_get(rv, ix, iy, iz, r, m);
-                if (endmode) m = -1;
+            const bool here = p < b1, next = p + 1 < b1;
+            // the lane's scaled point and (upsampling) the step to the next one
+            float qx = 0.f, qy = 0.f, qz = 0.f, dx = 0.f, dy = 0.f, dz = 0.f;
+            if (here) {
+                qx = load_stream(a.pts + 3 * p);
+                qy = load_stream(a.pts + 3 * p + 1);
+                qz = load_stream(a.pts + 3 * p + 2);
+                if (SCALED) {
+                    qx = __fmul_rn(qx, a.scale);
+                    qy = __fmul_rn(qy, a.scale);
+                    qz = __fmul_rn(qz, a.scale);
+                }
+                if (up > 1 && next) {
+                    float ux = a.pts[3 * p + 3], uy = a.pts[3 * p + 4], uz = a.pts[3 * p + 5];
+                    if (SCALED) {
+                        ux = __fmul_rn(ux, a.scale);
+                        uy = __fmul_rn(uy, a.scale);
+                        uz = __fmul_rn(uz, a.scale);
+                    }
+                    dx = __fsub_rn(ux, qx);
+                    dy = __fsub_rn(uy, qy);
+                    dz = __fsub_rn(uz, qz);
+                }
             }
-            // drop a hit equal to the previous point's (same voxel row/label), then the LDS set
-            int rp = __shfl_up(r, 1), mp = __shfl_up(m, 1);
+            // sub-point t: the point itself (t = 0) or a_t of the way to the next one
+            int rr[kMaxUp], mm[kMaxUp];
+#pragma unroll
+            for (int t = 0; t < kMaxUp; ++t) {
+                rr[t] = mm[t] = -1;
+                if (t < up && here && (t == 0 || next)) {
+                    float x = qx, y = qy, z = qz;
+                    if (t > 0) {
+                        const float at = (float)((double)t / (double)up);
+                        x = __fadd_rn(qx, __fmul_rn(at, dx));
+                        y = __fadd_rn(qy, __fmul_rn(at, dy));
+                        z = __fadd_rn(qz, __fmul_rn(at, dz));
+                    }
+                    int ix, iy, iz, r, m;
+                    if (voxelise<false>(x, y, z, 1.0f, a.g, ix, iy, iz)) {
+                        raster_get(rv, ix, iy, iz, r, m);
+                        rr[t] = r;
+                        mm[t] = endmode ? -1 : m;
+                    }
+                }
+            }
+            int rl = rr[0], ml = mm[0];   // the lane's last sub-point
+#pragma unroll
+            for (int t = 1; t < kMaxUp; ++t)
+                if (t == up - 1) {
+                    rl = rr[t];
+                    ml = mm[t];
+                }
+            // drop a hit equal to the hit before it in streamline order, then the LDS set
+            int rp = __shfl_up(rl, 1), mp = __shfl_up(ml, 1);
             if (lane == 0) {
                 rp = last_r;
                 mp = last_m;
             }
-            const uint64_t candR = __ballot(r >= 0 && r != rp);
-            const uint64_t candM = __ballot(m >= 0 && m != mp);
-            last_r = __shfl(r, kWave - 1);
-            last_m = __shfl(m, kWave - 1);
-            if ((candR | candM) == 0ull || set.skip) continue;
-            if (!set.add(candR, r, candM, m)) {
-                push_overflow(a.ovf, b0);
-                set.clear_entries();
-                set.skip = true;
+            last_r = __shfl(rl, kWave - 1);
+            last_m = __shfl(ml, kWave - 1);
+#pragma unroll
+            for (int t = 0; t < kMaxUp; ++t) {
+                if (t >= up) break;
+                const int pr = t == 0 ? rp : rr[t > 0 ? t - 1 : 0], pm = t == 0 ? mp : mm[t > 0 ? t - 1 : 0];
+                const uint64_t candR = __ballot(rr[t] >= 0 && rr[t] != pr);
+                const uint64_t candM = __ballot(mm[t] >= 0 && mm[t] != pm);
+                if ((candR | candM) == 0ull || set.skip) continue;
+                if (!set.add(candR, rr[t], candM, mm[t])) {
+                    push_overflow(a.ovf, b0);
+                    set.clear_entries();
+                    set.skip = true;
+                }
             }
         }
         if (endmode && !set.skip && set.nI > 0) {
@@ -691,9 +743,10 @@ using StreamSet = DeferredSet<kRCap, kLCap, kTCap>;
 // Counts streamlines [s0, s1) of one subject (whole streamlines only) into sub.C through `sink`.
 // `coarse` is the subject's coarse occupancy map in LDS.  PACKED: 0/1 = code width known at compile
 // time, 2 = read from cv.packed.
-template <bool SCALED, int PACKED, int kBatch, bool kEnds>
+template <bool SCALED, int PACKED, int kBatch, bool kEnds, int kUp>
 __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, int64_t s0, int64_t s1, int32_t subject,
                              const Overflow &ovf, StreamSet &set, BufferedSink &sink) {
+    constexpr int kV = kBatch * kUp;   // lookups per batch: kUp sub-points of each of kBatch windows
     const int lane = lane_id();
     const CompactVol &cv = sub.cv;
     const int64_t S = sub.S;
@@ -713,6 +766,12 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
     // endpoint modes (kEnds instantiations only): no point contributes its label; each closing
     // streamline gets its end labels
     const bool endmode = kEnds && uniform32(sub.ends.mode) != 0;
+    // upsampling (kUp > 1 instantiations): sub-point t = 1 .. up-1 of a point lies a_t = fl32(t/up)
+    // of the way to the next point of its streamline, in scaled coordinates
+    const int up = kUp > 1 ? uniform32(sub.up) : 1;
+    float at[kUp];
+#pragma unroll
+    for (int t = 0; t < kUp; ++t) at[t] = (float)((double)t / (double)up);
     // Starts of streamlines s0+1 .. s1-1, 64 at a time, one per lane (P1 = "no more starts");
     // k0 of them are consumed and `nxt` (uniform) is the next unconsumed start.
     int64_t vb = s0 + 1;
@@ -772,8 +831,11 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
 
     // one register set of points: batch k+1 is issued into it once batch k's gathers have
     // returned, and streams in while batch k is folded into the set
-    float ax[kBatch], ay[kBatch], az[kBatch];
-    auto load_batch = [&](int64_t w, float (&x)[kBatch], float (&y)[kBatch], float (&z)[kBatch]) {
+    // kUp > 1: each lane also holds the next point (the same load one point further on: it hits
+    // the lines the window itself brings in)
+    constexpr int kNext = kUp > 1 ? kBatch : 1;
+    float ax[kBatch], ay[kBatch], az[kBatch], nx[kNext], ny[kNext], nz[kNext];
+    auto load_batch = [&](int64_t w) {
         if (12 * (w - pbase) + 12 * BW > (int64_t)0xF0000000ll) {
             pbase = w;
             rp = make_rsrc(sub.pts + 3 * pbase, 12ull * (uint64_t)(Ptot - pbase));
@@ -782,99 +844,135 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
 #pragma unroll
         for (int b = 0; b < kBatch; ++b) {
             const auto v = __builtin_amdgcn_raw_buffer_load_b96(rp, lane12, so + 768u * b, kAuxStream);
-            x[b] = __uint_as_float(v[0]);
-            y[b] = __uint_as_float(v[1]);
-            z[b] = __uint_as_float(v[2]);
+            ax[b] = __uint_as_float(v[0]);
+            ay[b] = __uint_as_float(v[1]);
+            az[b] = __uint_as_float(v[2]);
+        }
+        if (kUp > 1) {
+#pragma unroll
+            for (int b = 0; b < kBatch; ++b) {
+                const auto v = __builtin_amdgcn_raw_buffer_load_b96(rp, lane12 + 12u, so + 768u * b, kAuxCached);
+                nx[b] = __uint_as_float(v[0]);
+                ny[b] = __uint_as_float(v[1]);
+                nz[b] = __uint_as_float(v[2]);
+            }
         }
     };
-    auto run_batch = [&](int64_t w0, float (&px)[kBatch], float (&py)[kBatch], float (&pz)[kBatch]) {
+    auto run_batch = [&](int64_t w0) {
         const int64_t rem64 = P1 - w0;
-        const int rem = rem64 > BW ? (int)BW : (int)rem64;   // valid points in this batch
+        const int rem = rem64 > BW ? (int)BW : (int)rem64;          // valid points in this batch
+        const int remn = rem64 > BW ? (int)BW + 1 : (int)rem64;     // lane + 1 < remn: a next point exists
         // phase 1: voxelise and test the coarse occupancy bit in LDS; only points in occupied
-        // coarse blocks gather their occupancy word and rank base (8 bytes)
-        uint32_t word[kBatch], bit[kBatch];
-        bool in[kBatch];
+        // coarse blocks gather their occupancy word and rank base (8 bytes).  Lookup v = b*kUp + t
+        // is sub-point t of window b.
+        uint32_t word[kV], bit[kV];
+        bool in[kV];
         bool anyc = false;
 #pragma unroll
         for (int b = 0; b < kBatch; ++b) {
-            float x = px[b], y = py[b], z = pz[b];
+            float qx = ax[b], qy = ay[b], qz = az[b];
             if (SCALED) {
-                x = __fmul_rn(x, sub.scale);
-                y = __fmul_rn(y, sub.scale);
-                z = __fmul_rn(z, sub.scale);
+                qx = __fmul_rn(qx, sub.scale);
+                qy = __fmul_rn(qy, sub.scale);
+                qz = __fmul_rn(qz, sub.scale);
             }
-            const float tx = __fadd_rn(x, 0.5f), ty = __fadd_rn(y, 0.5f), tz = __fadd_rn(z, 0.5f);
-            // 0 <= t < bound  <=>  bits(t) < bits(bound) as unsigned (t is never -0; NaN and
-            // negative values compare above every finite positive bound)
-            in[b] = (int)(fbits(tx) < bX) & (int)(fbits(ty) < bY) & (int)(fbits(tz) < bZ) &
-                    (int)(lane + b * kWave < rem);
-            const uint32_t ix = (uint32_t)(int)tx, iy = (uint32_t)(int)ty, iz = (uint32_t)(int)tz;
-            const uint32_t sb = __umul24(iz >> 3, SBXY) + __umul24(iy >> 3, SBX) + (ix >> 4);
-            const uint32_t bb = (ix & 15u) | ((iy & 7u) << 4) | ((iz & 7u) << 7);
-            const uint32_t cb = __umul24(iz >> cs, CBXY) + __umul24(iy >> cs, CBX) + (ix >> cs);
-            const uint32_t cw = coarse[in[b] ? (cb >> 5) : 0u];
-            in[b] = in[b] && ((cw >> (cb & 31u)) & 1u);
-            anyc |= in[b];
-            word[b] = in[b] ? ((sb << 5) | (bb >> 5)) : 0u;
-            bit[b] = bb & 31u;
-        }
-        uint32_t mw[kBatch], rank[kBatch];
+            float dx = 0.f, dy = 0.f, dz = 0.f;
+            if (kUp > 1) {
+                float mx = nx[b], my = ny[b], mz = nz[b];
+                if (SCALED) {
+                    mx = __fmul_rn(mx, sub.scale);
+                    my = __fmul_rn(my, sub.scale);
+                    mz = __fmul_rn(mz, sub.scale);
+                }
+                dx = __fsub_rn(mx, qx);
+                dy = __fsub_rn(my, qy);
+                dz = __fsub_rn(mz, qz);
+            }
 #pragma unroll
-        for (int b = 0; b < kBatch; ++b) mw[b] = rank[b] = 0u;
+            for (int t = 0; t < kUp; ++t) {
+                const int v = b * kUp + t;
+                float x = qx, y = qy, z = qz;
+                if (t > 0) {
+                    x = __fadd_rn(qx, __fmul_rn(at[t], dx));
+                    y = __fadd_rn(qy, __fmul_rn(at[t], dy));
+                    z = __fadd_rn(qz, __fmul_rn(at[t], dz));
+                }
+                const float tx = __fadd_rn(x, 0.5f), ty = __fadd_rn(y, 0.5f), tz = __fadd_rn(z, 0.5f);
+                // 0 <= t < bound  <=>  bits(t) < bits(bound) as unsigned (t is never -0; NaN and
+                // negative values compare above every finite positive bound)
+                const int valid = t == 0 ? (int)(lane + b * kWave < rem)
+                                         : (int)(t < up) & (int)(lane + b * kWave + 1 < remn);
+                in[v] = (int)(fbits(tx) < bX) & (int)(fbits(ty) < bY) & (int)(fbits(tz) < bZ) & valid;
+                const uint32_t ix = (uint32_t)(int)tx, iy = (uint32_t)(int)ty, iz = (uint32_t)(int)tz;
+                const uint32_t sb = __umul24(iz >> 3, SBXY) + __umul24(iy >> 3, SBX) + (ix >> 4);
+                const uint32_t bb = (ix & 15u) | ((iy & 7u) << 4) | ((iz & 7u) << 7);
+                const uint32_t cb = __umul24(iz >> cs, CBXY) + __umul24(iy >> cs, CBX) + (ix >> cs);
+                const uint32_t cw = coarse[in[v] ? (cb >> 5) : 0u];
+                in[v] = in[v] && ((cw >> (cb & 31u)) & 1u);
+                anyc |= in[v];
+                word[v] = in[v] ? ((sb << 5) | (bb >> 5)) : 0u;
+                bit[v] = bb & 31u;
+            }
+        }
+        uint32_t mw[kV], rank[kV];
+#pragma unroll
+        for (int v = 0; v < kV; ++v) mw[v] = rank[v] = 0u;
         if (__ballot(anyc)) {
 #pragma unroll
-            for (int b = 0; b < kBatch; ++b) {
-                const auto e = __builtin_amdgcn_raw_buffer_load_b64(rmb, in[b] ? (word[b] << 3) : kOutOfRange, 0,
+            for (int v = 0; v < kV; ++v) {
+                const auto e = __builtin_amdgcn_raw_buffer_load_b64(rmb, in[v] ? (word[v] << 3) : kOutOfRange, 0,
                                                                     kAuxCached);
-                mw[b] = e[0];
-                rank[b] = e[1];
+                mw[v] = e[0];
+                rank[v] = e[1];
             }
         }
-        bool flag[kBatch];
+        bool flag[kV];
         bool any = false;
 #pragma unroll
-        for (int b = 0; b < kBatch; ++b) {
-            flag[b] = in[b] && ((mw[b] >> bit[b]) & 1u);
-            any |= flag[b];
+        for (int v = 0; v < kV; ++v) {
+            flag[v] = in[v] && ((mw[v] >> bit[v]) & 1u);
+            any |= flag[v];
         }
-        int r[kBatch], m[kBatch];
+        int r[kV], m[kV];
 #pragma unroll
-        for (int b = 0; b < kBatch; ++b) r[b] = m[b] = -1;
+        for (int v = 0; v < kV; ++v) r[v] = m[v] = -1;
         if (__ballot(any)) {
             // phase 2: codes of the flagged voxels (other lanes read entry 0)
 #pragma unroll
-            for (int b = 0; b < kBatch; ++b)
-                rank[b] = flag[b] ? rank[b] + __popc(mw[b] & ((1u << bit[b]) - 1u)) : 0u;
+            for (int v = 0; v < kV; ++v)
+                rank[v] = flag[v] ? rank[v] + __popc(mw[v] & ((1u << bit[v]) - 1u)) : 0u;
             if (PACKED == 1 || (PACKED == 2 && cv.packed)) {
-                uint32_t code[kBatch];
+                uint32_t code[kV];
 #pragma unroll
-                for (int b = 0; b < kBatch; ++b)
-                    code[b] = __builtin_amdgcn_raw_buffer_load_b32(rcode, rank[b] << 2, 0, kAuxCached);
+                for (int v = 0; v < kV; ++v)
+                    code[v] = __builtin_amdgcn_raw_buffer_load_b32(rcode, rank[v] << 2, 0, kAuxCached);
 #pragma unroll
-                for (int b = 0; b < kBatch; ++b) {
-                    const uint32_t rv = code[b] & cv.rmask, mv = code[b] >> cv.rbits;
-                    r[b] = (flag[b] && rv < (uint32_t)cv.N) ? (int)rv : -1;
-                    m[b] = (flag[b] && mv < (uint32_t)cv.M) ? (int)mv : -1;
+                for (int v = 0; v < kV; ++v) {
+                    const uint32_t rv = code[v] & cv.rmask, mv = code[v] >> cv.rbits;
+                    r[v] = (flag[v] && rv < (uint32_t)cv.N) ? (int)rv : -1;
+                    m[v] = (flag[v] && mv < (uint32_t)cv.M) ? (int)mv : -1;
                 }
             } else {
 #pragma unroll
-                for (int b = 0; b < kBatch; ++b) {
-                    const auto c2 = __builtin_amdgcn_raw_buffer_load_b64(rcode, rank[b] << 3, 0, kAuxCached);
-                    r[b] = flag[b] ? (int)c2[0] : -1;
-                    m[b] = flag[b] ? (int)c2[1] : -1;
+                for (int v = 0; v < kV; ++v) {
+                    const auto c2 = __builtin_amdgcn_raw_buffer_load_b64(rcode, rank[v] << 3, 0, kAuxCached);
+                    r[v] = flag[v] ? (int)c2[0] : -1;
+                    m[v] = flag[v] ? (int)c2[1] : -1;
                 }
             }
         }
         // every gather of this batch has returned; its point registers now take the next batch
         const int64_t w2 = w0 + BW;
         __builtin_amdgcn_sched_barrier(0);
-        if (w2 < P1) load_batch(w2, px, py, pz);
+        if (w2 < P1) load_batch(w2);
         __builtin_amdgcn_sched_barrier(0);
         uint64_t fl[kBatch];
         uint64_t fall = 0;
 #pragma unroll
         for (int b = 0; b < kBatch; ++b) {
-            fl[b] = __ballot(flag[b]);
+            fl[b] = 0ull;
+#pragma unroll
+            for (int t = 0; t < kUp; ++t) fl[b] |= __ballot(flag[b * kUp + t]);
             fall |= fl[b];
         }
         if (fall == 0ull) {
@@ -902,21 +1000,60 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
                 last_r = last_m = -1;
                 continue;
             }
-            const int rb = r[b], mb = endmode ? -1 : m[b];
-            // previous point's row / label (lane 0: the last point of the previous window)
-            int rp_ = __builtin_amdgcn_update_dpp(last_r, rb, 0x138, 0xF, 0xF, false);   // wave_shr:1
-            int mp_ = __builtin_amdgcn_update_dpp(last_m, mb, 0x138, 0xF, 0xF, false);
-            if ((starts >> lane) & 1ull) rp_ = mp_ = -1;  // first point of a streamline
-            const uint64_t candR = __ballot(rb >= 0 && rb != rp_);
-            const uint64_t candM = __ballot(mb >= 0 && mb != mp_);
-            last_r = __builtin_amdgcn_readlane(rb, kWave - 1);
-            last_m = __builtin_amdgcn_readlane(mb, kWave - 1);
-            if (!starts) {   // the whole window belongs to the open streamline
-                if ((candR | candM) && !set.skip && !set.append(candR, rb, candM, mb)) {
-                    push_overflow(ovf, wb, subject);
-                    set.nR = set.nL = 0;
-                    set.skip = true;
+            // sub-points t >= 1 exist only where the next point continues the lane's streamline:
+            // not before a start, not at the range's end
+            uint64_t nextok = ~0ull;
+            if (kUp > 1) {
+                uint64_t brk = starts >> 1;
+                if (wb + kWave >= P1 || nxt == wb + kWave) brk |= 1ull << (kWave - 1);
+                const int64_t lastp = P1 - 1 - wb;   // lane of the range's last point
+                if (lastp < kWave) brk |= ~0ull << lastp;
+                nextok = ~brk;
+            }
+            int rr[kUp], mm[kUp];
+#pragma unroll
+            for (int t = 0; t < kUp; ++t) {
+                const bool ok = t == 0 || ((nextok >> lane) & 1ull);
+                rr[t] = ok ? r[b * kUp + t] : -1;
+                mm[t] = (ok && !endmode) ? m[b * kUp + t] : -1;
+            }
+            // each lane's last counted sub-point (t = up - 1) precedes the next lane's point
+            int rl = rr[0], ml = mm[0];
+#pragma unroll
+            for (int t = 1; t < kUp; ++t)
+                if (t == up - 1) {
+                    rl = rr[t];
+                    ml = mm[t];
                 }
+            // drop a hit equal to the hit just before it in streamline order: sub-point 0 against
+            // the previous lane's last sub-point (lane 0: the previous window's), t >= 1 against t - 1
+            int rp_ = __builtin_amdgcn_update_dpp(last_r, rl, 0x138, 0xF, 0xF, false);   // wave_shr:1
+            int mp_ = __builtin_amdgcn_update_dpp(last_m, ml, 0x138, 0xF, 0xF, false);
+            if ((starts >> lane) & 1ull) rp_ = mp_ = -1;  // first point of a streamline
+            uint64_t candR[kUp], candM[kUp];
+            candR[0] = __ballot(rr[0] >= 0 && rr[0] != rp_);
+            candM[0] = __ballot(mm[0] >= 0 && mm[0] != mp_);
+#pragma unroll
+            for (int t = 1; t < kUp; ++t) {
+                candR[t] = __ballot(rr[t] >= 0 && rr[t] != rr[t - 1]);
+                candM[t] = __ballot(mm[t] >= 0 && mm[t] != mm[t - 1]);
+            }
+            last_r = __builtin_amdgcn_readlane(rl, kWave - 1);
+            last_m = __builtin_amdgcn_readlane(ml, kWave - 1);
+            // the candidates of the lanes in `seg` into the open streamline's set
+            auto add = [&](uint64_t seg, int64_t at_point) {
+#pragma unroll
+                for (int t = 0; t < kUp; ++t) {
+                    const uint64_t cR = candR[t] & seg, cM = candM[t] & seg;
+                    if ((cR | cM) && !set.skip && !set.append(cR, rr[t], cM, mm[t])) {
+                        push_overflow(ovf, at_point, subject);
+                        set.nR = set.nL = 0;
+                        set.skip = true;
+                    }
+                }
+            };
+            if (!starts) {   // the whole window belongs to the open streamline
+                add(~0ull, wb);
                 continue;
             }
             int pos = 0;
@@ -924,13 +1061,7 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
             uint64_t st = starts;
             for (;;) {
                 const int end = st ? __builtin_ctzll(st) : kWave;
-                const uint64_t seg = lanes_between(pos, end);
-                const uint64_t cR = candR & seg, cM = candM & seg;
-                if ((cR | cM) && !set.skip && !set.append(cR, rb, cM, mb)) {
-                    push_overflow(ovf, wb + pos, subject);
-                    set.nR = set.nL = 0;
-                    set.skip = true;
-                }
+                add(lanes_between(pos, end), wb + pos);
                 if (!st) break;
                 close_open(id);
                 if (endmode) id += __builtin_amdgcn_readlane(mult, end);
@@ -939,8 +1070,8 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
             }
         }
     };
-    load_batch(P0, ax, ay, az);
-    for (int64_t w0 = P0; w0 < P1; w0 += BW) run_batch(w0, ax, ay, az);
+    load_batch(P0);
+    for (int64_t w0 = P0; w0 < P1; w0 += BW) run_batch(w0);
     close_open(vb - 1 + k0);
 }
 
@@ -966,7 +1097,36 @@ __global__ void __launch_bounds__(kBlock) k_count_stream(StreamSubject sub, Over
         const int64_t s0 = uniform64(clamp64(first[part], 0, sub.S));
         const int64_t s1 = uniform64(clamp64(first[part + 1], s0, sub.S));
         if (s0 >= s1) continue;
-        stream_range<SCALED, PACKED ? 1 : 0, kBatch, kEnds>(sub, s_coarse, s0, s1, 0, ovf, set, sink);
+        stream_range<SCALED, PACKED ? 1 : 0, kBatch, kEnds, 1>(sub, s_coarse, s0, s1, 0, ovf, set, sink);
+    }
+    sink.drain();
+}
+
+// Upsampled pass-through (up = 2 .. kUp): the scale is always applied (multiplying by 1.0f is
+// exact) and the code width is read from the volume, so two instantiations cover every case.
+template <int kUp>
+__global__ void __launch_bounds__(kBlock) k_count_stream_up(StreamSubject sub, Overflow ovf,
+                                                            const int32_t *__restrict__ first, int64_t nparts) {
+    constexpr int kB = kUp == 2 ? 2 : 1;   // kB * kUp lookups per batch, as the plain kernel's 4
+    __shared__ uint32_t s_set[kWavesPerBlock * kSetWords];
+    __shared__ uint32_t s_pend[kWavesPerBlock * kWave];
+    extern __shared__ uint32_t s_coarse[];
+    const int lane = lane_id(), wv = uniform32(threadIdx.x >> 6);
+    for (int k = threadIdx.x; k < sub.cv.ncoarse_words; k += blockDim.x) s_coarse[k] = sub.cv.coarse[k];
+    __syncthreads();
+    StreamSet set;
+    set.init(s_set + wv * kSetWords);
+    BufferedSink sink;
+    sink.init(s_pend + wv * kWave, sub.C);
+    for (;;) {
+        unsigned long long t = 0;
+        if (lane == 0) t = atomicAdd(ovf.work, 1ull);
+        const int64_t part = uniform64((int64_t)t);
+        if (part >= nparts) break;
+        const int64_t s0 = uniform64(clamp64(first[part], 0, sub.S));
+        const int64_t s1 = uniform64(clamp64(first[part + 1], s0, sub.S));
+        if (s0 >= s1) continue;
+        stream_range<true, 2, kB, false, kUp>(sub, s_coarse, s0, s1, 0, ovf, set, sink);
     }
     sink.drain();
 }
@@ -1009,7 +1169,7 @@ __global__ void __launch_bounds__(kBlock) k_count_batched(const StreamSubject *_
             loaded = subject;
         }
         sink.C = sub.C;
-        stream_range<true, 2, kBatch, false>(sub, coarse, s0, s1, subject, ovf, set, sink);
+        stream_range<true, 2, kBatch, false, 1>(sub, coarse, s0, s1, subject, ovf, set, sink);
         sink.drain();   // the next item may belong to another subject's C
     }
 }
@@ -1028,7 +1188,16 @@ static int blocks_per_cu_b(bool scaled, bool packed, size_t dyn) {
     return packed ? blocks_per_cu_of<false, true, B, E>(dyn) : blocks_per_cu_of<false, false, B, E>(dyn);
 }
 
-int count_stream_blocks_per_cu(bool scaled, bool packed, int batch, bool ends, size_t dyn) {
+template <int U>
+static int blocks_per_cu_up(size_t dyn) {
+    int n = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &n, reinterpret_cast<const void *>(&k_count_stream_up<U>), kBlock, dyn);
+    return (e == hipSuccess && n > 0) ? n : 4;
+}
+
+int count_stream_blocks_per_cu(bool scaled, bool packed, int batch, bool ends, int up, size_t dyn) {
+    if (up > 1) return up == 2 ? blocks_per_cu_up<2>(dyn) : blocks_per_cu_up<4>(dyn);
     if (ends) return batch == 2 ? blocks_per_cu_b<2, true>(scaled, packed, dyn) : blocks_per_cu_b<4, true>(scaled, packed, dyn);
     return batch == 2 ? blocks_per_cu_b<2, false>(scaled, packed, dyn) : blocks_per_cu_b<4, false>(scaled, packed, dyn);
 }
@@ -1046,6 +1215,7 @@ static StreamSubject stream_subject(const CountArgs &a, const CompactVol &cv) {
     s.si = a.si;
     s.sm = a.sm;
     s.ends = a.ends;
+    s.up = a.up;
     return s;
 }
 
@@ -1063,6 +1233,13 @@ static void launch_stream_b(const CountArgs &a, const CompactVol &cv, const int3
 
 hipError_t launch_count_stream(const CountArgs &a, const CompactVol &cv, const int32_t *first, int64_t nparts,
                                int blocks, int batch, hipStream_t st) {
+    if (a.up > 1) {
+        const size_t dyn = 4 * (size_t)cv.ncoarse_words;
+        const StreamSubject sub = stream_subject(a, cv);
+        if (a.up == 2) k_count_stream_up<2><<<blocks, kBlock, dyn, st>>>(sub, a.ovf, first, nparts);
+        else k_count_stream_up<4><<<blocks, kBlock, dyn, st>>>(sub, a.ovf, first, nparts);
+        return hipGetLastError();
+    }
     const bool ends = a.ends.mode != 0;
     if (batch == 2) {
         if (ends) launch_stream_b<2, true>(a, cv, first, nparts, blocks, st);
@@ -1080,11 +1257,43 @@ hipError_t launch_count_stream(const CountArgs &a, const CompactVol &cv, const i
 
 // One overflowed streamline (the one containing point p), counted by a whole workgroup with the
 // workgroup's all-zero scratch: a bit map over rows, one over labels and a list of the labels.
+// Sub-point k of the streamline [b0, b1) upsampled by `up` (0 <= k < (b1 - b0 - 1) * up + 1):
+// point j = b0 + k / up itself when t = k % up is 0, else the point a_t = fl32(t / up) of the way to
+// point j + 1, in scaled coordinates.  False when it has no voxel.
+template <typename Lookup, bool SCALED>
+__device__ bool sub_lookup(const float *__restrict__ pts, int64_t b0, int64_t k, int up, float scale, const Grid &g,
+                           const Lookup &lk, int &r, int &m) {
+    const int64_t j = b0 + k / up;
+    const int t = (int)(k % up);
+    float x = pts[3 * j], y = pts[3 * j + 1], z = pts[3 * j + 2];
+    if (SCALED) {
+        x = __fmul_rn(x, scale);
+        y = __fmul_rn(y, scale);
+        z = __fmul_rn(z, scale);
+    }
+    if (t > 0) {
+        float ux = pts[3 * j + 3], uy = pts[3 * j + 4], uz = pts[3 * j + 5];
+        if (SCALED) {
+            ux = __fmul_rn(ux, scale);
+            uy = __fmul_rn(uy, scale);
+            uz = __fmul_rn(uz, scale);
+        }
+        const float a = (float)((double)t / (double)up);
+        x = __fadd_rn(x, __fmul_rn(a, __fsub_rn(ux, x)));
+        y = __fadd_rn(y, __fmul_rn(a, __fsub_rn(uy, y)));
+        z = __fadd_rn(z, __fmul_rn(a, __fsub_rn(uz, z)));
+    }
+    int ix, iy, iz;
+    if (!voxelise<false>(x, y, z, 1.0f, g, ix, iy, iz)) return false;
+    lk.get(ix, iy, iz, r, m);
+    return true;
+}
+
 template <typename Lookup, bool SCALED>
 __device__ void fallback_streamline(const float *__restrict__ pts, const int64_t *__restrict__ offsets, int64_t S,
                                     const Grid &g, float scale, const Lookup &lk, int32_t *__restrict__ C, uint32_t si,
                                     uint32_t sm, int64_t p, uint32_t *bmN, uint32_t *bmM, uint32_t *labels,
-                                    int *s_nlab, const EndLabels &ends) {
+                                    int *s_nlab, const EndLabels &ends, int up) {
     const int64_t Ptot = offsets[S] > 0 ? offsets[S] : 0;
     // streamline containing point p: last s with offsets[s] <= p
     int64_t lo = 0, hi = S;  // answer in [0, S-1]
@@ -1095,6 +1304,7 @@ __device__ void fallback_streamline(const float *__restrict__ pts, const int64_t
     }
     const int64_t b0 = clamp64(offsets[lo], 0, Ptot);
     const int64_t b1 = clamp64(offsets[lo + 1], b0, Ptot);
+    const int64_t nsub = b1 > b0 ? (b1 - b0 - 1) * up + 1 : 0;   // points after upsampling
     if (threadIdx.x == 0) *s_nlab = 0;
     __syncthreads();
     // endpoint modes: the labels are the streamline's end labels
@@ -1106,10 +1316,9 @@ __device__ void fallback_streamline(const float *__restrict__ pts, const int64_t
         *s_nlab = n;
     }
     // distinct labels
-    for (int64_t j = b0 + threadIdx.x; ends.mode == 0 && j < b1; j += blockDim.x) {
-        int ix, iy, iz, r, m;
-        if (!voxelise<SCALED>(pts[3 * j], pts[3 * j + 1], pts[3 * j + 2], scale, g, ix, iy, iz)) continue;
-        lk.get(ix, iy, iz, r, m);
+    for (int64_t k = threadIdx.x; ends.mode == 0 && k < nsub; k += blockDim.x) {
+        int r, m;
+        if (!sub_lookup<Lookup, SCALED>(pts, b0, k, up, scale, g, lk, r, m)) continue;
         if (m >= 0) {
             const uint32_t bitm = 1u << (m & 31);
             if (!(atomicOr(&bmM[m >> 5], bitm) & bitm)) {
@@ -1122,10 +1331,9 @@ __device__ void fallback_streamline(const float *__restrict__ pts, const int64_t
     const int nlab = *s_nlab;
     // distinct rows: the first claimant of each row adds its pairs
     if (nlab > 0) {
-        for (int64_t j = b0 + threadIdx.x; j < b1; j += blockDim.x) {
-            int ix, iy, iz, r, m;
-            if (!voxelise<SCALED>(pts[3 * j], pts[3 * j + 1], pts[3 * j + 2], scale, g, ix, iy, iz)) continue;
-            lk.get(ix, iy, iz, r, m);
+        for (int64_t k = threadIdx.x; k < nsub; k += blockDim.x) {
+            int r, m;
+            if (!sub_lookup<Lookup, SCALED>(pts, b0, k, up, scale, g, lk, r, m)) continue;
             if (r >= 0) {
                 const uint32_t bitr = 1u << (r & 31);
                 if (!(atomicOr(&bmN[r >> 5], bitr) & bitr)) {
@@ -1138,10 +1346,9 @@ __device__ void fallback_streamline(const float *__restrict__ pts, const int64_t
     }
     __syncthreads();
     // restore the all-zero scratch (bit maps and label list)
-    for (int64_t j = b0 + threadIdx.x; j < b1; j += blockDim.x) {
-        int ix, iy, iz, r, m;
-        if (!voxelise<SCALED>(pts[3 * j], pts[3 * j + 1], pts[3 * j + 2], scale, g, ix, iy, iz)) continue;
-        lk.get(ix, iy, iz, r, m);
+    for (int64_t k = threadIdx.x; k < nsub; k += blockDim.x) {
+        int r, m;
+        if (!sub_lookup<Lookup, SCALED>(pts, b0, k, up, scale, g, lk, r, m)) continue;
         if (r >= 0) atomicExch(&bmN[r >> 5], 0u);
         if (m >= 0) atomicExch(&bmM[m >> 5], 0u);
     }
@@ -1161,7 +1368,7 @@ __global__ void __launch_bounds__(kBlock) k_fallback(CountArgs a, Lookup lk, Fal
     const int64_t nq_c = nq < a.ovf.cap ? nq : a.ovf.cap;
     for (int64_t q = blockIdx.x; q < nq_c; q += gridDim.x)
         fallback_streamline<Lookup, SCALED>(a.pts, a.offsets, a.S, a.g, a.scale, lk, a.C, a.si, a.sm,
-                                            a.ovf.list[q] & kPointMask, bmN, bmM, labels, &s_nlab, a.ends);
+                                            a.ovf.list[q] & kPointMask, bmN, bmM, labels, &s_nlab, a.ends, a.up);
 }
 
 // Batched fallback: the queue entry names its subject.
@@ -1180,7 +1387,7 @@ __global__ void __launch_bounds__(kBlock) k_fallback_batched(const StreamSubject
         const StreamSubject &sub = subs[subject];
         fallback_streamline<CompactLookup, true>(sub.pts, sub.offsets, sub.S, sub.g, sub.scale, CompactLookup{sub.cv},
                                                  sub.C, sub.si, sub.sm, e & kPointMask, bmN, bmM, labels, &s_nlab,
-                                                 sub.ends);
+                                                 sub.ends, sub.up);
     }
 }
 

@@ -145,6 +145,7 @@ class HipExecutor final : public fcs::Executor {
             ss.si = (uint32_t)v.M;
             ss.sm = 1u;
             ss.ends = fc::EndLabels{0, nullptr, nullptr};
+            ss.up = 1;
             const int64_t pts = r.offsets[c.s1] - r.offsets[c.s0];
             int64_t ni = total > 0 ? (int64_t)((double)want * (double)pts / (double)total + 0.5) : 1;
             ni = std::max<int64_t>(1, std::min<int64_t>(ni, c.s1 - c.s0));

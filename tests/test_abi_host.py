@@ -62,8 +62,9 @@ def test_bad_arguments_are_rejected_synchronously(lib, kw):
     assert lib.fastcod_last_error() != b""
 
 
-@pytest.mark.parametrize("field,value", [("upsample", 2), ("scale", 0.0), ("scale", float("nan")),
-                                         ("scale", float("inf")), ("variant", 7)])
+@pytest.mark.parametrize("field,value", [("upsample", 5), ("upsample", 0), ("mode", 4), ("mode", -1), ("scale", 0.0),
+                                         ("scale", float("nan")), ("scale", float("inf")), ("variant", 7),
+                                         ("batch", 8), ("blocks_per_cu", -1)])
 def test_bad_options_are_rejected(lib, field, value):
     o = lib.fastcod_default_opts()
     setattr(o, field, value)
@@ -128,3 +129,9 @@ def test_parcellate_rejects_bad_arguments(lib):
     assert lib.fastcod_parcellate(None, 3, 0, None, None, None, None) == fastcod.EINVAL
     assert lib.fastcod_parcellate(None, 1 << 20, 1 << 12, None, None, None, None) == fastcod.EINVAL
     assert lib.fastcod_parcellate(None, 5, 3, None, None, None, None) == fastcod.EINVAL
+
+
+def test_upsampling_needs_passthrough(lib):
+    o = lib.fastcod_default_opts()
+    o.upsample, o.mode = 2, 1
+    assert _count(lib, pts=16, off=16, roi=16, lab=16, C=16, opts=o) == fastcod.EINVAL

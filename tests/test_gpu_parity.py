@@ -240,7 +240,7 @@ def test_binding_rejects_bad_tensors(fc):
     with pytest.raises(TypeError):
         fc.count(w.points.double(), w.offsets, w.roi, w.lab, w.N, w.M)
     with pytest.raises(fc.FastcodError):
-        fc.count(w.points, w.offsets, w.roi, w.lab, w.N, w.M, upsample=2)
+        fc.count(w.points, w.offsets, w.roi, w.lab, w.N, w.M, upsample=5)
 
 
 # ---- full-size subjects -------------------------------------------------------------------------
