@@ -737,6 +737,7 @@ __device__ __forceinline__ int64_t uniform64(int64_t v) {
 }
 
 constexpr int kRCap = 192, kLCap = 64, kTCap = 512;   // per-wave candidate lists and set
+constexpr int64_t kMaxRangePoints = int64_t(1) << 28;  // longest point range the flat-stream loop takes
 constexpr int kSetWords = kRCap + 2 * kLCap + kTCap;
 using StreamSet = DeferredSet<kRCap, kLCap, kTCap>;
 
@@ -763,6 +764,17 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
     const int64_t P0 = uniform64(clamp64(sub.offsets[s0], 0, Ptot));
     const int64_t P1 = uniform64(clamp64(sub.offsets[s1], P0, Ptot));
     if (P0 >= P1) return;
+    if (P1 - P0 > kMaxRangePoints) {
+        // positions below are 32-bit offsets from P0: a range this long (a few giant streamlines
+        // make one) goes to the fallback kernel, one entry per non-empty streamline
+        for (int64_t s = s0; s < s1; ++s) {
+            const int64_t b = uniform64(clamp64(sub.offsets[s], P0, P1));
+            const int64_t e = uniform64(clamp64(sub.offsets[s + 1], b, P1));
+            if (e > b) push_overflow(ovf, b, subject);
+        }
+        return;
+    }
+    const uint32_t L = (uint32_t)(P1 - P0);   // points of the range; positions are relative to P0
     // endpoint modes (kEnds instantiations only): no point contributes its label; each closing
     // streamline gets its end labels
     const bool endmode = kEnds && uniform32(sub.ends.mode) != 0;
@@ -772,15 +784,15 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
     float at[kUp];
 #pragma unroll
     for (int t = 0; t < kUp; ++t) at[t] = (float)((double)t / (double)up);
-    // Starts of streamlines s0+1 .. s1-1, 64 at a time, one per lane (P1 = "no more starts");
-    // k0 of them are consumed and `nxt` (uniform) is the next unconsumed start.
+    // Starts of streamlines s0+1 .. s1-1 (relative to P0), 64 at a time, one per lane (L = "no
+    // more starts"); k0 of them are consumed and `nxt` (uniform) is the next unconsumed start.
     int64_t vb = s0 + 1;
-    int64_t voff = 0, nxt = P1;
+    uint32_t voff = 0, nxt = L;
     int k0 = 0;
     auto load_starts = [&]() {
-        voff = (vb + lane < s1) ? clamp64(sub.offsets[vb + lane], P0, P1) : P1;
+        voff = (vb + lane < s1) ? (uint32_t)(clamp64(sub.offsets[vb + lane], P0, P1) - P0) : L;
         k0 = 0;
-        nxt = readlane64(voff, 0);
+        nxt = (uint32_t)__builtin_amdgcn_readlane((int)voff, 0);
     };
     auto consumed = [&](uint64_t taken) {
         k0 += __popcll(taken);
@@ -788,17 +800,16 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
             vb += kWave;
             load_starts();
         } else {
-            nxt = readlane64(voff, k0);
+            nxt = (uint32_t)__builtin_amdgcn_readlane((int)voff, k0);
         }
     };
     // starts in [wb, wend) (wend <= wb + 64) as lane bits relative to wb; consumes them.  `mult`
     // (endpoint modes) counts the streamlines starting at each lane: empty streamlines share a start.
-    auto take_starts = [&](int64_t wb, int64_t wend, int &mult) -> uint64_t {
+    auto take_starts = [&](uint32_t wb, uint32_t wend, int &mult) -> uint64_t {
         uint64_t starts = 0;
         while (nxt < wend) {
-            const uint64_t inwin = __ballot(lane >= k0 && voff < wend);
-            int64_t qv = voff - wb;
-            qv = qv < 0 ? 0 : (qv > kWave - 1 ? kWave - 1 : qv);
+            const uint64_t inwin = __ballot((int)(lane >= k0) & (int)(voff < wend));
+            const uint32_t qv = min(voff - wb, (uint32_t)(kWave - 1));   // lane of the start (in-window lanes)
             uint64_t it = inwin;
             while (it) {
                 const int k = __builtin_ctzll(it);
@@ -811,8 +822,8 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
         }
         return starts;
     };
-    auto skip_starts = [&](int64_t limit) {
-        while (nxt < limit) consumed(__ballot(lane >= k0 && voff < limit));
+    auto skip_starts = [&](uint32_t limit) {
+        while (nxt < limit) consumed(__ballot((int)(lane >= k0) & (int)(voff < limit)));
     };
     load_starts();
     // the open streamline is vb - 1 + k0: the last one whose start has been consumed
@@ -824,10 +835,10 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
         set.close(sink, sub.si, sub.sm);
     };
     int last_r = -1, last_m = -1;
-    // points from `pbase` (re-based if a range ever passes 4 GB)
-    int64_t pbase = P0;
-    __amdgpu_buffer_rsrc_t rp = make_rsrc(sub.pts + 3 * pbase, 12ull * (uint64_t)(Ptot - pbase));
-    const int64_t BW = (int64_t)kWave * kBatch;   // points per batch
+    // points [P0, P1): loads at or past the range's end read zero without memory traffic, so the
+    // next batch can always be issued
+    const __amdgpu_buffer_rsrc_t rp = make_rsrc(sub.pts + 3 * P0, 12ull * L);
+    constexpr uint32_t BW = kWave * kBatch;   // points per batch
 
     // one register set of points: batch k+1 is issued into it once batch k's gathers have
     // returned, and streams in while batch k is folded into the set
@@ -835,12 +846,8 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
     // the lines the window itself brings in)
     constexpr int kNext = kUp > 1 ? kBatch : 1;
     float ax[kBatch], ay[kBatch], az[kBatch], nx[kNext], ny[kNext], nz[kNext];
-    auto load_batch = [&](int64_t w) {
-        if (12 * (w - pbase) + 12 * BW > (int64_t)0xF0000000ll) {
-            pbase = w;
-            rp = make_rsrc(sub.pts + 3 * pbase, 12ull * (uint64_t)(Ptot - pbase));
-        }
-        const uint32_t so = (uint32_t)(12 * (w - pbase));
+    auto load_batch = [&](uint32_t w) {
+        const uint32_t so = 12u * w;
 #pragma unroll
         for (int b = 0; b < kBatch; ++b) {
             const auto v = __builtin_amdgcn_raw_buffer_load_b96(rp, lane12, so + 768u * b, kAuxStream);
@@ -858,10 +865,10 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
             }
         }
     };
-    auto run_batch = [&](int64_t w0) {
-        const int64_t rem64 = P1 - w0;
-        const int rem = rem64 > BW ? (int)BW : (int)rem64;          // valid points in this batch
-        const int remn = rem64 > BW ? (int)BW + 1 : (int)rem64;     // lane + 1 < remn: a next point exists
+    auto run_batch = [&](uint32_t w0) {
+        const uint32_t left = L - w0;
+        const int rem = left > BW ? (int)BW : (int)left;          // valid points in this batch
+        const int remn = left > BW ? (int)BW + 1 : (int)left;     // lane + 1 < remn: a next point exists
         // phase 1: voxelise and test the coarse occupancy bit in LDS; only points in occupied
         // coarse blocks gather their occupancy word and rank base (8 bytes).  Lookup v = b*kUp + t
         // is sub-point t of window b.
@@ -904,11 +911,12 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
                                          : (int)(t < up) & (int)(lane + b * kWave + 1 < remn);
                 in[v] = (int)(fbits(tx) < bX) & (int)(fbits(ty) < bY) & (int)(fbits(tz) < bZ) & valid;
                 const uint32_t ix = (uint32_t)(int)tx, iy = (uint32_t)(int)ty, iz = (uint32_t)(int)tz;
-                const uint32_t sb = __umul24(iz >> 3, SBXY) + __umul24(iy >> 3, SBX) + (ix >> 4);
+                uint32_t sb = __umul24(iz >> 3, SBXY) + __umul24(iy >> 3, SBX) + (ix >> 4);
+                asm("" : "+v"(sb));   // keeps the 24-bit multiplies: (sb << 5) must not fold into them
                 const uint32_t bb = (ix & 15u) | ((iy & 7u) << 4) | ((iz & 7u) << 7);
                 const uint32_t cb = __umul24(iz >> cs, CBXY) + __umul24(iy >> cs, CBX) + (ix >> cs);
                 const uint32_t cw = coarse[in[v] ? (cb >> 5) : 0u];
-                in[v] = in[v] && ((cw >> (cb & 31u)) & 1u);
+                in[v] = (int)in[v] & (int)((cw >> (cb & 31u)) & 1u);
                 anyc |= in[v];
                 word[v] = in[v] ? ((sb << 5) | (bb >> 5)) : 0u;
                 bit[v] = bb & 31u;
@@ -933,6 +941,10 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
             flag[v] = in[v] && ((mw[v] >> bit[v]) & 1u);
             any |= flag[v];
         }
+        // The point registers are free since phase 1: the next batch's loads are issued after this
+        // batch's code gathers and before their results are used (loads return in issue order, so
+        // waiting for the codes does not wait for the stream).
+        const uint32_t w2 = w0 + BW;
         int r[kV], m[kV];
 #pragma unroll
         for (int v = 0; v < kV; ++v) r[v] = m[v] = -1;
@@ -946,6 +958,9 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
 #pragma unroll
                 for (int v = 0; v < kV; ++v)
                     code[v] = __builtin_amdgcn_raw_buffer_load_b32(rcode, rank[v] << 2, 0, kAuxCached);
+                __builtin_amdgcn_sched_barrier(0);
+                load_batch(w2);
+                __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int v = 0; v < kV; ++v) {
                     const uint32_t rv = code[v] & cv.rmask, mv = code[v] >> cv.rbits;
@@ -953,19 +968,27 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
                     m[v] = (flag[v] && mv < (uint32_t)cv.M) ? (int)mv : -1;
                 }
             } else {
+                uint32_t c0[kV], c1[kV];
 #pragma unroll
                 for (int v = 0; v < kV; ++v) {
                     const auto c2 = __builtin_amdgcn_raw_buffer_load_b64(rcode, rank[v] << 3, 0, kAuxCached);
-                    r[v] = flag[v] ? (int)c2[0] : -1;
-                    m[v] = flag[v] ? (int)c2[1] : -1;
+                    c0[v] = c2[0];
+                    c1[v] = c2[1];
+                }
+                __builtin_amdgcn_sched_barrier(0);
+                load_batch(w2);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int v = 0; v < kV; ++v) {
+                    r[v] = flag[v] ? (int)c0[v] : -1;
+                    m[v] = flag[v] ? (int)c1[v] : -1;
                 }
             }
+        } else {
+            __builtin_amdgcn_sched_barrier(0);
+            load_batch(w2);
+            __builtin_amdgcn_sched_barrier(0);
         }
-        // every gather of this batch has returned; its point registers now take the next batch
-        const int64_t w2 = w0 + BW;
-        __builtin_amdgcn_sched_barrier(0);
-        if (w2 < P1) load_batch(w2);
-        __builtin_amdgcn_sched_barrier(0);
         uint64_t fl[kBatch];
         uint64_t fall = 0;
 #pragma unroll
@@ -978,7 +1001,7 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
         if (fall == 0ull) {
             // nothing looked up: only a streamline start inside the batch matters (it closes the
             // open streamline, whose hits all came earlier)
-            const int64_t bend = (w0 + BW < P1) ? w0 + BW : P1;
+            const uint32_t bend = (w0 + BW < L) ? w0 + BW : L;
             if (nxt < bend) {
                 if (set.has_state()) close_open(vb - 1 + k0);
                 skip_starts(bend);
@@ -988,9 +1011,9 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
         }
 #pragma unroll
         for (int b = 0; b < kBatch; ++b) {
-            const int64_t wb = w0 + (int64_t)b * kWave;
-            if (wb >= P1) break;
-            const int64_t wend = (wb + kWave < P1) ? wb + kWave : P1;
+            const uint32_t wb = w0 + (uint32_t)b * kWave;
+            if (wb >= L) break;
+            const uint32_t wend = (wb + kWave < L) ? wb + kWave : L;
             // streamline starts inside this window -> bit q of `starts` for lane q
             const int64_t id0 = vb - 1 + k0;   // the streamline open at the window's first point
             int mult = 0;
@@ -1005,9 +1028,9 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
             uint64_t nextok = ~0ull;
             if (kUp > 1) {
                 uint64_t brk = starts >> 1;
-                if (wb + kWave >= P1 || nxt == wb + kWave) brk |= 1ull << (kWave - 1);
-                const int64_t lastp = P1 - 1 - wb;   // lane of the range's last point
-                if (lastp < kWave) brk |= ~0ull << lastp;
+                if (wb + kWave >= L || nxt == wb + kWave) brk |= 1ull << (kWave - 1);
+                const uint32_t lastp = L - 1 - wb;   // lane of the range's last point
+                if (lastp < (uint32_t)kWave) brk |= ~0ull << lastp;
                 nextok = ~brk;
             }
             int rr[kUp], mm[kUp];
@@ -1041,12 +1064,12 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
             last_r = __builtin_amdgcn_readlane(rl, kWave - 1);
             last_m = __builtin_amdgcn_readlane(ml, kWave - 1);
             // the candidates of the lanes in `seg` into the open streamline's set
-            auto add = [&](uint64_t seg, int64_t at_point) {
+            auto add = [&](uint64_t seg, uint32_t at) {
 #pragma unroll
                 for (int t = 0; t < kUp; ++t) {
                     const uint64_t cR = candR[t] & seg, cM = candM[t] & seg;
                     if ((cR | cM) && !set.skip && !set.append(cR, rr[t], cM, mm[t])) {
-                        push_overflow(ovf, at_point, subject);
+                        push_overflow(ovf, P0 + (int64_t)at, subject);
                         set.nR = set.nL = 0;
                         set.skip = true;
                     }
@@ -1070,8 +1093,8 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
             }
         }
     };
-    load_batch(P0);
-    for (int64_t w0 = P0; w0 < P1; w0 += BW) run_batch(w0);
+    load_batch(0u);
+    for (uint32_t w0 = 0; w0 < L; w0 += BW) run_batch(w0);
     close_open(vb - 1 + k0);
 }
 

@@ -281,3 +281,30 @@ def test_07mm_full_bench_configuration(fc, vols07):
     torch.cuda.synchronize()
     np.testing.assert_array_equal(got.cpu().numpy(), exp)
     vol.close()
+
+
+def test_giant_streamline_range(fc):
+    # one streamline of 2^28 + 4096 points (longer than the flat-stream loop takes in one range, so
+    # it goes to the fallback kernel) between short ones; a 2048-point loop through a 24^3 grid,
+    # repeated, touches few ROI / label voxels, so the oracle's sets stay small
+    rng = np.random.default_rng(21)
+    X = Y = Z = 24
+    roi = np.full((Z, Y, X), -1, np.int32)
+    lab = np.full((Z, Y, X), -1, np.int32)
+    cells = rng.choice(X * Y * Z, size=300, replace=False)
+    roi.reshape(-1)[cells[:200]] = np.arange(200)
+    lab.reshape(-1)[cells[200:]] = rng.integers(0, 9, size=100)
+    t = np.arange(2048) * (2 * np.pi / 2048)
+    loop = np.stack([12 + 9 * np.cos(t), 12 + 9 * np.sin(3 * t), 12 + 9 * np.sin(t)], axis=1).astype(np.float32)
+    T = (1 << 28) + 4096
+    short = [rng.uniform(0, 24, size=(n, 3)).astype(np.float32) for n in (50, 0, 700)]
+    giant_rows = T // 2048
+    pts_cpu = np.concatenate([short[0], np.tile(loop, (giant_rows, 1)), short[1], short[2]])
+    off = np.array([0, 50, 50 + T, 50 + T, 50 + T + 700], np.int64)
+    assert pts_cpu.shape[0] == off[-1]
+    _say(f"[parity] giant streamline: P={off[-1]}")
+    exp = oracle.count(pts_cpu, off, roi, lab, 200, 9)
+    w = _np_workload(pts_cpu, off, roi, lab, 200, 9, name="giant").to("cuda")
+    del pts_cpu
+    for v in (0, 2):
+        np.testing.assert_array_equal(_run(fc, w, v), exp, err_msg=f"variant {v}")
