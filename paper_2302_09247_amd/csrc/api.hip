@@ -554,7 +554,7 @@ int fastcod_count_ex(const float *points, const int64_t *offsets, int64_t S, con
     }
     const fc::Grid g = make_grid(dims);
     CompactLayout L;
-    const bool compact_ok = compact_layout(dims, N, M, L);
+    const bool compact_ok = compact_layout(dims, N, M, L, kMaxCoarseWords, true);
     if (o.variant == FASTCOD_VARIANT_STREAM && !compact_ok)
         return fail(FASTCOD_EINVAL, "grid too thin for the compact volume; use FASTCOD_VARIANT_WAVE");
     if (o.variant == FASTCOD_VARIANT_WAVE || !compact_ok) {
@@ -580,7 +580,7 @@ int fastcod_volume_create(const int32_t *roi, const int32_t *lab, const int32_t 
     int rc = check_volume_args(roi, lab, dims, N, M);
     if (rc) return rc;
     CompactLayout L;
-    if (!compact_layout(dims, N, M, L)) return fail(FASTCOD_EINVAL, "grid too thin for a compact volume");
+    if (!compact_layout(dims, N, M, L, kMaxCoarseWords, true)) return fail(FASTCOD_EINVAL, "grid too thin for a compact volume");
     int dev;
     rc = current_device(&dev);
     if (rc) return rc;

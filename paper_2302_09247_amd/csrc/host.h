@@ -111,13 +111,13 @@ struct CompactLayout {
     int64_t nvox;
     bool packed;
     int32_t rbits;
-    int32_t cs, CBX, CBY, CBZ, ncoarse_words;
+    int32_t csx, csyz, CBX, CBY, CBZ, ncoarse_words;
     int64_t ncodes;   // capacity of the code array (every voxel unless sized by compact_layout_fit)
     size_t off_mb, off_tiles, off_coarse, off_codes, bytes;
 };
 
 inline bool compact_layout(const int32_t dims[3], int32_t N, int32_t M, CompactLayout &L,
-                           int32_t max_coarse_words = kMaxCoarseWords) {
+                           int32_t max_coarse_words = kMaxCoarseWords, bool brick_coarse = false) {
     L.SBX = (dims[0] + 15) / 16;
     L.SBY = (dims[1] + 7) / 8;
     L.SBZ = (dims[2] + 7) / 8;
@@ -132,18 +132,22 @@ inline bool compact_layout(const int32_t dims[3], int32_t N, int32_t M, CompactL
     L.rbits = rb;
     // buffer-resource offsets are 32-bit: occupancy pairs and codes must stay below 4 GB
     if (8 * L.W >= (int64_t(1) << 32) || (L.packed ? 4 : 8) * L.nvox >= (int64_t(1) << 32)) return false;
-    // coarse occupancy (kept in LDS by the counting kernel): smallest block side 8, 16 or 32 whose
-    // bit map fits kMaxCoarseWords
-    for (L.cs = 3; L.cs <= 5; ++L.cs) {
-        const int32_t c = 1 << L.cs;
-        L.CBX = (dims[0] + c - 1) / c;
-        L.CBY = (dims[1] + c - 1) / c;
-        L.CBZ = (dims[2] + c - 1) / c;
+    // coarse occupancy (kept in LDS by the counting kernel): one bit per 16x8x8 super-brick when
+    // brick_coarse is asked for and the map fits max_coarse_words (the kernel then reuses the
+    // super-brick index), else the smallest cube side 8, 16 or 32 whose map fits
+    auto coarse_words = [&](int32_t csx, int32_t csyz) {
+        L.csx = csx;
+        L.csyz = csyz;
+        L.CBX = (dims[0] + (1 << csx) - 1) >> csx;
+        L.CBY = (dims[1] + (1 << csyz) - 1) >> csyz;
+        L.CBZ = (dims[2] + (1 << csyz) - 1) >> csyz;
         const int64_t ncb = (int64_t)L.CBX * L.CBY * L.CBZ;
         L.ncoarse_words = (int32_t)(2 * ((ncb + 63) / 64));
-        if (L.ncoarse_words <= max_coarse_words) break;
-    }
-    if (L.cs > 5) return false;
+        return L.ncoarse_words;
+    };
+    bool fits = brick_coarse && coarse_words(4, 3) <= max_coarse_words;
+    for (int32_t c = 3; !fits && c <= 5; ++c) fits = coarse_words(c, c) <= max_coarse_words;
+    if (!fits) return false;
     auto align = [](size_t v) { return (v + 255) & ~size_t(255); };
     L.off_mb = 0;
     L.off_tiles = align(L.off_mb + 8 * (size_t)L.W);
@@ -166,7 +170,8 @@ inline fc::CompactVol compact_view(void *buf, const CompactLayout &L, int32_t N,
     fc::CompactVol cv;
     cv.mb = reinterpret_cast<const uint2 *>(b + L.off_mb);
     cv.coarse = reinterpret_cast<const uint32_t *>(b + L.off_coarse);
-    cv.cs = L.cs;
+    cv.csx = L.csx;
+    cv.csyz = L.csyz;
     cv.CBX = L.CBX;
     cv.CBXY = L.CBX * L.CBY;
     cv.ncoarse_words = L.ncoarse_words;

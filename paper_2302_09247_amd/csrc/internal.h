@@ -32,7 +32,8 @@ struct RasterVol {
 struct CompactVol {
     const uint2 *mb;          // [W] {occupancy word, rank base}
     const uint32_t *coarse;   // one bit per (2^cs)^3 block: any occupied voxel inside
-    int32_t cs;               // log2 of the coarse block side (3, 4 or 5)
+    int32_t csx, csyz;        // log2 of the coarse block's x and y/z sides: 3,3 / 4,4 / 5,5 (cubes) or
+                              // 4,3 (one 16x8x8 super-brick per block, coarse index = super-brick index)
     int32_t CBX, CBXY;        // coarse blocks along x, and per z-slab
     int32_t ncoarse_words;    // words of `coarse` (a multiple of 2)
     const uint32_t *codes32;  // packed (row | label << rbits), if packed

@@ -493,8 +493,8 @@ __global__ void k_compact_codes(uint32_t *__restrict__ mb, const uint32_t *__res
 
 // Coarse occupancy: bit of block (cx, cy, cz) of side 2^cs is set iff an occupancy word covering
 // it has a bit inside it.  One thread per block, 64 blocks per wavefront packed with a ballot.
-__global__ void k_compact_coarse(const uint32_t *__restrict__ mb, int32_t SBX, int32_t SBY, int32_t SBZ, int32_t cs,
-                                 int32_t CBX, int32_t CBY, int32_t CBZ, uint32_t *__restrict__ coarse) {
+__global__ void k_compact_coarse(const uint32_t *__restrict__ mb, int32_t SBX, int32_t SBY, int32_t SBZ, int32_t csx,
+                                 int32_t csyz, int32_t CBX, int32_t CBY, int32_t CBZ, uint32_t *__restrict__ coarse) {
     const int64_t ncb = (int64_t)CBX * CBY * CBZ;
     const int64_t cb = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool occ = false;
@@ -502,13 +502,14 @@ __global__ void k_compact_coarse(const uint32_t *__restrict__ mb, int32_t SBX, i
         const int cx = (int)(cb % CBX);
         const int64_t t = cb / CBX;
         const int cy = (int)(t % CBY), cz = (int)(t / CBY);
-        if (cs == 3) {
+        if (csx == 3) {
             // half of one 16x8x8 super-brick: x in [0,8) are bits 0-7 and 16-23 of each word
             const uint32_t half = (cx & 1) ? 0xFF00FF00u : 0x00FF00FFu;
             const int64_t sb = (cx >> 1) + (int64_t)SBX * (cy + (int64_t)SBY * cz);
             for (int wl = 0; wl < 32; ++wl) occ |= (mb[2 * (sb * 32 + wl)] & half) != 0u;
         } else {
-            const int fx = 1 << (cs - 4), fyz = 1 << (cs - 3);   // super-bricks per block side
+            // whole super-bricks: 1 << (csx - 4) in x, 1 << (csyz - 3) in y and z
+            const int fx = 1 << (csx - 4), fyz = 1 << (csyz - 3);
             for (int sz = cz * fyz; sz < (cz + 1) * fyz && sz < SBZ; ++sz)
                 for (int sy = cy * fyz; sy < (cy + 1) * fyz && sy < SBY; ++sy)
                     for (int sx = cx * fx; sx < (cx + 1) * fx && sx < SBX; ++sx) {
@@ -540,11 +541,10 @@ hipError_t launch_compact_build(const int32_t *roi, const int32_t *lab, Grid g, 
     else
         k_compact_codes<false><<<(unsigned)ntiles, kBlock, 0, st>>>(mb, tile_sums, W, roi, lab, g, cv, SBY, codes);
     const int32_t SBZ = (int32_t)(W / 32 / cv.SBXY);
-    const int32_t c = 1 << cv.cs;
-    const int32_t CBY = (g.Y + c - 1) >> cv.cs, CBZ = (g.Z + c - 1) >> cv.cs;
+    const int32_t CBY = (g.Y + (1 << cv.csyz) - 1) >> cv.csyz, CBZ = (g.Z + (1 << cv.csyz) - 1) >> cv.csyz;
     const int64_t nthreads = (int64_t)cv.ncoarse_words * 32;
-    k_compact_coarse<<<(unsigned)((nthreads + kBlock - 1) / kBlock), kBlock, 0, st>>>(mb, cv.SBX, SBY, SBZ, cv.cs, cv.CBX,
-                                                                                    CBY, CBZ, coarse);
+    k_compact_coarse<<<(unsigned)((nthreads + kBlock - 1) / kBlock), kBlock, 0, st>>>(mb, cv.SBX, SBY, SBZ, cv.csx, cv.csyz,
+                                                                                    cv.CBX, CBY, CBZ, coarse);
     return hipGetLastError();
 }
 
@@ -744,7 +744,7 @@ using StreamSet = DeferredSet<kRCap, kLCap, kTCap>;
 // Counts streamlines [s0, s1) of one subject (whole streamlines only) into sub.C through `sink`.
 // `coarse` is the subject's coarse occupancy map in LDS.  PACKED: 0/1 = code width known at compile
 // time, 2 = read from cv.packed.
-template <bool SCALED, int PACKED, int kBatch, bool kEnds, int kUp>
+template <bool SCALED, int PACKED, int kBatch, bool kEnds, int kUp, bool kBrick>
 __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, int64_t s0, int64_t s1, int32_t subject,
                              const Overflow &ovf, StreamSet &set, BufferedSink &sink) {
     constexpr int kV = kBatch * kUp;   // lookups per batch: kUp sub-points of each of kBatch windows
@@ -759,7 +759,7 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
     const uint32_t lane12 = 12u * (uint32_t)lane;
     const uint32_t bX = fbits(sub.g.Xf), bY = fbits(sub.g.Yf), bZ = fbits(sub.g.Zf);
     const uint32_t SBX = (uint32_t)cv.SBX, SBXY = (uint32_t)cv.SBXY;
-    const uint32_t cs = (uint32_t)cv.cs, CBX = (uint32_t)cv.CBX, CBXY = (uint32_t)cv.CBXY;
+    const uint32_t csx = (uint32_t)cv.csx, csyz = (uint32_t)cv.csyz, CBX = (uint32_t)cv.CBX, CBXY = (uint32_t)cv.CBXY;
     constexpr uint32_t kOutOfRange = 0xFFFFFFF8u;   // buffer offset past every resource: reads 0, no traffic
     const int64_t P0 = uniform64(clamp64(sub.offsets[s0], 0, Ptot));
     const int64_t P1 = uniform64(clamp64(sub.offsets[s1], P0, Ptot));
@@ -914,7 +914,9 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
                 uint32_t sb = __umul24(iz >> 3, SBXY) + __umul24(iy >> 3, SBX) + (ix >> 4);
                 asm("" : "+v"(sb));   // keeps the 24-bit multiplies: (sb << 5) must not fold into them
                 const uint32_t bb = (ix & 15u) | ((iy & 7u) << 4) | ((iz & 7u) << 7);
-                const uint32_t cb = __umul24(iz >> cs, CBXY) + __umul24(iy >> cs, CBX) + (ix >> cs);
+                // coarse block: the super-brick itself (kBrick: the volume's map is per super-brick)
+                // or a cube of 8, 16 or 32
+                const uint32_t cb = kBrick ? sb : __umul24(iz >> csyz, CBXY) + __umul24(iy >> csyz, CBX) + (ix >> csx);
                 const uint32_t cw = coarse[in[v] ? (cb >> 5) : 0u];
                 in[v] = (int)in[v] & (int)((cw >> (cb & 31u)) & 1u);
                 anyc |= in[v];
@@ -1098,7 +1100,7 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
     close_open(vb - 1 + k0);
 }
 
-template <bool SCALED, bool PACKED, int kBatch, bool kEnds>
+template <bool SCALED, bool PACKED, int kBatch, bool kEnds, bool kBrick>
 __global__ void __launch_bounds__(kBlock) k_count_stream(StreamSubject sub, Overflow ovf, const int32_t *__restrict__ first,
                                                          int64_t nparts) {
     __shared__ uint32_t s_set[kWavesPerBlock * kSetWords];
@@ -1120,7 +1122,7 @@ __global__ void __launch_bounds__(kBlock) k_count_stream(StreamSubject sub, Over
         const int64_t s0 = uniform64(clamp64(first[part], 0, sub.S));
         const int64_t s1 = uniform64(clamp64(first[part + 1], s0, sub.S));
         if (s0 >= s1) continue;
-        stream_range<SCALED, PACKED ? 1 : 0, kBatch, kEnds, 1>(sub, s_coarse, s0, s1, 0, ovf, set, sink);
+        stream_range<SCALED, PACKED ? 1 : 0, kBatch, kEnds, 1, kBrick>(sub, s_coarse, s0, s1, 0, ovf, set, sink);
     }
     sink.drain();
 }
@@ -1149,7 +1151,7 @@ __global__ void __launch_bounds__(kBlock) k_count_stream_up(StreamSubject sub, O
         const int64_t s0 = uniform64(clamp64(first[part], 0, sub.S));
         const int64_t s1 = uniform64(clamp64(first[part + 1], s0, sub.S));
         if (s0 >= s1) continue;
-        stream_range<true, 2, kB, false, kUp>(sub, s_coarse, s0, s1, 0, ovf, set, sink);
+        stream_range<true, 2, kB, false, kUp, false>(sub, s_coarse, s0, s1, 0, ovf, set, sink);
     }
     sink.drain();
 }
@@ -1192,7 +1194,7 @@ __global__ void __launch_bounds__(kBlock) k_count_batched(const StreamSubject *_
             loaded = subject;
         }
         sink.C = sub.C;
-        stream_range<true, 2, kBatch, false, 1>(sub, coarse, s0, s1, subject, ovf, set, sink);
+        stream_range<true, 2, kBatch, false, 1, false>(sub, coarse, s0, s1, subject, ovf, set, sink);
         sink.drain();   // the next item may belong to another subject's C
     }
 }
@@ -1201,7 +1203,7 @@ template <bool SCALED, bool PACKED, int B, bool E>
 static int blocks_per_cu_of(size_t dyn) {
     int n = 0;
     const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &n, reinterpret_cast<const void *>(&k_count_stream<SCALED, PACKED, B, E>), kBlock, dyn);
+        &n, reinterpret_cast<const void *>(&k_count_stream<SCALED, PACKED, B, E, true>), kBlock, dyn);
     return (e == hipSuccess && n > 0) ? n : 4;
 }
 
@@ -1242,16 +1244,24 @@ static StreamSubject stream_subject(const CountArgs &a, const CompactVol &cv) {
     return s;
 }
 
-template <int B, bool E>
-static void launch_stream_b(const CountArgs &a, const CompactVol &cv, const int32_t *first, int64_t nparts, int blocks,
-                            hipStream_t st) {
+template <int B, bool E, bool K>
+static void launch_stream_bk(const CountArgs &a, const CompactVol &cv, const int32_t *first, int64_t nparts, int blocks,
+                             hipStream_t st) {
     const bool scaled = a.scale != 1.0f;
     const size_t dyn = 4 * (size_t)cv.ncoarse_words;
     const StreamSubject sub = stream_subject(a, cv);
-    if (scaled && cv.packed) k_count_stream<true, true, B, E><<<blocks, kBlock, dyn, st>>>(sub, a.ovf, first, nparts);
-    else if (scaled) k_count_stream<true, false, B, E><<<blocks, kBlock, dyn, st>>>(sub, a.ovf, first, nparts);
-    else if (cv.packed) k_count_stream<false, true, B, E><<<blocks, kBlock, dyn, st>>>(sub, a.ovf, first, nparts);
-    else k_count_stream<false, false, B, E><<<blocks, kBlock, dyn, st>>>(sub, a.ovf, first, nparts);
+    if (scaled && cv.packed) k_count_stream<true, true, B, E, K><<<blocks, kBlock, dyn, st>>>(sub, a.ovf, first, nparts);
+    else if (scaled) k_count_stream<true, false, B, E, K><<<blocks, kBlock, dyn, st>>>(sub, a.ovf, first, nparts);
+    else if (cv.packed) k_count_stream<false, true, B, E, K><<<blocks, kBlock, dyn, st>>>(sub, a.ovf, first, nparts);
+    else k_count_stream<false, false, B, E, K><<<blocks, kBlock, dyn, st>>>(sub, a.ovf, first, nparts);
+}
+
+// the super-brick coarse map (csx 4, csyz 3) has its own instantiations
+template <int B, bool E>
+static void launch_stream_b(const CountArgs &a, const CompactVol &cv, const int32_t *first, int64_t nparts, int blocks,
+                            hipStream_t st) {
+    if (cv.csx == 4 && cv.csyz == 3) launch_stream_bk<B, E, true>(a, cv, first, nparts, blocks, st);
+    else launch_stream_bk<B, E, false>(a, cv, first, nparts, blocks, st);
 }
 
 hipError_t launch_count_stream(const CountArgs &a, const CompactVol &cv, const int32_t *first, int64_t nparts,
