@@ -60,7 +60,7 @@ class HipEvents:
 
 def kernel_source_sha() -> str:
     h = hashlib.sha256()
-    for f in ("kernels.hip", "internal.h", "api.hip"):
+    for f in ("kernels.hip", "internal.h", "host.h", "api.hip"):
         with open(os.path.join(ROOT, "paper_2302_09247_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
