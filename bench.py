@@ -85,7 +85,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--streamlines", type=int, default=5_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-streamlines", type=int, default=1_500_000)
+    ap.add_argument("--cpu-sample-streamlines", type=int, default=3_000_000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (for rocprofv3 counter scaling)")
     ap.add_argument("--form", choices=("plain", "batched", "served", "sr"), default="plain",
