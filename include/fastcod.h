@@ -83,9 +83,14 @@ typedef struct fastcod_opts {
     int32_t batch;      /* flat-stream schedule: 64-point windows per pipelined batch, 2 or 4; 0 = 4 */
     int32_t blocks_per_cu; /* flat-stream schedule: resident workgroups per CU, 0 = occupancy limit */
     int32_t mode;       /* FASTCOD_MODE_*; the batched and served forms count FASTCOD_MODE_PASSTHROUGH */
+    int64_t pair_capacity; /* flat-stream path: workspace entries (4 bytes each, held twice) for the   */
+                        /* C updates it appends and later adds into C tile by tile; 0 = 8 per       */
+                        /* streamline, clamped to [2^20, 2^28]; values above INT32_MAX are clamped.  */
+                        /* Updates that find their wavefront's share full go to C as atomics: the   */
+                        /* result is the same, only slower.  Must be >= 0.                           */
 } fastcod_opts;
 
-/* Default options: {1.0f, 1, 0, FASTCOD_VARIANT_AUTO, NULL, NULL, 0, 0, FASTCOD_MODE_PASSTHROUGH}. */
+/* Default options: {1.0f, 1, 0, FASTCOD_VARIANT_AUTO, NULL, NULL, 0, 0, FASTCOD_MODE_PASSTHROUGH, 0}. */
 fastcod_opts fastcod_default_opts(void);
 
 /*

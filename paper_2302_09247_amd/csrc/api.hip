@@ -27,8 +27,9 @@ struct Workspace {
     DevBuf ovf;         // overflow counter + queue
     DevBuf fallback;    // fallback scratch (all-zero between launches)
     DevBuf flags;       // validation flags
-    DevBuf ct;          // transposed accumulation copy of C
+    DevBuf ct;          // transposed accumulation copy of C (C beyond the histogram's tiles)
     DevBuf ends;        // per-streamline end labels of the endpoint modes
+    DevBuf pairs;       // appended C updates: slice lengths, tile histogram, slices, sorted copy
 };
 
 std::mutex g_ws_mu;
@@ -55,6 +56,7 @@ int check_stream_args(const float *points, const int64_t *offsets, int64_t S, in
     if (o.batch != 0 && o.batch != 2 && o.batch != 4) return fail(FASTCOD_EINVAL, "batch must be 0, 2 or 4");
     if (o.blocks_per_cu < 0) return fail(FASTCOD_EINVAL, "blocks_per_cu must be >= 0");
     if (o.mode < FASTCOD_MODE_PASSTHROUGH || o.mode > FASTCOD_MODE_SEED_END) return fail(FASTCOD_EINVAL, "unknown mode");
+    if (o.pair_capacity < 0) return fail(FASTCOD_EINVAL, "pair_capacity must be >= 0");
     return FASTCOD_OK;
 }
 
@@ -115,9 +117,14 @@ int enqueue_count(Workspace &ws, int dev, const float *points, const int64_t *of
         if (o.event_end) FC_HIP(hipEventRecord((hipEvent_t)o.event_end, st));
         return FASTCOD_OK;
     }
-    // The flat-stream path accumulates into a transposed workspace copy CT[M][N]: the rows of one
-    // streamline are neighbouring ROI indices, so its pair updates share memory lines there.
-    const bool transposed = cv != nullptr && S > 0 && M > 1 && N >= 64;
+    // The flat-stream path appends its pair updates to per-wavefront slices and adds their
+    // histogram into C tile by tile.  Past kMaxPairTiles tiles it accumulates atomically into a
+    // transposed workspace copy CT[M][N] instead: the rows of one streamline are neighbouring ROI
+    // indices, so its pair updates share memory lines there.
+    const int64_t NM = (int64_t)N * M;
+    const int64_t ntiles = (NM + (1 << fc::kPairTileLog2) - 1) >> fc::kPairTileLog2;
+    const bool append = cv != nullptr && S > 0 && ntiles <= fc::kMaxPairTiles;
+    const bool transposed = !append && cv != nullptr && S > 0 && M > 1 && N >= 64;
     if (!(o.flags & FASTCOD_ACCUMULATE) && !transposed) FC_HIP(fc::launch_fill_i32(C, (int64_t)N * M, 0, cus, st));
     if (S == 0) {
         if (o.event_begin) FC_HIP(hipEventRecord((hipEvent_t)o.event_begin, st));
@@ -170,10 +177,31 @@ int enqueue_count(Workspace &ws, int dev, const float *points, const int64_t *of
         FC_HIP(ws.first.ensure(4 * (size_t)(nparts + 1), false));
         int32_t *first = static_cast<int32_t *>(ws.first.p);
         FC_HIP(fc::launch_partition(offsets, S, nparts, first, cus, st));
+        // pair slices: pair_capacity entries in all (default 8 per streamline, between 2^20 and
+        // 2^28), split evenly between the wavefronts; a full slice sends the rest of its
+        // wavefront's updates to C as atomics
+        const int64_t nwaves = blocks * fc::kWavesPerBlock;
+        int64_t total = o.pair_capacity > 0 ? o.pair_capacity : std::min<int64_t>(std::max<int64_t>(8 * S, 1 << 20), 1 << 28);
+        total = std::min<int64_t>(total, INT32_MAX);
+        const int64_t cap = append ? total / nwaves : 0;
+        auto align = [](size_t v) { return (v + 255) & ~size_t(255); };
+        const size_t off_hist = align(4 * (size_t)nwaves);
+        const size_t off_pairs = align(off_hist + 4 * (size_t)fc::pair_hist_words(ntiles));
+        const size_t off_sorted = align(off_pairs + 4 * (size_t)(nwaves * cap));
+        FC_HIP(ws.pairs.ensure(off_sorted + 4 * (size_t)(nwaves * cap), false));
+        char *pb = static_cast<char *>(ws.pairs.p);
+        fc::PairOut po;
+        po.counts = reinterpret_cast<uint32_t *>(pb);
+        po.pairs = reinterpret_cast<uint32_t *>(pb + off_pairs);
+        po.cap = (uint32_t)cap;
         if (o.event_begin) FC_HIP(hipEventRecord((hipEvent_t)o.event_begin, st));
-        FC_HIP(fc::launch_count_stream(a, *cv, first, nparts, (int)blocks, batch, st));
+        FC_HIP(fc::launch_count_stream(a, *cv, first, nparts, (int)blocks, batch, po, st));
         if (o.event_end) FC_HIP(hipEventRecord((hipEvent_t)o.event_end, st));
         FC_HIP(fc::launch_fallback_compact(a, *cv, fs, st));
+        if (append)
+            FC_HIP(fc::launch_pair_histogram(po, (int32_t)nwaves, (int32_t)ntiles, C, NM,
+                                             reinterpret_cast<uint32_t *>(pb + off_hist),
+                                             reinterpret_cast<uint32_t *>(pb + off_sorted), cus, st));
         if (transposed) FC_HIP(fc::launch_transpose(a.C, C, N, M, (o.flags & FASTCOD_ACCUMULATE) != 0, st));
     } else {
         int64_t blocks = (S + fc::kWavesPerBlock - 1) / fc::kWavesPerBlock;
@@ -515,6 +543,7 @@ fastcod_opts fastcod_default_opts(void) {
     o.batch = 0;
     o.blocks_per_cu = 0;
     o.mode = FASTCOD_MODE_PASSTHROUGH;
+    o.pair_capacity = 0;
     return o;
 }
 

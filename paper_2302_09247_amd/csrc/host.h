@@ -155,6 +155,8 @@ inline bool compact_layout(const int32_t dims[3], int32_t N, int32_t M, CompactL
     L.off_codes = align(L.off_coarse + 4 * (size_t)L.ncoarse_words);
     L.ncodes = L.nvox;
     L.bytes = L.off_codes + (L.packed ? 4 : 8) * (size_t)L.nvox;   // at most every voxel occupied
+    // the counting kernel reads pairs and codes through one buffer resource with 32-bit offsets
+    if (L.bytes >= (size_t(1) << 32) - 16) return false;
     return true;
 }
 
@@ -186,6 +188,8 @@ inline fc::CompactVol compact_view(void *buf, const CompactLayout &L, int32_t N,
     cv.packed = L.packed ? 1 : 0;
     cv.W = L.W;
     cv.ncodes = L.ncodes;
+    cv.codes_off = (uint32_t)L.off_codes;
+    cv.span = (uint32_t)(L.off_codes + (L.packed ? 4 : 8) * (size_t)L.ncodes);
     return cv;
 }
 

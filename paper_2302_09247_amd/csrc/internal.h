@@ -45,10 +45,29 @@ struct CompactVol {
     int32_t packed;
     int64_t W;                // occupancy words
     int64_t ncodes;           // capacity of the code array (bounds of every code read)
+    uint32_t codes_off;       // byte offset of the code array from mb (one allocation)
+    uint32_t span;            // bytes from mb to the end of the code array (< 2^32 - 16)
 };
 
 // Streamlines whose distinct (row, label) keys outgrow the per-wave LDS set are handed to a
 // fallback kernel through this queue of point indices (one point inside each such streamline).
+// Per-wavefront slices of appended C updates (flat-stream kernel, plain path): wavefront w writes
+// its entries to pairs[w * cap ...] and their number to counts[w]; cap 0 = every update is an atomic.
+struct PairOut {
+    uint32_t *pairs;
+    uint32_t *counts;
+    uint32_t cap;
+};
+
+// Histogram of the appended updates into C, tile by tile in LDS.
+constexpr int kPairTileLog2 = 14;                   // 16K counters (64 KB of LDS) per tile of C
+constexpr int kMaxPairTiles = 4096;                 // up to 2^26 entries of C take this path
+// workgroups of the histogram and scatter passes: fewer for many tiles (each keeps ntiles offsets)
+inline int pair_hist_blocks(int64_t ntiles) {
+    const int64_t b = (int64_t(1) << 22) / (ntiles > 0 ? ntiles : 1);
+    return (int)(b < 64 ? 64 : (b > 1024 ? 1024 : b));
+}
+
 struct Overflow {
     unsigned long long *count;
     int64_t *list;
@@ -135,7 +154,15 @@ hipError_t launch_count_seed_end(const CountArgs &a, const RasterVol *rv, const 
 // wavefronts take the nparts ranges of `first` from ovf.work; batch: 64-point windows per
 // pipelined batch (2 or 4)
 hipError_t launch_count_stream(const CountArgs &a, const CompactVol &cv, const int32_t *first, int64_t nparts,
-                               int blocks, int batch, hipStream_t st);
+                               int blocks, int batch, const PairOut &po, hipStream_t st);
+// C[NM] += histogram of the updates in the slices (nwaves slices of po.cap entries, lengths in
+// po.counts), ntiles = ceil(NM / 16K).  hist: pair_hist_words(ntiles) words; sorted: nwaves * po.cap
+// words.
+hipError_t launch_pair_histogram(const PairOut &po, int32_t nwaves, int32_t ntiles, int32_t *C, int64_t NM,
+                                 uint32_t *hist, uint32_t *sorted, int cus, hipStream_t st);
+inline int64_t pair_hist_words(int64_t ntiles) {
+    return 32 * (int64_t)kMaxPairTiles + kMaxPairTiles + 64 + pair_hist_blocks(ntiles) * ntiles;
+}
 hipError_t launch_fallback_raster(const CountArgs &a, const RasterVol &rv, FallbackScratch fs,
                                   hipStream_t st);
 hipError_t launch_fallback_compact(const CountArgs &a, const CompactVol &cv, FallbackScratch fs,

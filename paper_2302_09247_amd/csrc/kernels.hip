@@ -231,6 +231,55 @@ struct BufferedSink {
     }
 };
 
+// C updates appended, 64 at a time, to this wavefront's slice of a pair buffer (coalesced
+// non-temporal stores), for a later histogram pass.  Stores are acknowledged once the cache takes
+// them, whereas an atomic must first fetch its line of C: on this architecture every later vector
+// memory wait also waits for it.  Once the slice is full, updates go to C as atomics.
+struct AppendSink {
+    uint32_t *buf;   // [kWave] LDS
+    int n;           // pending entries (wave-uniform)
+    uint32_t *out;   // next free entry of this wavefront's slice
+    uint32_t room;   // free entries left in the slice
+    int32_t *C;
+    __device__ void init(uint32_t *b, int32_t *c, const PairOut &po, uint32_t wave) {
+        buf = b;
+        n = 0;
+        C = c;
+        out = po.pairs + (size_t)wave * po.cap;
+        room = po.cap;
+    }
+    __device__ void emit(int cnt) {   // the first cnt (<= 64) entries of buf
+        const int lane = lane_id();
+        if ((uint32_t)cnt <= room) {
+            if (lane < cnt) __builtin_nontemporal_store(buf[lane], out + lane);
+            out += cnt;
+            room -= (uint32_t)cnt;
+        } else if (lane < cnt) {
+            atomicAdd(C + buf[lane], 1);
+        }
+    }
+    __device__ void push(bool valid, uint32_t idx) {
+        const uint64_t vm = __ballot(valid);
+        if (!vm) return;
+        const int pos = n + mbcnt(vm);
+        if (valid && pos < kWave) buf[pos] = idx;
+        const int cnt = __popcll(vm);
+        if (n + cnt >= kWave) {
+            emit(kWave);
+            if (valid && pos >= kWave) buf[pos - kWave] = idx;
+            n = n + cnt - kWave;
+        } else {
+            n += cnt;
+        }
+    }
+    // flushes the pending entries and records the slice's length
+    __device__ void drain(const PairOut &po, uint32_t wave) {
+        if (n) emit(n);
+        n = 0;
+        if (lane_id() == 0) po.counts[wave] = po.cap - room;
+    }
+};
+
 // Per-wavefront state of the flat-stream kernel's open streamline: raw candidate lists (hits
 // that differ from the previous point's), de-duplicated only when the streamline closes and only
 // if it has both rows and labels.  tab is an open-addressing set, empty between closes; it holds
@@ -744,20 +793,21 @@ using StreamSet = DeferredSet<kRCap, kLCap, kTCap>;
 // Counts streamlines [s0, s1) of one subject (whole streamlines only) into sub.C through `sink`.
 // `coarse` is the subject's coarse occupancy map in LDS.  PACKED: 0/1 = code width known at compile
 // time, 2 = read from cv.packed.
-template <bool SCALED, int PACKED, int kBatch, bool kEnds, int kUp, bool kBrick>
+template <bool SCALED, int PACKED, int kBatch, bool kEnds, int kUp, bool kBrick, typename Sink>
 __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, int64_t s0, int64_t s1, int32_t subject,
-                             const Overflow &ovf, StreamSet &set, BufferedSink &sink) {
+                             const Overflow &ovf, StreamSet &set, Sink &sink) {
     constexpr int kV = kBatch * kUp;   // lookups per batch: kUp sub-points of each of kBatch windows
     const int lane = lane_id();
     const CompactVol &cv = sub.cv;
     const int64_t S = sub.S;
     const int64_t Ptot = uniform64(sub.offsets[S] > 0 ? sub.offsets[S] : 0);
-    const bool packed = PACKED == 1 || (PACKED == 2 && cv.packed);
-    const __amdgpu_buffer_rsrc_t rmb = make_rsrc(cv.mb, 8ull * cv.W);
-    const __amdgpu_buffer_rsrc_t rcode = make_rsrc(packed ? (const void *)cv.codes32 : (const void *)cv.codes64,
-                                                   (packed ? 4ull : 8ull) * cv.ncodes);
+    // occupancy pairs and codes share one allocation and one resource (codes at cv.codes_off)
+    const __amdgpu_buffer_rsrc_t rvol = make_rsrc(cv.mb, cv.span);
+    const int codes_off = uniform32((int)cv.codes_off);
     const uint32_t lane12 = 12u * (uint32_t)lane;
-    const uint32_t bX = fbits(sub.g.Xf), bY = fbits(sub.g.Yf), bZ = fbits(sub.g.Zf);
+    // the grid bounds live in VGPRs: as scalars they crowd out the loop's lane masks
+    uint32_t bX = fbits(sub.g.Xf), bY = fbits(sub.g.Yf), bZ = fbits(sub.g.Zf);
+    asm volatile("" : "+v"(bX), "+v"(bY), "+v"(bZ));
     const uint32_t SBX = (uint32_t)cv.SBX, SBXY = (uint32_t)cv.SBXY;
     const uint32_t csx = (uint32_t)cv.csx, csyz = (uint32_t)cv.csyz, CBX = (uint32_t)cv.CBX, CBXY = (uint32_t)cv.CBXY;
     constexpr uint32_t kOutOfRange = 0xFFFFFFF8u;   // buffer offset past every resource: reads 0, no traffic
@@ -869,12 +919,12 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
         const uint32_t left = L - w0;
         const int rem = left > BW ? (int)BW : (int)left;          // valid points in this batch
         const int remn = left > BW ? (int)BW + 1 : (int)left;     // lane + 1 < remn: a next point exists
-        // phase 1: voxelise and test the coarse occupancy bit in LDS; only points in occupied
-        // coarse blocks gather their occupancy word and rank base (8 bytes).  Lookup v = b*kUp + t
-        // is sub-point t of window b.
-        uint32_t word[kV], bit[kV];
-        bool in[kV];
-        bool anyc = false;
+        // phase 1: voxelise and test the coarse occupancy bit in LDS; only lookups in occupied
+        // coarse blocks gather their occupancy word and rank base (8 bytes): the others read past
+        // the resource (zero, no traffic), so the gathered word alone decides the hit.  Lookup
+        // v = b*kUp + t is sub-point t of window b.
+        uint32_t addr[kV], bix[kV];
+        uint64_t anyc = 0ull;
 #pragma unroll
         for (int b = 0; b < kBatch; ++b) {
             float qx = ax[b], qy = ay[b], qz = az[b];
@@ -907,31 +957,31 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
                 const float tx = __fadd_rn(x, 0.5f), ty = __fadd_rn(y, 0.5f), tz = __fadd_rn(z, 0.5f);
                 // 0 <= t < bound  <=>  bits(t) < bits(bound) as unsigned (t is never -0; NaN and
                 // negative values compare above every finite positive bound)
-                const int valid = t == 0 ? (int)(lane + b * kWave < rem)
-                                         : (int)(t < up) & (int)(lane + b * kWave + 1 < remn);
-                in[v] = (int)(fbits(tx) < bX) & (int)(fbits(ty) < bY) & (int)(fbits(tz) < bZ) & valid;
+                // (bitwise & throughout: no short-circuit branches)
+                const int valid = t == 0 ? (int)(lane + b * kWave < rem) : (int)(t < up) & (int)(lane + b * kWave + 1 < remn);
+                const bool ok = valid & (int)(fbits(tx) < bX) & (int)(fbits(ty) < bY) & (int)(fbits(tz) < bZ);
                 const uint32_t ix = (uint32_t)(int)tx, iy = (uint32_t)(int)ty, iz = (uint32_t)(int)tz;
                 uint32_t sb = __umul24(iz >> 3, SBXY) + __umul24(iy >> 3, SBX) + (ix >> 4);
-                asm("" : "+v"(sb));   // keeps the 24-bit multiplies: (sb << 5) must not fold into them
-                const uint32_t bb = (ix & 15u) | ((iy & 7u) << 4) | ((iz & 7u) << 7);
+                asm("" : "+v"(sb));   // keeps the 24-bit multiplies: (sb << 8) must not fold into them
                 // coarse block: the super-brick itself (kBrick: the volume's map is per super-brick)
                 // or a cube of 8, 16 or 32
                 const uint32_t cb = kBrick ? sb : __umul24(iz >> csyz, CBXY) + __umul24(iy >> csyz, CBX) + (ix >> csx);
-                const uint32_t cw = coarse[in[v] ? (cb >> 5) : 0u];
-                in[v] = (int)in[v] & (int)((cw >> (cb & 31u)) & 1u);
-                anyc |= in[v];
-                word[v] = in[v] ? ((sb << 5) | (bb >> 5)) : 0u;
-                bit[v] = bb & 31u;
+                const uint32_t cw = coarse[ok ? (cb >> 5) : 0u];
+                const bool hit = (int)ok & (int)(__builtin_amdgcn_ubfe(cw, cb, 1) != 0u);   // bfe: offset mod 32
+                anyc |= __ballot(hit);
+                // byte offset of the (word, base) pair: 32 words of 16x2x1 voxels per super-brick,
+                // word (y/2 mod 4) + 4 (z mod 8), bit (x mod 16) + 16 (y mod 2)
+                addr[v] = hit ? (sb << 8) | ((iy << 2) & 0x18u) | ((iz << 5) & 0xE0u) : kOutOfRange;
+                bix[v] = (ix & 15u) | ((iy & 1u) << 4);
             }
         }
         uint32_t mw[kV], rank[kV];
 #pragma unroll
         for (int v = 0; v < kV; ++v) mw[v] = rank[v] = 0u;
-        if (__ballot(anyc)) {
+        if (anyc) {
 #pragma unroll
             for (int v = 0; v < kV; ++v) {
-                const auto e = __builtin_amdgcn_raw_buffer_load_b64(rmb, in[v] ? (word[v] << 3) : kOutOfRange, 0,
-                                                                    kAuxCached);
+                const auto e = __builtin_amdgcn_raw_buffer_load_b64(rvol, addr[v], 0, kAuxCached);
                 mw[v] = e[0];
                 rank[v] = e[1];
             }
@@ -940,7 +990,7 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
         bool any = false;
 #pragma unroll
         for (int v = 0; v < kV; ++v) {
-            flag[v] = in[v] && ((mw[v] >> bit[v]) & 1u);
+            flag[v] = __builtin_amdgcn_ubfe(mw[v], bix[v], 1) != 0u;
             any |= flag[v];
         }
         // The point registers are free since phase 1: the next batch's loads are issued after this
@@ -951,15 +1001,15 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
 #pragma unroll
         for (int v = 0; v < kV; ++v) r[v] = m[v] = -1;
         if (__ballot(any)) {
-            // phase 2: codes of the flagged voxels (other lanes read entry 0)
+            // phase 2: codes of the flagged voxels.  Other lanes read entry 0 (no word: base 0) or an
+            // entry of their word at most one past the last code (beyond the resource: zero)
 #pragma unroll
-            for (int v = 0; v < kV; ++v)
-                rank[v] = flag[v] ? rank[v] + __popc(mw[v] & ((1u << bit[v]) - 1u)) : 0u;
+            for (int v = 0; v < kV; ++v) rank[v] += __popc(__builtin_amdgcn_ubfe(mw[v], 0, bix[v]));
             if (PACKED == 1 || (PACKED == 2 && cv.packed)) {
                 uint32_t code[kV];
 #pragma unroll
                 for (int v = 0; v < kV; ++v)
-                    code[v] = __builtin_amdgcn_raw_buffer_load_b32(rcode, rank[v] << 2, 0, kAuxCached);
+                    code[v] = __builtin_amdgcn_raw_buffer_load_b32(rvol, rank[v] << 2, codes_off, kAuxCached);
                 __builtin_amdgcn_sched_barrier(0);
                 load_batch(w2);
                 __builtin_amdgcn_sched_barrier(0);
@@ -973,7 +1023,7 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
                 uint32_t c0[kV], c1[kV];
 #pragma unroll
                 for (int v = 0; v < kV; ++v) {
-                    const auto c2 = __builtin_amdgcn_raw_buffer_load_b64(rcode, rank[v] << 3, 0, kAuxCached);
+                    const auto c2 = __builtin_amdgcn_raw_buffer_load_b64(rvol, rank[v] << 3, codes_off, kAuxCached);
                     c0[v] = c2[0];
                     c1[v] = c2[1];
                 }
@@ -1102,7 +1152,7 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
 
 template <bool SCALED, bool PACKED, int kBatch, bool kEnds, bool kBrick>
 __global__ void __launch_bounds__(kBlock) k_count_stream(StreamSubject sub, Overflow ovf, const int32_t *__restrict__ first,
-                                                         int64_t nparts) {
+                                                         int64_t nparts, PairOut po) {
     __shared__ uint32_t s_set[kWavesPerBlock * kSetWords];
     __shared__ uint32_t s_pend[kWavesPerBlock * kWave];
     extern __shared__ uint32_t s_coarse[];   // coarse occupancy bit map, cv.ncoarse_words words
@@ -1111,8 +1161,9 @@ __global__ void __launch_bounds__(kBlock) k_count_stream(StreamSubject sub, Over
     __syncthreads();
     StreamSet set;
     set.init(s_set + wv * kSetWords);
-    BufferedSink sink;
-    sink.init(s_pend + wv * kWave, sub.C);
+    const uint32_t wave = blockIdx.x * kWavesPerBlock + wv;
+    AppendSink sink;
+    sink.init(s_pend + wv * kWave, sub.C, po, wave);
     for (;;) {
         // next point range: streamlines [first[part], first[part+1])
         unsigned long long t = 0;
@@ -1124,14 +1175,14 @@ __global__ void __launch_bounds__(kBlock) k_count_stream(StreamSubject sub, Over
         if (s0 >= s1) continue;
         stream_range<SCALED, PACKED ? 1 : 0, kBatch, kEnds, 1, kBrick>(sub, s_coarse, s0, s1, 0, ovf, set, sink);
     }
-    sink.drain();
+    sink.drain(po, wave);
 }
 
 // Upsampled pass-through (up = 2 .. kUp): the scale is always applied (multiplying by 1.0f is
 // exact) and the code width is read from the volume, so two instantiations cover every case.
 template <int kUp>
 __global__ void __launch_bounds__(kBlock) k_count_stream_up(StreamSubject sub, Overflow ovf,
-                                                            const int32_t *__restrict__ first, int64_t nparts) {
+                                                            const int32_t *__restrict__ first, int64_t nparts, PairOut po) {
     constexpr int kB = kUp == 2 ? 2 : 1;   // kB * kUp lookups per batch, as the plain kernel's 4
     __shared__ uint32_t s_set[kWavesPerBlock * kSetWords];
     __shared__ uint32_t s_pend[kWavesPerBlock * kWave];
@@ -1141,8 +1192,9 @@ __global__ void __launch_bounds__(kBlock) k_count_stream_up(StreamSubject sub, O
     __syncthreads();
     StreamSet set;
     set.init(s_set + wv * kSetWords);
-    BufferedSink sink;
-    sink.init(s_pend + wv * kWave, sub.C);
+    const uint32_t wave = blockIdx.x * kWavesPerBlock + wv;
+    AppendSink sink;
+    sink.init(s_pend + wv * kWave, sub.C, po, wave);
     for (;;) {
         unsigned long long t = 0;
         if (lane == 0) t = atomicAdd(ovf.work, 1ull);
@@ -1153,7 +1205,7 @@ __global__ void __launch_bounds__(kBlock) k_count_stream_up(StreamSubject sub, O
         if (s0 >= s1) continue;
         stream_range<true, 2, kB, false, kUp, false>(sub, s_coarse, s0, s1, 0, ovf, set, sink);
     }
-    sink.drain();
+    sink.drain(po, wave);
 }
 
 // Batched form: work items (subject, first streamline) from every subject, handed out by one
@@ -1170,6 +1222,7 @@ __global__ void __launch_bounds__(kBlock) k_count_batched(const StreamSubject *_
     uint32_t *coarse = s_coarse + wv * coarse_words;
     StreamSet set;
     set.init(s_set + wv * kSetWords);
+    // updates go to C as atomics: with many hits per point, this form's cost is the hit processing
     BufferedSink sink;
     sink.init(s_pend + wv * kWave, nullptr);
     int loaded = -1;
@@ -1246,40 +1299,40 @@ static StreamSubject stream_subject(const CountArgs &a, const CompactVol &cv) {
 
 template <int B, bool E, bool K>
 static void launch_stream_bk(const CountArgs &a, const CompactVol &cv, const int32_t *first, int64_t nparts, int blocks,
-                             hipStream_t st) {
+                             const PairOut &po, hipStream_t st) {
     const bool scaled = a.scale != 1.0f;
     const size_t dyn = 4 * (size_t)cv.ncoarse_words;
     const StreamSubject sub = stream_subject(a, cv);
-    if (scaled && cv.packed) k_count_stream<true, true, B, E, K><<<blocks, kBlock, dyn, st>>>(sub, a.ovf, first, nparts);
-    else if (scaled) k_count_stream<true, false, B, E, K><<<blocks, kBlock, dyn, st>>>(sub, a.ovf, first, nparts);
-    else if (cv.packed) k_count_stream<false, true, B, E, K><<<blocks, kBlock, dyn, st>>>(sub, a.ovf, first, nparts);
-    else k_count_stream<false, false, B, E, K><<<blocks, kBlock, dyn, st>>>(sub, a.ovf, first, nparts);
+    if (scaled && cv.packed) k_count_stream<true, true, B, E, K><<<blocks, kBlock, dyn, st>>>(sub, a.ovf, first, nparts, po);
+    else if (scaled) k_count_stream<true, false, B, E, K><<<blocks, kBlock, dyn, st>>>(sub, a.ovf, first, nparts, po);
+    else if (cv.packed) k_count_stream<false, true, B, E, K><<<blocks, kBlock, dyn, st>>>(sub, a.ovf, first, nparts, po);
+    else k_count_stream<false, false, B, E, K><<<blocks, kBlock, dyn, st>>>(sub, a.ovf, first, nparts, po);
 }
 
 // the super-brick coarse map (csx 4, csyz 3) has its own instantiations
 template <int B, bool E>
 static void launch_stream_b(const CountArgs &a, const CompactVol &cv, const int32_t *first, int64_t nparts, int blocks,
-                            hipStream_t st) {
-    if (cv.csx == 4 && cv.csyz == 3) launch_stream_bk<B, E, true>(a, cv, first, nparts, blocks, st);
-    else launch_stream_bk<B, E, false>(a, cv, first, nparts, blocks, st);
+                            const PairOut &po, hipStream_t st) {
+    if (cv.csx == 4 && cv.csyz == 3) launch_stream_bk<B, E, true>(a, cv, first, nparts, blocks, po, st);
+    else launch_stream_bk<B, E, false>(a, cv, first, nparts, blocks, po, st);
 }
 
 hipError_t launch_count_stream(const CountArgs &a, const CompactVol &cv, const int32_t *first, int64_t nparts,
-                               int blocks, int batch, hipStream_t st) {
+                               int blocks, int batch, const PairOut &po, hipStream_t st) {
     if (a.up > 1) {
         const size_t dyn = 4 * (size_t)cv.ncoarse_words;
         const StreamSubject sub = stream_subject(a, cv);
-        if (a.up == 2) k_count_stream_up<2><<<blocks, kBlock, dyn, st>>>(sub, a.ovf, first, nparts);
-        else k_count_stream_up<4><<<blocks, kBlock, dyn, st>>>(sub, a.ovf, first, nparts);
+        if (a.up == 2) k_count_stream_up<2><<<blocks, kBlock, dyn, st>>>(sub, a.ovf, first, nparts, po);
+        else k_count_stream_up<4><<<blocks, kBlock, dyn, st>>>(sub, a.ovf, first, nparts, po);
         return hipGetLastError();
     }
     const bool ends = a.ends.mode != 0;
     if (batch == 2) {
-        if (ends) launch_stream_b<2, true>(a, cv, first, nparts, blocks, st);
-        else launch_stream_b<2, false>(a, cv, first, nparts, blocks, st);
+        if (ends) launch_stream_b<2, true>(a, cv, first, nparts, blocks, po, st);
+        else launch_stream_b<2, false>(a, cv, first, nparts, blocks, po, st);
     } else {
-        if (ends) launch_stream_b<4, true>(a, cv, first, nparts, blocks, st);
-        else launch_stream_b<4, false>(a, cv, first, nparts, blocks, st);
+        if (ends) launch_stream_b<4, true>(a, cv, first, nparts, blocks, po, st);
+        else launch_stream_b<4, false>(a, cv, first, nparts, blocks, po, st);
     }
     return hipGetLastError();
 }
@@ -1681,6 +1734,186 @@ hipError_t launch_transpose(const int32_t *CT, int32_t *C, int32_t N, int32_t M,
     const dim3 grid((unsigned)((N + 31) / 32), (unsigned)((M + 31) / 32));
     if (accumulate) k_transpose<true><<<grid, 256, 0, st>>>(CT, C, N, M);
     else k_transpose<false><<<grid, 256, 0, st>>>(CT, C, N, M);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------------
+// histogram of appended C updates: a counting sort by tile of C, then one LDS histogram per tile
+// ---------------------------------------------------------------------------------------------
+
+constexpr uint32_t kNoEntry = 0xFFFFFFFFu;   // never an update (updates index C: < 2^31)
+constexpr int kPairUnroll = 8;               // independent loads in flight per thread
+
+// Slices [w0, w1) of workgroup b out of nblk.
+__device__ __forceinline__ void slice_range(int32_t nwaves, int b, int nblk, int32_t &w0, int32_t &w1) {
+    w0 = (int32_t)((int64_t)nwaves * b / nblk);
+    w1 = (int32_t)((int64_t)nwaves * (b + 1) / nblk);
+}
+
+constexpr int kMaxSlicesPerBlock = 64;   // nblk >= nwaves / 64 (checked by the launcher)
+
+// Calls f(entry) for every update in this workgroup's slices, taken as one flat index range (pre:
+// LDS prefix of the slice lengths) so that every thread keeps kPairUnroll loads in flight.
+template <typename F>
+__device__ __forceinline__ void for_each_update(const PairOut &po, int32_t nwaves, uint32_t *pre, F &&f) {
+    int32_t w0, w1;
+    slice_range(nwaves, blockIdx.x, gridDim.x, w0, w1);
+    const int ns = w1 - w0;
+    if (threadIdx.x < (unsigned)ns) pre[threadIdx.x + 1] = min(po.counts[w0 + threadIdx.x], po.cap);
+    if (threadIdx.x == 0) pre[0] = 0u;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int k = 1; k <= ns; ++k) pre[k] += pre[k - 1];
+    __syncthreads();
+    const uint32_t total = pre[ns];
+    for (uint32_t k0 = threadIdx.x; k0 < total; k0 += kPairUnroll * blockDim.x) {
+        uint32_t v[kPairUnroll];
+#pragma unroll
+        for (int j = 0; j < kPairUnroll; ++j) {
+            const uint32_t k = k0 + j * blockDim.x;
+            v[j] = kNoEntry;
+            if (k < total) {
+                int lo = 0, hi = ns - 1;   // the slice holding flat index k: pre[lo] <= k < pre[lo + 1]
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (pre[mid] <= k) lo = mid;
+                    else hi = mid - 1;
+                }
+                v[j] = __builtin_nontemporal_load(po.pairs + (size_t)(w0 + lo) * po.cap + (k - pre[lo]));
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kPairUnroll; ++j)
+            if (v[j] != kNoEntry) f(v[j]);
+    }
+}
+
+// Tile histogram of workgroup b's updates; reserves b's run inside each tile with one atomic on
+// the tile's cursor (cursors one 128-byte line apart): boff[b * ntiles + t] = offset of the run.
+__global__ void __launch_bounds__(1024) k_pair_tile_counts(PairOut po, int32_t nwaves, int32_t ntiles,
+                                                           uint32_t *__restrict__ cursor, uint32_t *__restrict__ boff) {
+    __shared__ uint32_t h[kMaxPairTiles];
+    __shared__ uint32_t pre[kMaxSlicesPerBlock + 1];
+    for (int t = threadIdx.x; t < ntiles; t += blockDim.x) h[t] = 0u;
+    __syncthreads();
+    for_each_update(po, nwaves, pre, [&](uint32_t e) {
+        const uint32_t t = e >> kPairTileLog2;
+        if (t < (uint32_t)ntiles) atomicAdd(&h[t], 1u);
+    });
+    __syncthreads();
+    for (int t = threadIdx.x; t < ntiles; t += blockDim.x)
+        boff[(size_t)blockIdx.x * ntiles + t] = h[t] ? atomicAdd(&cursor[32 * t], h[t]) : 0u;
+}
+
+// base[t] = exclusive scan of the tile totals (cursor[32 t]), base[ntiles] = the total; one
+// workgroup of 1024 threads, ntiles <= kMaxPairTiles.
+__global__ void __launch_bounds__(1024) k_pair_tile_base(const uint32_t *__restrict__ cursor, int32_t ntiles,
+                                                         uint32_t *__restrict__ base) {
+    __shared__ uint32_t part[1024];
+    constexpr int kPer = kMaxPairTiles / 1024;
+    uint32_t v[kPer];
+    uint32_t sum = 0u;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int t = threadIdx.x * kPer + j;
+        v[j] = t < ntiles ? cursor[32 * t] : 0u;
+        sum += v[j];
+    }
+    part[threadIdx.x] = sum;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {   // inclusive scan of the per-thread sums
+        const uint32_t x = threadIdx.x >= (unsigned)d ? part[threadIdx.x - d] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += x;
+        __syncthreads();
+    }
+    uint32_t run = part[threadIdx.x] - sum;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int t = threadIdx.x * kPer + j;
+        if (t < ntiles) base[t] = run;
+        run += v[j];
+    }
+    if (threadIdx.x == 1023) base[ntiles] = part[1023];
+}
+
+// Each update into its tile's run of `sorted`, at workgroup b's reserved offset.
+__global__ void __launch_bounds__(1024) k_pair_scatter(PairOut po, int32_t nwaves, int32_t ntiles,
+                                                       const uint32_t *__restrict__ base,
+                                                       const uint32_t *__restrict__ boff, uint32_t *__restrict__ sorted) {
+    __shared__ uint32_t cur[kMaxPairTiles];
+    __shared__ uint32_t pre[kMaxSlicesPerBlock + 1];
+    for (int t = threadIdx.x; t < ntiles; t += blockDim.x) cur[t] = base[t] + boff[(size_t)blockIdx.x * ntiles + t];
+    __syncthreads();
+    for_each_update(po, nwaves, pre, [&](uint32_t e) {
+        const uint32_t t = e >> kPairTileLog2;
+        // a cached store: a workgroup's updates of one tile land side by side, and the cache merges
+        // them into whole lines before they go to memory
+        if (t < (uint32_t)ntiles) sorted[atomicAdd(&cur[t], 1u)] = e;
+    });
+}
+
+// One workgroup per tile: C[tile] += the histogram of the tile's updates.
+__global__ void __launch_bounds__(512) k_pair_tile_add(const uint32_t *__restrict__ sorted,
+                                                       const uint32_t *__restrict__ base, int32_t *__restrict__ Cm,
+                                                       int64_t NM) {
+    constexpr uint32_t kTile = 1u << kPairTileLog2;
+    __shared__ uint32_t h[kTile];
+    for (uint32_t k = threadIdx.x; k < kTile; k += blockDim.x) h[k] = 0u;
+    __syncthreads();
+    const uint32_t b = base[blockIdx.x], e = base[blockIdx.x + 1];
+    for (uint32_t k0 = b + threadIdx.x; k0 < e; k0 += kPairUnroll * blockDim.x) {
+        uint32_t v[kPairUnroll];
+#pragma unroll
+        for (int j = 0; j < kPairUnroll; ++j) {
+            const uint32_t k = k0 + j * blockDim.x;
+            v[j] = k < e ? __builtin_nontemporal_load(sorted + k) : kNoEntry;
+        }
+#pragma unroll
+        for (int j = 0; j < kPairUnroll; ++j)
+            if (v[j] != kNoEntry) atomicAdd(&h[v[j] & (kTile - 1u)], 1u);
+    }
+    __syncthreads();
+    const int64_t t0 = (int64_t)blockIdx.x << kPairTileLog2;
+    int32_t *C = Cm + t0;   // the tile's entries of C
+    const uint32_t len = (uint32_t)min((int64_t)kTile, NM - t0);
+    if (len == kTile && (reinterpret_cast<uintptr_t>(C) & 15u) == 0) {
+        // whole tile: four entries per thread and step, all loads of C first
+        constexpr int kSteps = kTile / (4 * 512);
+        int4 c[kSteps];
+        int4 *C4 = reinterpret_cast<int4 *>(C);
+        const uint4 *h4 = reinterpret_cast<const uint4 *>(h);
+#pragma unroll
+        for (int j = 0; j < kSteps; ++j) c[j] = C4[threadIdx.x + j * 512];
+#pragma unroll
+        for (int j = 0; j < kSteps; ++j) {
+            const uint4 a = h4[threadIdx.x + j * 512];
+            c[j].x += (int)a.x;
+            c[j].y += (int)a.y;
+            c[j].z += (int)a.z;
+            c[j].w += (int)a.w;
+            C4[threadIdx.x + j * 512] = c[j];
+        }
+    } else {
+        for (uint32_t k = threadIdx.x; k < len; k += blockDim.x) C[k] += (int32_t)h[k];
+    }
+}
+
+hipError_t launch_pair_histogram(const PairOut &po, int32_t nwaves, int32_t ntiles, int32_t *C, int64_t NM,
+                                 uint32_t *hist, uint32_t *sorted, int cus, hipStream_t st) {
+    if (ntiles < 1 || ntiles > kMaxPairTiles || nwaves < 1) return hipErrorInvalidValue;
+    const int nblk = pair_hist_blocks(ntiles);
+    if ((int64_t)nblk * kMaxSlicesPerBlock < nwaves) return hipErrorInvalidValue;
+    // hist: cursors (32 words per tile) | tile bases (ntiles + 1) | per-workgroup offsets
+    uint32_t *cursor = hist;
+    uint32_t *base = cursor + 32 * (size_t)kMaxPairTiles;
+    uint32_t *boff = base + kMaxPairTiles + 64;
+    const hipError_t fe = launch_fill_i32(reinterpret_cast<int32_t *>(cursor), 32 * (int64_t)ntiles, 0, cus, st);
+    if (fe != hipSuccess) return fe;
+    k_pair_tile_counts<<<nblk, 1024, 0, st>>>(po, nwaves, ntiles, cursor, boff);
+    k_pair_tile_base<<<1, 1024, 0, st>>>(cursor, ntiles, base);
+    k_pair_scatter<<<nblk, 1024, 0, st>>>(po, nwaves, ntiles, base, boff, sorted);
+    k_pair_tile_add<<<ntiles, 512, 0, st>>>(sorted, base, C, NM);
     return hipGetLastError();
 }
 

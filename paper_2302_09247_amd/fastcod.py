@@ -44,7 +44,8 @@ class FastcodError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("scale", ctypes.c_float), ("upsample", ctypes.c_int32), ("flags", ctypes.c_uint32),
                 ("variant", ctypes.c_int32), ("event_begin", ctypes.c_void_p), ("event_end", ctypes.c_void_p),
-                ("batch", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32), ("mode", ctypes.c_int32)]
+                ("batch", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32), ("mode", ctypes.c_int32),
+                ("pair_capacity", ctypes.c_int64)]
 
 
 class Subject(ctypes.Structure):
@@ -170,7 +171,7 @@ def _dev(t: torch.Tensor, dtype, name: str, shape=None) -> torch.Tensor:
 
 def make_opts(scale: float = 1.0, upsample: int = 1, accumulate: bool = False, validate: bool = False,
               variant: int = VARIANT_AUTO, events: Optional[Tuple[int, int]] = None, batch: int = 0,
-              blocks_per_cu: int = 0, mode: int = MODE_PASSTHROUGH) -> Opts:
+              blocks_per_cu: int = 0, mode: int = MODE_PASSTHROUGH, pair_capacity: int = 0) -> Opts:
     o = load().fastcod_default_opts()
     o.scale = float(scale)
     o.upsample = int(upsample)
@@ -181,6 +182,7 @@ def make_opts(scale: float = 1.0, upsample: int = 1, accumulate: bool = False, v
     o.batch = int(batch)
     o.blocks_per_cu = int(blocks_per_cu)
     o.mode = int(mode)
+    o.pair_capacity = int(pair_capacity)
     return o
 
 
@@ -188,7 +190,7 @@ def count(points: torch.Tensor, offsets: torch.Tensor, roi: torch.Tensor, lab: t
           scale: float = 1.0, upsample: int = 1, accumulate: bool = False, validate: bool = False,
           variant: int = VARIANT_AUTO, out: Optional[torch.Tensor] = None, stream=None,
           events: Optional[Tuple[int, int]] = None, batch: int = 0,
-          blocks_per_cu: int = 0, mode: int = MODE_PASSTHROUGH) -> torch.Tensor:
+          blocks_per_cu: int = 0, mode: int = MODE_PASSTHROUGH, pair_capacity: int = 0) -> torch.Tensor:
     """C[N, M] (int32, on the points' device) of the pass-through definition (fastcod_count_ex).
 
     points [P,3] float32, offsets [S+1] int64, roi/lab [Z,Y,X] int32, all on one HIP device.
@@ -206,7 +208,7 @@ def count(points: torch.Tensor, offsets: torch.Tensor, roi: torch.Tensor, lab: t
     if tuple(out.shape) != (N, M):
         raise ValueError("out must be [N, M]")
     dims = (ctypes.c_int32 * 3)(int(roi.shape[2]), int(roi.shape[1]), int(roi.shape[0]))
-    o = make_opts(scale, upsample, accumulate, validate, variant, events, batch, blocks_per_cu, mode)
+    o = make_opts(scale, upsample, accumulate, validate, variant, events, batch, blocks_per_cu, mode, pair_capacity)
     S = int(offsets.shape[0]) - 1
     with torch.cuda.device(points.device):
         _check(lib.fastcod_count_ex(_points_ptr(points), offsets.data_ptr(), S, roi.data_ptr(), lab.data_ptr(),
@@ -241,7 +243,8 @@ class Volume:
         return int(load().fastcod_volume_bytes(self._h))
 
     def count(self, points: torch.Tensor, offsets: torch.Tensor, *, scale: float = 1.0, accumulate: bool = False,
-              out: Optional[torch.Tensor] = None, stream=None, events=None, mode: int = MODE_PASSTHROUGH) -> torch.Tensor:
+              out: Optional[torch.Tensor] = None, stream=None, events=None, mode: int = MODE_PASSTHROUGH,
+              pair_capacity: int = 0) -> torch.Tensor:
         lib = load()
         _dev(points, torch.float32, "points", (3,))
         _dev(offsets, torch.int64, "offsets")
@@ -249,7 +252,7 @@ class Volume:
             out = (torch.empty if not accumulate else torch.zeros)((self.N, self.M), dtype=torch.int32,
                                                                   device=points.device)
         _dev(out, torch.int32, "out")
-        o = make_opts(scale, 1, accumulate, False, VARIANT_STREAM, events, mode=mode)
+        o = make_opts(scale, 1, accumulate, False, VARIANT_STREAM, events, mode=mode, pair_capacity=pair_capacity)
         with torch.cuda.device(points.device):
             _check(lib.fastcod_volume_count(self._h, _points_ptr(points), offsets.data_ptr(),
                                             int(offsets.shape[0]) - 1, out.data_ptr(), ctypes.byref(o),

@@ -39,6 +39,8 @@ def test_strerror_and_default_opts(lib):
     assert lib.fastcod_strerror(12345) == b"unknown status"
     o = lib.fastcod_default_opts()
     assert (o.scale, o.upsample, o.flags, o.variant) == (1.0, 1, 0, 0)
+    assert (o.batch, o.blocks_per_cu, o.mode, o.pair_capacity) == (0, 0, 0, 0)
+    assert ctypes.sizeof(fastcod.Opts) == 56   # 4+4+4+4 + 8+8 + 4+4+4 (+4 padding) + 8
 
 
 def _count(lib, dims=(4, 4, 4), N=3, M=2, S=1, pts=1, off=1, roi=1, lab=1, C=1, opts=None):
@@ -64,7 +66,7 @@ def test_bad_arguments_are_rejected_synchronously(lib, kw):
 
 @pytest.mark.parametrize("field,value", [("upsample", 5), ("upsample", 0), ("mode", 4), ("mode", -1), ("scale", 0.0),
                                          ("scale", float("nan")), ("scale", float("inf")), ("variant", 7),
-                                         ("batch", 8), ("blocks_per_cu", -1)])
+                                         ("batch", 8), ("blocks_per_cu", -1), ("pair_capacity", -1)])
 def test_bad_options_are_rejected(lib, field, value):
     o = lib.fastcod_default_opts()
     setattr(o, field, value)
