@@ -1001,10 +1001,10 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
 #pragma unroll
         for (int v = 0; v < kV; ++v) r[v] = m[v] = -1;
         if (__ballot(any)) {
-            // phase 2: codes of the flagged voxels.  Other lanes read entry 0 (no word: base 0) or an
-            // entry of their word at most one past the last code (beyond the resource: zero)
+            // phase 2: codes of the flagged voxels; the other lanes all read entry 0 (one line for
+            // the whole wavefront rather than one per lane)
 #pragma unroll
-            for (int v = 0; v < kV; ++v) rank[v] += __popc(__builtin_amdgcn_ubfe(mw[v], 0, bix[v]));
+            for (int v = 0; v < kV; ++v) rank[v] = flag[v] ? rank[v] + __popc(__builtin_amdgcn_ubfe(mw[v], 0, bix[v])) : 0u;
             if (PACKED == 1 || (PACKED == 2 && cv.packed)) {
                 uint32_t code[kV];
 #pragma unroll

@@ -133,4 +133,3 @@ def test_count_batched_one_shot(fc, subjects):
         d["C"].fill_(-1)
     fc.count_batched(subjects)
     _check_all(subjects)
-
