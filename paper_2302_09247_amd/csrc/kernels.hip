@@ -435,21 +435,44 @@ hipError_t launch_fill_u64(unsigned long long *p, int64_t n, int cus, hipStream_
 // ---------------------------------------------------------------------------------------------
 
 // one thread per voxel (coalesced reads of both volumes); occupied voxels set their bit
+// Sets the occupancy bit of voxel lin (0 <= roi < N or 0 <= lab < M).
+__device__ __forceinline__ void mark_voxel(int32_t lin, int32_t r, int32_t m, const Grid &g, int32_t N, int32_t M,
+                                           int32_t SBX, int32_t SBXY, uint32_t *mb) {
+    if ((unsigned)r < (unsigned)N || (unsigned)m < (unsigned)M) {
+        const int32_t t = lin / g.X;
+        const int x = lin - t * g.X;
+        const int y = t % g.Y;
+        const int z = t / g.Y;
+        const uint32_t sb = (uint32_t)(x >> 4) + (uint32_t)SBX * (uint32_t)(y >> 3) + (uint32_t)SBXY * (uint32_t)(z >> 3);
+        const uint32_t b = (uint32_t)(x & 15) | ((uint32_t)(y & 7) << 4) | ((uint32_t)(z & 7) << 7);
+        atomicOr(&mb[2 * ((sb << 5) | (b >> 5))], 1u << (b & 31u));
+    }
+}
+
+// One pass over both volumes (X*Y*Z < 2^31): four voxels per thread and step with 16-byte loads
+// when both volumes are 16-byte aligned (VEC), else one.
+template <bool VEC>
 __global__ void k_compact_mark(const int32_t *__restrict__ roi, const int32_t *__restrict__ lab, Grid g,
                                int32_t N, int32_t M, int32_t SBX, int32_t SBXY, uint32_t *__restrict__ mb) {
-    const int64_t nvox = (int64_t)g.X * g.Y * g.Z;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t lin = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; lin < nvox; lin += stride) {
-        const int32_t r = roi[lin], m = lab[lin];
-        if ((unsigned)r < (unsigned)N || (unsigned)m < (unsigned)M) {
-            const int x = (int)(lin % g.X);
-            const int64_t t = lin / g.X;
-            const int y = (int)(t % g.Y);
-            const int z = (int)(t / g.Y);
-            const uint32_t sb = (uint32_t)(x >> 4) + (uint32_t)SBX * (uint32_t)(y >> 3) + (uint32_t)SBXY * (uint32_t)(z >> 3);
-            const uint32_t b = (uint32_t)(x & 15) | ((uint32_t)(y & 7) << 4) | ((uint32_t)(z & 7) << 7);
-            atomicOr(&mb[2 * ((sb << 5) | (b >> 5))], 1u << (b & 31u));
+    const int32_t nvox = g.X * g.Y * g.Z;
+    const int32_t stride = gridDim.x * blockDim.x;
+    if (VEC) {
+        const int32_t n4 = nvox >> 2;
+        typedef int32_t v4i __attribute__((ext_vector_type(4)));
+        const v4i *r4 = reinterpret_cast<const v4i *>(roi);
+        const v4i *m4 = reinterpret_cast<const v4i *>(lab);
+        for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
+            const v4i r = __builtin_nontemporal_load(r4 + i), m = __builtin_nontemporal_load(m4 + i);
+            mark_voxel(4 * i, r.x, m.x, g, N, M, SBX, SBXY, mb);
+            mark_voxel(4 * i + 1, r.y, m.y, g, N, M, SBX, SBXY, mb);
+            mark_voxel(4 * i + 2, r.z, m.z, g, N, M, SBX, SBXY, mb);
+            mark_voxel(4 * i + 3, r.w, m.w, g, N, M, SBX, SBXY, mb);
         }
+        for (int32_t lin = 4 * n4 + blockIdx.x * blockDim.x + threadIdx.x; lin < nvox; lin += stride)
+            mark_voxel(lin, roi[lin], lab[lin], g, N, M, SBX, SBXY, mb);
+    } else {
+        for (int32_t lin = blockIdx.x * blockDim.x + threadIdx.x; lin < nvox; lin += stride)
+            mark_voxel(lin, roi[lin], lab[lin], g, N, M, SBX, SBXY, mb);
     }
 }
 
@@ -497,10 +520,8 @@ __global__ void k_compact_scan_tiles(uint32_t *__restrict__ tile_sums, int64_t n
     }
 }
 
-template <bool PACKED>
-__global__ void k_compact_codes(uint32_t *__restrict__ mb, const uint32_t *__restrict__ tile_base, int64_t W,
-                                const int32_t *__restrict__ roi, const int32_t *__restrict__ lab, Grid g, CompactVol cv,
-                                int32_t SBY, void *__restrict__ codes) {
+// Rank base of every occupancy word: the number of occupied voxels in the words before it.
+__global__ void k_compact_bases(uint32_t *__restrict__ mb, const uint32_t *__restrict__ tile_base, int64_t W) {
     __shared__ uint32_t lds4[4];
     const int64_t w0 = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kWordsPerThread;
     uint32_t words[kWordsPerThread];
@@ -512,30 +533,61 @@ __global__ void k_compact_codes(uint32_t *__restrict__ mb, const uint32_t *__res
     uint32_t total;
     uint32_t run = tile_base[blockIdx.x] + block_scan_incl(s, lds4, total) - s;
     for (int k = 0; k < kWordsPerThread; ++k) {
-        const int64_t w = w0 + k;
-        if (w >= W) break;
-        mb[2 * w + 1] = run;
-        uint32_t bits = words[k];
-        const uint32_t sb = (uint32_t)(w >> 5), wl = (uint32_t)(w & 31);
-        const int sbx = (int)(sb % (uint32_t)cv.SBX);
-        const int sby = (int)((sb / (uint32_t)cv.SBX) % (uint32_t)SBY);
-        const int sbz = (int)(sb / (uint32_t)cv.SBXY);
-        while (bits) {
-            const uint32_t j = __builtin_ctz(bits);
-            bits &= bits - 1u;
-            const uint32_t b = (wl << 5) | j;
-            const int x = sbx * 16 + (int)(b & 15u), y = sby * 8 + (int)((b >> 4) & 7u), z = sbz * 8 + (int)(b >> 7);
-            const int64_t lin = (int64_t)x + (int64_t)g.X * ((int64_t)y + (int64_t)g.Y * z);
-            const int32_t r = roi[lin], m = lab[lin];
-            const bool rv = (unsigned)r < (unsigned)cv.N, mv = (unsigned)m < (unsigned)cv.M;
-            if (PACKED) {
-                const uint32_t rf = rv ? (uint32_t)r : cv.rmask;
-                const uint32_t mf = mv ? (uint32_t)m : (0xFFFFFFFFu >> cv.rbits);
-                static_cast<uint32_t *>(codes)[run] = rf | (mf << cv.rbits);
-            } else {
-                static_cast<int2 *>(codes)[run] = make_int2(rv ? r : -1, mv ? m : -1);
+        if (w0 + k >= W) break;
+        mb[2 * (w0 + k) + 1] = run;
+        run += __popc(words[k]);
+    }
+}
+
+// Codes of the occupied voxels, in rank order.  A wavefront takes 64 words at a time and fills the
+// occupied ones two by two: word w covers x in [16 sbx, 16 sbx + 16) of rows y and y + 1 (y even) of
+// one z, so its 32 lanes read two runs of 16 consecutive voxels.
+template <bool PACKED>
+__global__ void k_compact_fill_codes(const uint32_t *__restrict__ mb, int64_t W, const int32_t *__restrict__ roi,
+                                     const int32_t *__restrict__ lab, Grid g, CompactVol cv, int32_t SBY,
+                                     void *__restrict__ codes) {
+    const int lane = lane_id();
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / kWave);
+    for (int64_t grp = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x >> 6); grp * kWave < W; grp += nwaves) {
+        const int64_t w = grp * kWave + lane;
+        uint32_t word = 0u, base = 0u;
+        if (w < W) {
+            word = mb[2 * w];
+            base = mb[2 * w + 1];
+        }
+        uint64_t todo = __ballot(word != 0u);
+        while (todo) {
+            const int ka = __builtin_ctzll(todo);
+            todo &= todo - 1ull;
+            const int kb = todo ? __builtin_ctzll(todo) : ka;   // second word of the pair (or the first again)
+            if (todo) todo &= todo - 1ull;
+            const bool upper = lane >= 32;
+            const int k = upper ? kb : ka;
+            const uint32_t wda = (uint32_t)__builtin_amdgcn_readlane((int)word, ka);
+            const uint32_t wdb = (uint32_t)__builtin_amdgcn_readlane((int)word, kb);
+            const uint32_t bsa = (uint32_t)__builtin_amdgcn_readlane((int)base, ka);
+            const uint32_t bsb = (uint32_t)__builtin_amdgcn_readlane((int)base, kb);
+            const uint32_t wd = upper ? wdb : wda, bs = upper ? bsb : bsa;
+            const uint32_t j = (uint32_t)lane & 31u;
+            if (((wd >> j) & 1u) && !(upper && kb == ka)) {
+                const uint32_t ww = (uint32_t)(grp * kWave + k);
+                const uint32_t sb = ww >> 5, wl = ww & 31u;
+                const uint32_t b = (wl << 5) | j;
+                const int x = (int)(sb % (uint32_t)cv.SBX) * 16 + (int)(b & 15u);
+                const int y = (int)((sb / (uint32_t)cv.SBX) % (uint32_t)SBY) * 8 + (int)((b >> 4) & 7u);
+                const int z = (int)(sb / (uint32_t)cv.SBXY) * 8 + (int)(b >> 7);
+                const int64_t lin = (int64_t)x + (int64_t)g.X * ((int64_t)y + (int64_t)g.Y * z);
+                const int32_t r = roi[lin], m = lab[lin];
+                const bool rv = (unsigned)r < (unsigned)cv.N, mv = (unsigned)m < (unsigned)cv.M;
+                const uint32_t at = bs + __popc(wd & ((1u << j) - 1u));
+                if (PACKED) {
+                    const uint32_t rf = rv ? (uint32_t)r : cv.rmask;
+                    const uint32_t mf = mv ? (uint32_t)m : (0xFFFFFFFFu >> cv.rbits);
+                    static_cast<uint32_t *>(codes)[at] = rf | (mf << cv.rbits);
+                } else {
+                    static_cast<int2 *>(codes)[at] = make_int2(rv ? r : -1, mv ? m : -1);
+                }
             }
-            ++run;
         }
     }
 }
@@ -582,13 +634,16 @@ hipError_t launch_compact_build(const int32_t *roi, const int32_t *lab, Grid g, 
     const int32_t SBY = cv.SBXY / cv.SBX;
     k_fill_i32<<<fill_blocks(2 * W, cus), kBlock, 0, st>>>(reinterpret_cast<int32_t *>(mb), 2 * W, 0);
     const int64_t nvox = (int64_t)g.X * g.Y * g.Z;
-    k_compact_mark<<<fill_blocks(nvox, cus * 2), kBlock, 0, st>>>(roi, lab, g, N, M, cv.SBX, cv.SBXY, mb);
+    const bool vec = ((reinterpret_cast<uintptr_t>(roi) | reinterpret_cast<uintptr_t>(lab)) & 15u) == 0;
+    if (vec) k_compact_mark<true><<<fill_blocks(nvox / 4, cus * 2), kBlock, 0, st>>>(roi, lab, g, N, M, cv.SBX, cv.SBXY, mb);
+    else k_compact_mark<false><<<fill_blocks(nvox, cus * 2), kBlock, 0, st>>>(roi, lab, g, N, M, cv.SBX, cv.SBXY, mb);
     k_compact_tile_sums<<<(unsigned)ntiles, kBlock, 0, st>>>(mb, W, tile_sums);
     k_compact_scan_tiles<<<1, kBlock, 0, st>>>(tile_sums, ntiles);
-    if (cv.packed)
-        k_compact_codes<true><<<(unsigned)ntiles, kBlock, 0, st>>>(mb, tile_sums, W, roi, lab, g, cv, SBY, codes);
-    else
-        k_compact_codes<false><<<(unsigned)ntiles, kBlock, 0, st>>>(mb, tile_sums, W, roi, lab, g, cv, SBY, codes);
+    k_compact_bases<<<(unsigned)ntiles, kBlock, 0, st>>>(mb, tile_sums, W);
+    const int64_t groups = (W + kWave - 1) / kWave;
+    const unsigned fblocks = (unsigned)std::min<int64_t>((groups + kWavesPerBlock - 1) / kWavesPerBlock, (int64_t)cus * 8);
+    if (cv.packed) k_compact_fill_codes<true><<<fblocks, kBlock, 0, st>>>(mb, W, roi, lab, g, cv, SBY, codes);
+    else k_compact_fill_codes<false><<<fblocks, kBlock, 0, st>>>(mb, W, roi, lab, g, cv, SBY, codes);
     const int32_t SBZ = (int32_t)(W / 32 / cv.SBXY);
     const int32_t CBY = (g.Y + (1 << cv.csyz) - 1) >> cv.csyz, CBZ = (g.Z + (1 << cv.csyz) - 1) >> cv.csyz;
     const int64_t nthreads = (int64_t)cv.ncoarse_words * 32;
