@@ -168,7 +168,7 @@ int enqueue_count(Workspace &ws, int dev, const float *points, const int64_t *of
     FC_HIP(fc::launch_fill_u64(a.ovf.count, 2, cus, st));   // overflow count and range counter
     const int64_t resident = (int64_t)cus * kBlocksPerCU;
     if (cv) {
-        const int batch = o.batch == 2 ? 2 : 4;
+        const int batch = o.batch == 4 ? 4 : 2;
         int per_cu = fc::count_stream_blocks_per_cu(o.scale != 1.0f, cv->packed != 0, batch, a.ends.mode != 0,
                                                     a.up, 4 * (size_t)cv->ncoarse_words);
         if (o.blocks_per_cu > 0 && o.blocks_per_cu < per_cu) per_cu = o.blocks_per_cu;

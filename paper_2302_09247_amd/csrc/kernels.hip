@@ -970,16 +970,16 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
             }
         }
     };
-    auto run_batch = [&](uint32_t w0) {
-        const uint32_t left = L - w0;
+    // Lookup stage of the batch at w0 (its points are in ax.. / nx..): gather offsets and bit
+    // indices.
+    auto lookup = [&](uint32_t w0, uint32_t (&addr)[kV], uint32_t (&bix)[kV]) {
+        const uint32_t left = w0 < L ? L - w0 : 0u;
         const int rem = left > BW ? (int)BW : (int)left;          // valid points in this batch
         const int remn = left > BW ? (int)BW + 1 : (int)left;     // lane + 1 < remn: a next point exists
         // phase 1: voxelise and test the coarse occupancy bit in LDS; only lookups in occupied
         // coarse blocks gather their occupancy word and rank base (8 bytes): the others read past
         // the resource (zero, no traffic), so the gathered word alone decides the hit.  Lookup
         // v = b*kUp + t is sub-point t of window b.
-        uint32_t addr[kV], bix[kV];
-        uint64_t anyc = 0ull;
 #pragma unroll
         for (int b = 0; b < kBatch; ++b) {
             float qx = ax[b], qy = ay[b], qz = az[b];
@@ -1023,79 +1023,26 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
                 const uint32_t cb = kBrick ? sb : __umul24(iz >> csyz, CBXY) + __umul24(iy >> csyz, CBX) + (ix >> csx);
                 const uint32_t cw = coarse[ok ? (cb >> 5) : 0u];
                 const bool hit = (int)ok & (int)(__builtin_amdgcn_ubfe(cw, cb, 1) != 0u);   // bfe: offset mod 32
-                anyc |= __ballot(hit);
                 // byte offset of the (word, base) pair: 32 words of 16x2x1 voxels per super-brick,
                 // word (y/2 mod 4) + 4 (z mod 8), bit (x mod 16) + 16 (y mod 2)
                 addr[v] = hit ? (sb << 8) | ((iy << 2) & 0x18u) | ((iz << 5) & 0xE0u) : kOutOfRange;
                 bix[v] = (ix & 15u) | ((iy & 1u) << 4);
             }
         }
-        uint32_t mw[kV], rank[kV];
-#pragma unroll
-        for (int v = 0; v < kV; ++v) mw[v] = rank[v] = 0u;
-        if (anyc) {
-#pragma unroll
-            for (int v = 0; v < kV; ++v) {
-                const auto e = __builtin_amdgcn_raw_buffer_load_b64(rvol, addr[v], 0, kAuxCached);
-                mw[v] = e[0];
-                rank[v] = e[1];
-            }
-        }
-        bool flag[kV];
-        bool any = false;
+    };
+    // (word, base) pairs of a batch's lookups.  Always issued: lanes that failed the coarse test
+    // read past the resource (zero, no traffic), so every path through the loop issues the same
+    // vector-memory sequence and each wait covers exactly what it needs.
+    auto gather_pairs = [&](const uint32_t (&addr)[kV], uint32_t (&mw)[kV], uint32_t (&base)[kV]) {
 #pragma unroll
         for (int v = 0; v < kV; ++v) {
-            flag[v] = __builtin_amdgcn_ubfe(mw[v], bix[v], 1) != 0u;
-            any |= flag[v];
+            const auto e = __builtin_amdgcn_raw_buffer_load_b64(rvol, addr[v], 0, kAuxCached);
+            mw[v] = e[0];
+            base[v] = e[1];
         }
-        // The point registers are free since phase 1: the next batch's loads are issued after this
-        // batch's code gathers and before their results are used (loads return in issue order, so
-        // waiting for the codes does not wait for the stream).
-        const uint32_t w2 = w0 + BW;
-        int r[kV], m[kV];
-#pragma unroll
-        for (int v = 0; v < kV; ++v) r[v] = m[v] = -1;
-        if (__ballot(any)) {
-            // phase 2: codes of the flagged voxels; the other lanes all read entry 0 (one line for
-            // the whole wavefront rather than one per lane)
-#pragma unroll
-            for (int v = 0; v < kV; ++v) rank[v] = flag[v] ? rank[v] + __popc(__builtin_amdgcn_ubfe(mw[v], 0, bix[v])) : 0u;
-            if (PACKED == 1 || (PACKED == 2 && cv.packed)) {
-                uint32_t code[kV];
-#pragma unroll
-                for (int v = 0; v < kV; ++v)
-                    code[v] = __builtin_amdgcn_raw_buffer_load_b32(rvol, rank[v] << 2, codes_off, kAuxCached);
-                __builtin_amdgcn_sched_barrier(0);
-                load_batch(w2);
-                __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                for (int v = 0; v < kV; ++v) {
-                    const uint32_t rv = code[v] & cv.rmask, mv = code[v] >> cv.rbits;
-                    r[v] = (flag[v] && rv < (uint32_t)cv.N) ? (int)rv : -1;
-                    m[v] = (flag[v] && mv < (uint32_t)cv.M) ? (int)mv : -1;
-                }
-            } else {
-                uint32_t c0[kV], c1[kV];
-#pragma unroll
-                for (int v = 0; v < kV; ++v) {
-                    const auto c2 = __builtin_amdgcn_raw_buffer_load_b64(rvol, rank[v] << 3, codes_off, kAuxCached);
-                    c0[v] = c2[0];
-                    c1[v] = c2[1];
-                }
-                __builtin_amdgcn_sched_barrier(0);
-                load_batch(w2);
-                __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                for (int v = 0; v < kV; ++v) {
-                    r[v] = flag[v] ? (int)c0[v] : -1;
-                    m[v] = flag[v] ? (int)c1[v] : -1;
-                }
-            }
-        } else {
-            __builtin_amdgcn_sched_barrier(0);
-            load_batch(w2);
-            __builtin_amdgcn_sched_barrier(0);
-        }
+    };
+    // The rest of a batch once its codes are in: candidates, streamline starts and closes.
+    auto tail = [&](uint32_t w0, const int (&r)[kV], const int (&m)[kV], const bool (&flag)[kV]) {
         uint64_t fl[kBatch];
         uint64_t fall = 0;
 #pragma unroll
@@ -1200,8 +1147,76 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
             }
         }
     };
-    load_batch(0u);
-    for (uint32_t w0 = 0; w0 < L; w0 += BW) run_batch(w0);
+    // Software pipeline over batches k: the pair gathers of batch k + 1 are in flight while batch k's
+    // codes return and its tail runs.  Vector-memory loads complete in issue order, so each
+    // iteration issues: the codes of k, the pairs of k + 1, the points of k + 2; batch k's decode
+    // then waits for its codes only, and the next iteration's flags for the pairs of k + 1 only.
+    const bool packed = PACKED == 1 || (PACKED == 2 && cv.packed);
+    const uint32_t code_oob = kOutOfRange - (uint32_t)codes_off;   // with the code offset: past the resource
+    uint32_t bix[kV], mw[kV], rank[kV];
+    {
+        uint32_t addr[kV];
+        load_batch(0u);
+        lookup(0u, addr, bix);
+        __builtin_amdgcn_sched_barrier(0);
+        gather_pairs(addr, mw, rank);
+        __builtin_amdgcn_sched_barrier(0);
+        load_batch(BW);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    for (uint32_t w0 = 0; w0 < L; w0 += BW) {
+        // flags of batch k and its code gathers (unflagged lanes read past the resource)
+        bool flag[kV];
+#pragma unroll
+        for (int v = 0; v < kV; ++v) flag[v] = __builtin_amdgcn_ubfe(mw[v], bix[v], 1) != 0u;
+        uint32_t c0[kV], c1[kV];
+#pragma unroll
+        for (int v = 0; v < kV; ++v) {
+            const uint32_t at = rank[v] + __popc(__builtin_amdgcn_ubfe(mw[v], 0, bix[v]));
+            if (packed) {
+                c0[v] = __builtin_amdgcn_raw_buffer_load_b32(rvol, flag[v] ? at << 2 : code_oob, codes_off, kAuxCached);
+                c1[v] = 0u;
+            } else {
+                const auto c2 = __builtin_amdgcn_raw_buffer_load_b64(rvol, flag[v] ? at << 3 : code_oob, codes_off,
+                                                                     kAuxCached);
+                c0[v] = c2[0];
+                c1[v] = c2[1];
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        // lookups and pair gathers of batch k + 1 (its points arrived during the last iteration),
+        // then the points of batch k + 2 into the registers the lookups just freed
+        uint32_t bix2[kV], mw2[kV], rank2[kV];
+        {
+            uint32_t addr[kV];
+            lookup(w0 + BW, addr, bix2);
+            __builtin_amdgcn_sched_barrier(0);
+            gather_pairs(addr, mw2, rank2);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        load_batch(w0 + 2 * BW);
+        __builtin_amdgcn_sched_barrier(0);
+        // codes of batch k
+        int r[kV], m[kV];
+#pragma unroll
+        for (int v = 0; v < kV; ++v) {
+            if (packed) {
+                const uint32_t rv = c0[v] & cv.rmask, mv = c0[v] >> cv.rbits;
+                r[v] = (flag[v] && rv < (uint32_t)cv.N) ? (int)rv : -1;
+                m[v] = (flag[v] && mv < (uint32_t)cv.M) ? (int)mv : -1;
+            } else {
+                r[v] = flag[v] ? (int)c0[v] : -1;
+                m[v] = flag[v] ? (int)c1[v] : -1;
+            }
+        }
+        tail(w0, r, m, flag);
+#pragma unroll
+        for (int v = 0; v < kV; ++v) {
+            bix[v] = bix2[v];
+            mw[v] = mw2[v];
+            rank[v] = rank2[v];
+        }
+    }
     close_open(vb - 1 + k0);
 }
 

@@ -106,3 +106,25 @@ def test_large_C_takes_the_atomic_path(fc):
     assert int(C.sum(dtype=torch.int64).item()) == int(exp.sum())
     del C
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("batch", [2, 4])
+def test_both_batch_sizes(fc, batch):
+    # the flat-stream loop's two schedules (64-point windows per pipelined batch), every mode, with
+    # upsampling, and with slices small enough to overflow
+    w = synth.make_tiny64(seed=16, S=12_000)
+    g = w.to("cuda")
+    for mode in (0, 1, 2):
+        exp = oracle.count(w.points, w.offsets, w.roi, w.lab, w.N, w.M, mode=mode)
+        for cap in (0, 500):
+            np.testing.assert_array_equal(_run(fc, g, mode=mode, batch=batch, pair_capacity=cap), exp,
+                                          err_msg=f"mode {mode} capacity {cap}")
+    exp = oracle.count(w.points, w.offsets, w.roi, w.lab, w.N, w.M, scale=1.25, upsample=2)
+    C = fc.count(g.points, g.offsets, g.roi, g.lab, g.N, g.M, scale=1.25, upsample=2, variant=2, batch=batch)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(C.cpu().numpy().astype(np.int64), exp)
+    for seed in range(4):
+        s = synth.random_small(seed, dims=[(12, 10, 9), (70, 9, 11)][seed % 2], S=300, max_len=400,
+                               bad_values=(seed % 2 == 0))
+        exp = oracle.count(s.points, s.offsets, s.roi, s.lab, s.N, s.M)
+        np.testing.assert_array_equal(_run(fc, s.to("cuda"), batch=batch), exp, err_msg=f"seed {seed}")
