@@ -179,7 +179,22 @@ def main():
                   "frac_of_peak": p_bytes / (p_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS}
     log(f"parcellate: {p_ms * 1e3:.1f} us, {parcellate['GBps']:.0f} GB/s")
 
-    cpu = None
+    # stream-copy ceiling on this device: a 4 GiB device-to-device copy (read + write bytes / time)
+    ca = torch.empty(1 << 30, dtype=torch.float32, device="cuda")
+    cb = torch.empty_like(ca)
+    cb.copy_(ca)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        cb.copy_(ca)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbps = 5 * 2 * 4 * (1 << 30) / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del ca, cb
+    log(f"device copy: {copy_gbps:.0f} GB/s (read + write)")
+
+    cpu = cpu_parallel = None
     if not args.no_cpu_baseline:
         import oracle
         ns = min(args.cpu_sample_streamlines, S)
@@ -194,6 +209,14 @@ def main():
                "sample": f"first {ns} of {S} streamlines ({p_end} points) of the same workload, "
                          f"single-threaded C oracle, {dt:.1f} s on {os.cpu_count()} visible host CPUs"}
         log(f"cpu oracle: {p_end / dt:.3e} points/s over {dt:.1f}s")
+        # the same sample on all host cores (the oracle is additive over streamline ranges)
+        workers = max(1, min(16, os.cpu_count() or 1))
+        t0 = time.perf_counter()
+        oracle.count_chunked(pts, off, roi, lab, w.N, w.M, streamlines_per_chunk=1 << 16, workers=workers)
+        dtp = time.perf_counter() - t0
+        cpu_parallel = {"value": p_end / dtp, "unit": "points/s", "cores": workers, "kind": "oracle",
+                        "sample": f"the same {p_end} points, 2^16-streamline ranges on {workers} threads, {dtp:.1f} s"}
+        log(f"cpu oracle on {workers} threads: {p_end / dtp:.3e} points/s over {dtp:.1f}s")
 
     out = {
         "metric": "streamline points/s into bit-exact C[NxM]; HBM GB/s as % of MI355X peak",
@@ -215,8 +238,10 @@ def main():
                    "parallelism": "1 GPU"},
         "roofline": {"bound": "hbm", "kernel": KERNEL_NAME, "achieved": achieved, "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic_per_launch(),
-                     "kernel_ms": k_ms, "algorithmic_bytes": alg_bytes},
+                     "kernel_ms": k_ms, "algorithmic_bytes": alg_bytes,
+                     "copy_GBps": copy_gbps},
         "cpu_baseline": cpu,
+        "cpu_baseline_all_cores": cpu_parallel,
         "parcellate": parcellate,
     }
     print(json.dumps(out), flush=True)
