@@ -945,8 +945,8 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
     const __amdgpu_buffer_rsrc_t rp = make_rsrc(sub.pts + 3 * P0, 12ull * L);
     constexpr uint32_t BW = kWave * kBatch;   // points per batch
 
-    // one register set of points: batch k+1 is issued into it once batch k's gathers have
-    // returned, and streams in while batch k is folded into the set
+    // one register set of points: the lookup stage of a batch consumes it, and the points of the
+    // batch after next are then loaded into it (see the pipeline below)
     // kUp > 1: each lane also holds the next point (the same load one point further on: it hits
     // the lines the window itself brings in)
     constexpr int kNext = kUp > 1 ? kBatch : 1;
@@ -976,9 +976,9 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
         const uint32_t left = w0 < L ? L - w0 : 0u;
         const int rem = left > BW ? (int)BW : (int)left;          // valid points in this batch
         const int remn = left > BW ? (int)BW + 1 : (int)left;     // lane + 1 < remn: a next point exists
-        // phase 1: voxelise and test the coarse occupancy bit in LDS; only lookups in occupied
-        // coarse blocks gather their occupancy word and rank base (8 bytes): the others read past
-        // the resource (zero, no traffic), so the gathered word alone decides the hit.  Lookup
+        // voxelise and test the coarse occupancy bit in LDS; only lookups in occupied coarse
+        // blocks gather their occupancy word and rank base (8 bytes): the others read past the
+        // resource (zero, no traffic), so the gathered word alone decides the hit.  Lookup
         // v = b*kUp + t is sub-point t of window b.
 #pragma unroll
         for (int b = 0; b < kBatch; ++b) {
