@@ -47,7 +47,7 @@ def test_rounding_pins_brute_agrees():
 
 LINES = [
     # origin, step, T, dims, M
-    ((Fractionless := None) or (0.25, 2.0, 1.0), (0.5, 0.0, 0.0), 23, (13, 4, 3), 4),
+    ((0.25, 2.0, 1.0), (0.5, 0.0, 0.0), 23, (13, 4, 3), 4),
     ((1.0, -0.25, 2.0), (0.0, 0.5, 0.0), 17, (3, 9, 4), 3),
     ((1.0, 2.0, -0.75), (0.0, 0.0, 0.5), 21, (3, 4, 10), 5),
     ((0.125, 0.375, 0.0625), (0.25, 0.25, 0.25), 40, (11, 12, 13), 6),
