@@ -6,7 +6,6 @@ equality of every element.  Every kernel variant must agree.  Sizes: small cases
 (the 0.7 mm one in the launch configuration the benchmark times), the super-resolution job,
 overflow of the per-wavefront set, and the degenerate inputs.
 """
-import ctypes
 import sys
 
 import numpy as np
