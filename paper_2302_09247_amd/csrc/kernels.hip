@@ -461,12 +461,24 @@ __global__ void k_compact_mark(const int32_t *__restrict__ roi, const int32_t *_
         typedef int32_t v4i __attribute__((ext_vector_type(4)));
         const v4i *r4 = reinterpret_cast<const v4i *>(roi);
         const v4i *m4 = reinterpret_cast<const v4i *>(lab);
-        for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
+        // two groups of loads in flight before any mark: the marks are atomics, and on this
+        // architecture a wait for a later load also waits for every earlier atomic
+        for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += 2 * stride) {
+            const int32_t i2 = i + stride;
             const v4i r = __builtin_nontemporal_load(r4 + i), m = __builtin_nontemporal_load(m4 + i);
+            v4i r2 = {-1, -1, -1, -1}, m2 = {-1, -1, -1, -1};
+            if (i2 < n4) {
+                r2 = __builtin_nontemporal_load(r4 + i2);
+                m2 = __builtin_nontemporal_load(m4 + i2);
+            }
             mark_voxel(4 * i, r.x, m.x, g, N, M, SBX, SBXY, mb);
             mark_voxel(4 * i + 1, r.y, m.y, g, N, M, SBX, SBXY, mb);
             mark_voxel(4 * i + 2, r.z, m.z, g, N, M, SBX, SBXY, mb);
             mark_voxel(4 * i + 3, r.w, m.w, g, N, M, SBX, SBXY, mb);
+            mark_voxel(4 * i2, r2.x, m2.x, g, N, M, SBX, SBXY, mb);
+            mark_voxel(4 * i2 + 1, r2.y, m2.y, g, N, M, SBX, SBXY, mb);
+            mark_voxel(4 * i2 + 2, r2.z, m2.z, g, N, M, SBX, SBXY, mb);
+            mark_voxel(4 * i2 + 3, r2.w, m2.w, g, N, M, SBX, SBXY, mb);
         }
         for (int32_t lin = 4 * n4 + blockIdx.x * blockDim.x + threadIdx.x; lin < nvox; lin += stride)
             mark_voxel(lin, roi[lin], lab[lin], g, N, M, SBX, SBXY, mb);
