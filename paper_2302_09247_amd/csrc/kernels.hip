@@ -231,10 +231,11 @@ struct BufferedSink {
     }
 };
 
-// C updates appended, 64 at a time, to this wavefront's slice of a pair buffer (coalesced
-// non-temporal stores), for a later histogram pass.  Stores are acknowledged once the cache takes
-// them, whereas an atomic must first fetch its line of C: on this architecture every later vector
-// memory wait also waits for it.  Once the slice is full, updates go to C as atomics.
+// C updates appended, 64 at a time, to this wavefront's slice of a pair buffer (one coalesced
+// store), for a later histogram pass.  A cached store is acknowledged once the cache takes it,
+// whereas an atomic must first fetch its line of C, and on this architecture every later vector
+// memory wait also waits for it (a non-temporal store measured 1.5% slower for the same reason).
+// Once the slice is full, updates go to C as atomics.
 struct AppendSink {
     uint32_t *buf;   // [kWave] LDS
     int n;           // pending entries (wave-uniform)
@@ -251,7 +252,7 @@ struct AppendSink {
     __device__ void emit(int cnt) {   // the first cnt (<= 64) entries of buf
         const int lane = lane_id();
         if ((uint32_t)cnt <= room) {
-            if (lane < cnt) __builtin_nontemporal_store(buf[lane], out + lane);
+            if (lane < cnt) out[lane] = buf[lane];
             out += cnt;
             room -= (uint32_t)cnt;
         } else if (lane < cnt) {
