@@ -1920,20 +1920,116 @@ __global__ void __launch_bounds__(1024) k_pair_tile_base(const uint32_t *__restr
     if (threadIdx.x == 1023) base[ntiles] = part[1023];
 }
 
-// Each update into its tile's run of `sorted`, at workgroup b's reserved offset.
-__global__ void __launch_bounds__(1024) k_pair_scatter(PairOut po, int32_t nwaves, int32_t ntiles,
+// Exclusive scan of c[0 .. n) in LDS (n <= kMaxPairTiles) by a 1024-thread workgroup; thread i
+// owns entries 4i .. 4i+3 and gets their counts back in own[].  wsum: 16 words of LDS.
+__device__ __forceinline__ uint32_t block_scan_tiles(uint32_t *c, int32_t n, uint32_t (&own)[4], uint32_t *wsum) {
+    static_assert(kMaxPairTiles == 4 * 1024, "four tiles per thread");
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    uint32_t s = 0u;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int t = 4 * tid + q;
+        own[q] = t < n ? c[t] : 0u;
+        s += own[q];
+    }
+    uint32_t x = s;   // inclusive scan over the wavefront
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) wsum[wv] = x;
+    __syncthreads();
+    uint32_t before = 0u, total = 0u;
+    for (int k = 0; k < 16; ++k) {
+        const uint32_t w = wsum[k];
+        before += k < wv ? w : 0u;
+        total += w;
+    }
+    uint32_t run = before + x - s;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int t = 4 * tid + q;
+        if (t < n) c[t] = run;
+        run += own[q];
+    }
+    return total;
+}
+
+constexpr int kScatterUnroll = 6;                      // loads in flight per thread (64 VGPRs in all)
+constexpr int kScatterRound = kScatterUnroll * 1024;   // updates staged in LDS per round
+
+// Each update into its tile's run of `sorted`, at workgroup b's reserved offset.  A round of up to
+// kScatterRound updates is first grouped by tile in LDS; the stores then go out in that order, so
+// neighbouring lanes write neighbouring entries of a run instead of one entry per run each.  Two
+// workgroups per CU: 64 VGPRs and 57.9 KB of LDS each.
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) k_pair_scatter(PairOut po, int32_t nwaves, int32_t ntiles,
                                                        const uint32_t *__restrict__ base,
                                                        const uint32_t *__restrict__ boff, uint32_t *__restrict__ sorted) {
-    __shared__ uint32_t cur[kMaxPairTiles];
+    __shared__ uint32_t cur[kMaxPairTiles];     // next entry of this workgroup's run in each tile
+    __shared__ uint32_t cnt[kMaxPairTiles];     // the round's count per tile, then its offset in stage
+    __shared__ uint32_t stage[kScatterRound];   // the round's updates, grouped by tile
     __shared__ uint32_t pre[kMaxSlicesPerBlock + 1];
-    for (int t = threadIdx.x; t < ntiles; t += blockDim.x) cur[t] = base[t] + boff[(size_t)blockIdx.x * ntiles + t];
+    __shared__ uint32_t wsum[16];
+    for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
+        cur[t] = base[t] + boff[(size_t)blockIdx.x * ntiles + t];
+        cnt[t] = 0u;
+    }
+    int32_t w0, w1;
+    slice_range(nwaves, blockIdx.x, gridDim.x, w0, w1);
+    const int ns = w1 - w0;
+    if (threadIdx.x < (unsigned)ns) pre[threadIdx.x + 1] = min(po.counts[w0 + threadIdx.x], po.cap);
+    if (threadIdx.x == 0) pre[0] = 0u;
     __syncthreads();
-    for_each_update(po, nwaves, pre, [&](uint32_t e) {
-        const uint32_t t = e >> kPairTileLog2;
-        // a cached store: a workgroup's updates of one tile land side by side, and the cache merges
-        // them into whole lines before they go to memory
-        if (t < (uint32_t)ntiles) sorted[atomicAdd(&cur[t], 1u)] = e;
-    });
+    if (threadIdx.x == 0)
+        for (int k = 1; k <= ns; ++k) pre[k] += pre[k - 1];
+    __syncthreads();
+    const uint32_t total = pre[ns];
+    for (uint32_t r0 = 0; r0 < total; r0 += kScatterRound) {   // uniform over the workgroup
+        uint32_t v[kScatterUnroll], rank[kScatterUnroll];
+#pragma unroll
+        for (int j = 0; j < kScatterUnroll; ++j) {
+            const uint32_t k = r0 + threadIdx.x + j * 1024u;
+            v[j] = kNoEntry;
+            if (k < total) {
+                int lo = 0, hi = ns - 1;   // the slice holding flat index k: pre[lo] <= k < pre[lo + 1]
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (pre[mid] <= k) lo = mid;
+                    else hi = mid - 1;
+                }
+                v[j] = __builtin_nontemporal_load(po.pairs + (size_t)(w0 + lo) * po.cap + (k - pre[lo]));
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kScatterUnroll; ++j) {
+            const uint32_t t = v[j] >> kPairTileLog2;   // kNoEntry: t >= ntiles
+            if (t < (uint32_t)ntiles) rank[j] = atomicAdd(&cnt[t], 1u);
+            else v[j] = kNoEntry;
+        }
+        __syncthreads();
+        uint32_t own[4];
+        const uint32_t n = block_scan_tiles(cnt, ntiles, own, wsum);   // cnt: offsets in stage
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kScatterUnroll; ++j)
+            if (v[j] != kNoEntry) stage[cnt[v[j] >> kPairTileLog2] + rank[j]] = v[j];
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < n; i += 1024u) {
+            const uint32_t e = stage[i], t = e >> kPairTileLog2;
+            sorted[cur[t] + (i - cnt[t])] = e;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int t = 4 * (int)threadIdx.x + q;
+            if (t < ntiles) {
+                cur[t] += own[q];
+                cnt[t] = 0u;
+            }
+        }
+        __syncthreads();
+    }
 }
 
 // One workgroup per tile: C[tile] += the histogram of the tile's updates.
