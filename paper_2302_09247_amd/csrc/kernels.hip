@@ -30,6 +30,9 @@ __device__ __forceinline__ int mbcnt(uint64_t m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
+// this lane's bit of a wave-uniform mask, which the hardware takes directly as a lane predicate
+__device__ __forceinline__ bool in_mask(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
+
 __device__ __forceinline__ uint64_t lanes_between(int lo, int hi) {  // bits [lo, hi)
     const uint64_t below_hi = hi >= 64 ? ~0ull : ((1ull << hi) - 1ull);
     return below_hi & ~((1ull << lo) - 1ull);
@@ -130,8 +133,7 @@ struct WaveSet {
 
     // Insert the keys of the lanes in `cand`; returns the lanes whose key was not yet present.
     __device__ uint64_t insert(uint64_t cand, uint32_t key, uint32_t &slot) {
-        const int lane = lane_id();
-        bool active = (cand >> lane) & 1ull;
+        bool active = in_mask(cand);
         bool fresh = false;
         uint32_t h = (__umul24(key ^ (key >> 20), 0x9E3779u) >> 12) & (CAP - 1);
         while (__ballot(active)) {
@@ -154,12 +156,11 @@ struct WaveSet {
     // Adds the candidate rows / labels; false when the set could outgrow its capacity.
     __device__ bool add(uint64_t candR, int r, uint64_t candM, int m) {
         if (nI + nM + __popcll(candR) + __popcll(candM) > kHalf) return false;
-        const int lane = lane_id();
         uint32_t slotR = 0, slotM = 0;
         const uint64_t newR = candR ? insert(candR, (uint32_t)r, slotR) : 0ull;
         const uint64_t newM = candM ? insert(candM, (uint32_t)m | kLabelTag, slotM) : 0ull;
-        if ((newR >> lane) & 1ull) slots[nI + mbcnt(newR)] = slotR;
-        if ((newM >> lane) & 1ull) slots[kHalf - 1 - (nM + mbcnt(newM))] = slotM;
+        if (in_mask(newR)) slots[nI + mbcnt(newR)] = slotR;
+        if (in_mask(newM)) slots[kHalf - 1 - (nM + mbcnt(newM))] = slotM;
         nI += __popcll(newR);
         nM += __popcll(newM);
         return true;
@@ -322,9 +323,8 @@ struct DeferredSet {
     __device__ bool append(uint64_t cR, int r, uint64_t cM, int m) {
         const int addR = __popcll(cR), addM = __popcll(cM);
         if (nR + addR > RCAP || nL + addM > LCAP) return false;
-        const int lane = lane_id();
-        if ((cR >> lane) & 1ull) rows[nR + mbcnt(cR)] = (uint32_t)r;
-        if ((cM >> lane) & 1ull) labs[nL + mbcnt(cM)] = (uint32_t)m;
+        if (in_mask(cR)) rows[nR + mbcnt(cR)] = (uint32_t)r;
+        if (in_mask(cM)) labs[nL + mbcnt(cM)] = (uint32_t)m;
         nR += addR;
         nL += addM;
         return true;
@@ -335,8 +335,7 @@ struct DeferredSet {
     }
     // Inserts the key of every lane in `cand`; returns the lanes whose key was new (slot set).
     __device__ uint64_t insert(uint64_t cand, uint32_t key, uint32_t &slot) const {
-        const int lane = lane_id();
-        bool active = (cand >> lane) & 1ull;
+        bool active = in_mask(cand);
         bool fresh = false;
         uint32_t h = slot_of(key);
         while (__ballot(active)) {
@@ -363,7 +362,7 @@ struct DeferredSet {
                 const uint32_t m = ok ? labs[k] : 0u;
                 uint32_t slot = 0;
                 const uint64_t fresh = insert(__ballot(ok), m | kLabelTag, slot);
-                const bool f = (fresh >> lane) & 1ull;
+                const bool f = in_mask(fresh);
                 if (f) ulab[nU + mbcnt(fresh)] = m;
                 if (ok) labs[k] = f ? slot : kEmpty;
                 nU += __popcll(fresh);
@@ -374,7 +373,7 @@ struct DeferredSet {
                 const uint32_t i = ok ? rows[k] : 0u;
                 uint32_t slot = 0;
                 const uint64_t fresh = insert(__ballot(ok), i, slot);
-                const bool f = (fresh >> lane) & 1ull;
+                const bool f = in_mask(fresh);
                 const uint32_t row = i * si;   // N*M < 2^31
                 for (int j = 0; j < nU; ++j) sink.push(f, row + __builtin_amdgcn_readfirstlane(ulab[j]) * sm);
                 if (ok) rows[k] = f ? slot : kEmpty;
@@ -1103,7 +1102,7 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
             int rr[kUp], mm[kUp];
 #pragma unroll
             for (int t = 0; t < kUp; ++t) {
-                const bool ok = t == 0 || ((nextok >> lane) & 1ull);
+                const bool ok = t == 0 || in_mask(nextok);
                 rr[t] = ok ? r[b * kUp + t] : -1;
                 mm[t] = (ok && !endmode) ? m[b * kUp + t] : -1;
             }
@@ -1119,14 +1118,15 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
             // the previous lane's last sub-point (lane 0: the previous window's), t >= 1 against t - 1
             int rp_ = __builtin_amdgcn_update_dpp(last_r, rl, 0x138, 0xF, 0xF, false);   // wave_shr:1
             int mp_ = __builtin_amdgcn_update_dpp(last_m, ml, 0x138, 0xF, 0xF, false);
-            if ((starts >> lane) & 1ull) rp_ = mp_ = -1;  // first point of a streamline
+            if (in_mask(starts)) rp_ = mp_ = -1;  // first point of a streamline
             uint64_t candR[kUp], candM[kUp];
-            candR[0] = __ballot(rr[0] >= 0 && rr[0] != rp_);
-            candM[0] = __ballot(mm[0] >= 0 && mm[0] != mp_);
+            // (one ballot per comparison: each compare writes its lane mask directly)
+            candR[0] = __ballot(rr[0] >= 0) & __ballot(rr[0] != rp_);
+            candM[0] = __ballot(mm[0] >= 0) & __ballot(mm[0] != mp_);
 #pragma unroll
             for (int t = 1; t < kUp; ++t) {
-                candR[t] = __ballot(rr[t] >= 0 && rr[t] != rr[t - 1]);
-                candM[t] = __ballot(mm[t] >= 0 && mm[t] != mm[t - 1]);
+                candR[t] = __ballot(rr[t] >= 0) & __ballot(rr[t] != rr[t - 1]);
+                candM[t] = __ballot(mm[t] >= 0) & __ballot(mm[t] != mm[t - 1]);
             }
             last_r = __builtin_amdgcn_readlane(rl, kWave - 1);
             last_m = __builtin_amdgcn_readlane(ml, kWave - 1);
