@@ -132,25 +132,21 @@ struct WaveSet {
     }
 
     // Insert the keys of the lanes in `cand`; returns the lanes whose key was not yet present.
+    // The lanes still probing are a wave-uniform mask; the outcome ballots count those lanes only
+    // (a lane outside `cand` may hold any value, kEmpty included, as its key).
     __device__ uint64_t insert(uint64_t cand, uint32_t key, uint32_t &slot) {
-        bool active = in_mask(cand);
-        bool fresh = false;
+        uint64_t act = cand, fresh = 0ull;
         uint32_t h = (__umul24(key ^ (key >> 20), 0x9E3779u) >> 12) & (CAP - 1);
-        while (__ballot(active)) {
-            if (active) {
-                const uint32_t old = atomicCAS(&tab[h], kEmpty, key);
-                if (old == kEmpty) {
-                    fresh = true;
-                    slot = h;
-                    active = false;
-                } else if (old == key) {
-                    active = false;
-                } else {
-                    h = (h + 1u) & (CAP - 1);
-                }
-            }
+        while (act) {
+            uint32_t old = 0u;
+            if (in_mask(act)) old = atomicCAS(&tab[h], kEmpty, key);
+            const uint64_t got = __ballot(old == kEmpty) & act, dup = __ballot(old == key) & act;
+            if (in_mask(got)) slot = h;
+            fresh |= got;
+            act &= ~(got | dup);
+            h = (h + 1u) & (CAP - 1);
         }
-        return __ballot(fresh);
+        return fresh;
     }
 
     // Adds the candidate rows / labels; false when the set could outgrow its capacity.
@@ -178,12 +174,12 @@ struct WaveSet {
         if (!skip && nI > 0 && nM > 0) {
             for (int b = 0; b < nI; b += kWave) {
                 const int k = b + lane_id();
-                const bool ok = k < nI;
-                const uint32_t i = ok ? tab[slots[k]] : 0u;
+                const uint64_t ok = __ballot(k < nI);
+                const uint32_t i = in_mask(ok) ? tab[slots[k]] : 0u;
                 const uint32_t row = i * si;   // N*M < 2^31
                 for (int j = 0; j < nM; ++j) {
                     const uint32_t mk = __builtin_amdgcn_readfirstlane(tab[slots[kHalf - 1 - j]]) & ~kLabelTag;
-                    sink.push(ok, row + mk * sm);
+                    sink.push_lanes(ok, row + mk * sm);
                 }
             }
         }
@@ -195,9 +191,10 @@ struct WaveSet {
 // C updates straight to global memory (one atomic per pair).
 struct DirectSink {
     int32_t *C;
-    __device__ void push(bool valid, uint32_t idx) {
-        if (valid) atomicAdd(C + idx, 1);
+    __device__ void push_lanes(uint64_t vm, uint32_t idx) {   // the lanes in vm (wave-uniform)
+        if (in_mask(vm)) atomicAdd(C + idx, 1);
     }
+    __device__ void push(bool valid, uint32_t idx) { push_lanes(__ballot(valid), idx); }
 };
 
 // C updates buffered per wavefront in LDS and issued 64 at a time: a wave-wide atomic
@@ -212,9 +209,10 @@ struct BufferedSink {
         n = 0;
         C = c;
     }
-    __device__ void push(bool valid, uint32_t idx) {
-        const uint64_t vm = __ballot(valid);
+    __device__ void push(bool valid, uint32_t idx) { push_lanes(__ballot(valid), idx); }
+    __device__ void push_lanes(uint64_t vm, uint32_t idx) {   // the lanes in vm (wave-uniform)
         if (!vm) return;
+        const bool valid = in_mask(vm);
         const int pos = n + mbcnt(vm);
         if (valid && pos < kWave) buf[pos] = idx;
         const int cnt = __popcll(vm);
@@ -260,9 +258,10 @@ struct AppendSink {
             atomicAdd(C + buf[lane], 1);
         }
     }
-    __device__ void push(bool valid, uint32_t idx) {
-        const uint64_t vm = __ballot(valid);
+    __device__ void push(bool valid, uint32_t idx) { push_lanes(__ballot(valid), idx); }
+    __device__ void push_lanes(uint64_t vm, uint32_t idx) {   // the lanes in vm (wave-uniform)
         if (!vm) return;
+        const bool valid = in_mask(vm);
         const int pos = n + mbcnt(vm);
         if (valid && pos < kWave) buf[pos] = idx;
         const int cnt = __popcll(vm);
@@ -334,20 +333,24 @@ struct DeferredSet {
         return (key ^ (key >> 9) ^ (key >> 18) ^ (key >> 27)) & (TCAP - 1);
     }
     // Inserts the key of every lane in `cand`; returns the lanes whose key was new (slot set).
+    // The lanes still probing are a wave-uniform mask; the outcome ballots count those lanes only
+    // (a lane outside `cand` may hold any value as its key).  Each lane's slot ends where its key
+    // was found or put.
     __device__ uint64_t insert(uint64_t cand, uint32_t key, uint32_t &slot) const {
-        bool active = in_mask(cand);
-        bool fresh = false;
+        uint64_t act = cand, fresh = 0ull;
         uint32_t h = slot_of(key);
-        while (__ballot(active)) {
-            if (active) {
-                const uint32_t old = atomicCAS(&tab[h], kEmpty, key);
-                fresh = old == kEmpty;
-                active = !fresh && old != key;
+        while (act) {
+            uint32_t old = 0u;
+            if (in_mask(act)) {
+                old = atomicCAS(&tab[h], kEmpty, key);
                 slot = h;
-                h = (h + 1u) & (TCAP - 1);
             }
+            const uint64_t got = __ballot(old == kEmpty) & act, dup = __ballot(old == key) & act;
+            fresh |= got;
+            act &= ~(got | dup);
+            h = (h + 1u) & (TCAP - 1);
         }
-        return __ballot(fresh);
+        return fresh;
     }
 
     // The streamline ends: C(i, m) += 1 for each distinct row i and distinct label m, then reset.
@@ -356,27 +359,28 @@ struct DeferredSet {
         if (!skip && nR > 0 && nL > 0) {
             const int lane = lane_id();
             int nU = 0;
+            // (lane conditions as wave-uniform masks throughout: no per-lane booleans carried
+            // across loads and loops)
             for (int b = 0; b < nL; b += kWave) {
                 const int k = b + lane;
-                const bool ok = k < nL;
-                const uint32_t m = ok ? labs[k] : 0u;
+                const uint64_t ok = __ballot(k < nL);
+                const uint32_t m = in_mask(ok) ? labs[k] : 0u;
                 uint32_t slot = 0;
-                const uint64_t fresh = insert(__ballot(ok), m | kLabelTag, slot);
-                const bool f = in_mask(fresh);
-                if (f) ulab[nU + mbcnt(fresh)] = m;
-                if (ok) labs[k] = f ? slot : kEmpty;
+                const uint64_t fresh = insert(ok, m | kLabelTag, slot);
+                if (in_mask(fresh)) ulab[nU + mbcnt(fresh)] = m;
+                if (in_mask(ok)) labs[k] = in_mask(fresh) ? slot : kEmpty;
                 nU += __popcll(fresh);
             }
             for (int b = 0; b < nR; b += kWave) {
                 const int k = b + lane;
-                const bool ok = k < nR;
-                const uint32_t i = ok ? rows[k] : 0u;
+                const uint64_t ok = __ballot(k < nR);
+                const uint32_t i = in_mask(ok) ? rows[k] : 0u;
                 uint32_t slot = 0;
-                const uint64_t fresh = insert(__ballot(ok), i, slot);
-                const bool f = in_mask(fresh);
+                const uint64_t fresh = insert(ok, i, slot);
                 const uint32_t row = i * si;   // N*M < 2^31
-                for (int j = 0; j < nU; ++j) sink.push(f, row + __builtin_amdgcn_readfirstlane(ulab[j]) * sm);
-                if (ok) rows[k] = f ? slot : kEmpty;
+                for (int j = 0; j < nU; ++j)
+                    sink.push_lanes(fresh, row + __builtin_amdgcn_readfirstlane(ulab[j]) * sm);
+                if (in_mask(ok)) rows[k] = in_mask(fresh) ? slot : kEmpty;
             }
             for (int k = lane; k < nL; k += kWave)
                 if (labs[k] != kEmpty) tab[labs[k]] = kEmpty;
@@ -925,7 +929,7 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
     auto take_starts = [&](uint32_t wb, uint32_t wend, int &mult) -> uint64_t {
         uint64_t starts = 0;
         while (nxt < wend) {
-            const uint64_t inwin = __ballot((int)(lane >= k0) & (int)(voff < wend));
+            const uint64_t inwin = __ballot(lane >= k0) & __ballot(voff < wend);
             const uint32_t qv = min(voff - wb, (uint32_t)(kWave - 1));   // lane of the start (in-window lanes)
             uint64_t it = inwin;
             while (it) {
@@ -940,7 +944,7 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
         return starts;
     };
     auto skip_starts = [&](uint32_t limit) {
-        while (nxt < limit) consumed(__ballot((int)(lane >= k0) & (int)(voff < limit)));
+        while (nxt < limit) consumed(__ballot(lane >= k0) & __ballot(voff < limit));
     };
     load_starts();
     // the open streamline is vb - 1 + k0: the last one whose start has been consumed
