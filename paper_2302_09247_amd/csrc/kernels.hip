@@ -438,19 +438,47 @@ hipError_t launch_fill_u64(unsigned long long *p, int64_t n, int cus, hipStream_
 // compact volume build
 // ---------------------------------------------------------------------------------------------
 
-// one thread per voxel (coalesced reads of both volumes); occupied voxels set their bit
-// Sets the occupancy bit of voxel lin (0 <= roi < N or 0 <= lab < M).
+// Occupancy word (index into the {word, base} pairs) and bit of voxel lin; false when the voxel
+// is not occupied (0 <= roi < N or 0 <= lab < M).
+__device__ __forceinline__ bool occupancy_bit(int32_t lin, int32_t r, int32_t m, const Grid &g, int32_t N, int32_t M,
+                                              int32_t SBX, int32_t SBXY, uint32_t &word, uint32_t &bit) {
+    if (!((unsigned)r < (unsigned)N || (unsigned)m < (unsigned)M)) return false;
+    const int32_t t = lin / g.X;
+    const int x = lin - t * g.X;
+    const int y = t % g.Y;
+    const int z = t / g.Y;
+    const uint32_t sb = (uint32_t)(x >> 4) + (uint32_t)SBX * (uint32_t)(y >> 3) + (uint32_t)SBXY * (uint32_t)(z >> 3);
+    const uint32_t b = (uint32_t)(x & 15) | ((uint32_t)(y & 7) << 4) | ((uint32_t)(z & 7) << 7);
+    word = (sb << 5) | (b >> 5);
+    bit = 1u << (b & 31u);
+    return true;
+}
+
+// Sets the occupancy bit of voxel lin.
 __device__ __forceinline__ void mark_voxel(int32_t lin, int32_t r, int32_t m, const Grid &g, int32_t N, int32_t M,
                                            int32_t SBX, int32_t SBXY, uint32_t *mb) {
-    if ((unsigned)r < (unsigned)N || (unsigned)m < (unsigned)M) {
-        const int32_t t = lin / g.X;
-        const int x = lin - t * g.X;
-        const int y = t % g.Y;
-        const int z = t / g.Y;
-        const uint32_t sb = (uint32_t)(x >> 4) + (uint32_t)SBX * (uint32_t)(y >> 3) + (uint32_t)SBXY * (uint32_t)(z >> 3);
-        const uint32_t b = (uint32_t)(x & 15) | ((uint32_t)(y & 7) << 4) | ((uint32_t)(z & 7) << 7);
-        atomicOr(&mb[2 * ((sb << 5) | (b >> 5))], 1u << (b & 31u));
+    uint32_t w, bit;
+    if (occupancy_bit(lin, r, m, g, N, M, SBX, SBXY, w, bit)) atomicOr(&mb[2 * w], bit);
+}
+
+// Sets the occupancy bits of voxels lin0 .. lin0+3 with one atomic per run of them in one word
+// (four neighbours along x share a word unless a row or a 16-voxel run ends among them).
+__device__ __forceinline__ void mark_voxels4(int32_t lin0, const int32_t (&r)[4], const int32_t (&m)[4], const Grid &g,
+                                             int32_t N, int32_t M, int32_t SBX, int32_t SBXY, uint32_t *mb) {
+    uint32_t word = 0u, bits = 0u;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        uint32_t w, bit;
+        if (occupancy_bit(lin0 + q, r[q], m[q], g, N, M, SBX, SBXY, w, bit)) {
+            if (bits && w != word) {
+                atomicOr(&mb[2 * word], bits);
+                bits = 0u;
+            }
+            word = w;
+            bits |= bit;
+        }
     }
+    if (bits) atomicOr(&mb[2 * word], bits);
 }
 
 // One pass over both volumes (X*Y*Z < 2^31): four voxels per thread and step with 16-byte loads
@@ -475,14 +503,14 @@ __global__ void k_compact_mark(const int32_t *__restrict__ roi, const int32_t *_
                 r2 = __builtin_nontemporal_load(r4 + i2);
                 m2 = __builtin_nontemporal_load(m4 + i2);
             }
-            mark_voxel(4 * i, r.x, m.x, g, N, M, SBX, SBXY, mb);
-            mark_voxel(4 * i + 1, r.y, m.y, g, N, M, SBX, SBXY, mb);
-            mark_voxel(4 * i + 2, r.z, m.z, g, N, M, SBX, SBXY, mb);
-            mark_voxel(4 * i + 3, r.w, m.w, g, N, M, SBX, SBXY, mb);
-            mark_voxel(4 * i2, r2.x, m2.x, g, N, M, SBX, SBXY, mb);
-            mark_voxel(4 * i2 + 1, r2.y, m2.y, g, N, M, SBX, SBXY, mb);
-            mark_voxel(4 * i2 + 2, r2.z, m2.z, g, N, M, SBX, SBXY, mb);
-            mark_voxel(4 * i2 + 3, r2.w, m2.w, g, N, M, SBX, SBXY, mb);
+            {
+                const int32_t ra[4] = {r.x, r.y, r.z, r.w}, ma[4] = {m.x, m.y, m.z, m.w};
+                mark_voxels4(4 * i, ra, ma, g, N, M, SBX, SBXY, mb);
+            }
+            {
+                const int32_t ra[4] = {r2.x, r2.y, r2.z, r2.w}, ma[4] = {m2.x, m2.y, m2.z, m2.w};
+                mark_voxels4(4 * i2, ra, ma, g, N, M, SBX, SBXY, mb);
+            }
         }
         for (int32_t lin = 4 * n4 + blockIdx.x * blockDim.x + threadIdx.x; lin < nvox; lin += stride)
             mark_voxel(lin, roi[lin], lab[lin], g, N, M, SBX, SBXY, mb);
