@@ -1490,23 +1490,45 @@ __device__ bool sub_lookup(const float *__restrict__ pts, int64_t b0, int64_t k,
     return true;
 }
 
+constexpr int kFallbackCached = 4;   // sub-points per thread whose lookup is kept for the later passes
+
 template <typename Lookup, bool SCALED>
 __device__ void fallback_streamline(const float *__restrict__ pts, const int64_t *__restrict__ offsets, int64_t S,
                                     const Grid &g, float scale, const Lookup &lk, int32_t *__restrict__ C, uint32_t si,
                                     uint32_t sm, int64_t p, uint32_t *bmN, uint32_t *bmM, uint32_t *labels,
                                     int *s_nlab, const EndLabels &ends, int up) {
     const int64_t Ptot = offsets[S] > 0 ? offsets[S] : 0;
-    // streamline containing point p: last s with offsets[s] <= p
-    int64_t lo = 0, hi = S;  // answer in [0, S-1]
+    // streamline containing point p: the last s with offsets[s] <= p.  The offsets never decrease,
+    // so of blockDim.x evenly spaced candidates the ones at or below p are a prefix of the threads,
+    // and their count narrows [lo, hi) blockDim.x-fold per round (3 rounds for 5M streamlines).
+    int64_t lo = 0, hi = S;  // answer in [lo, hi)
     while (hi - lo > 1) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (offsets[mid] <= p) lo = mid;
-        else hi = mid;
+        const int64_t step = (hi - lo + blockDim.x - 1) / blockDim.x;
+        const int64_t idx = lo + (int64_t)threadIdx.x * step;
+        const int at_or_below = (threadIdx.x > 0 && idx < hi && offsets[idx] <= p) ? 1 : 0;
+        lo += (int64_t)__syncthreads_count(at_or_below) * step;
+        hi = min(hi, lo + step);
     }
     const int64_t b0 = clamp64(offsets[lo], 0, Ptot);
     const int64_t b1 = clamp64(offsets[lo + 1], b0, Ptot);
     const int64_t nsub = b1 > b0 ? (b1 - b0 - 1) * up + 1 : 0;   // points after upsampling
     if (threadIdx.x == 0) *s_nlab = 0;
+    // each sub-point is looked up once: thread t's sub-points t + j * blockDim.x, j < kFallbackCached,
+    // keep (r, m) in registers for the three passes; the rest (streamlines of more than
+    // kFallbackCached * blockDim.x sub-points) are looked up again in each pass.  -1: none.
+    int cr[kFallbackCached], cm[kFallbackCached];
+#pragma unroll
+    for (int j = 0; j < kFallbackCached; ++j) {
+        const int64_t k = threadIdx.x + (int64_t)j * blockDim.x;
+        int r = -1, m = -1;
+        if (k >= nsub || !sub_lookup<Lookup, SCALED>(pts, b0, k, up, scale, g, lk, r, m)) r = m = -1;
+        cr[j] = r;
+        cm[j] = m;
+    }
+    const int64_t k_rest = threadIdx.x + (int64_t)kFallbackCached * blockDim.x;
+    auto lookup_rest = [&](int64_t k, int &r, int &m) {
+        if (!sub_lookup<Lookup, SCALED>(pts, b0, k, up, scale, g, lk, r, m)) r = m = -1;
+    };
     __syncthreads();
     // endpoint modes: the labels are the streamline's end labels
     if (ends.mode != 0 && threadIdx.x == 0) {
@@ -1517,9 +1539,7 @@ __device__ void fallback_streamline(const float *__restrict__ pts, const int64_t
         *s_nlab = n;
     }
     // distinct labels
-    for (int64_t k = threadIdx.x; ends.mode == 0 && k < nsub; k += blockDim.x) {
-        int r, m;
-        if (!sub_lookup<Lookup, SCALED>(pts, b0, k, up, scale, g, lk, r, m)) continue;
+    auto add_label = [&](int m) {
         if (m >= 0) {
             const uint32_t bitm = 1u << (m & 31);
             if (!(atomicOr(&bmM[m >> 5], bitm) & bitm)) {
@@ -1527,31 +1547,50 @@ __device__ void fallback_streamline(const float *__restrict__ pts, const int64_t
                 atomicExch(&labels[k], (uint32_t)m);
             }
         }
+    };
+    if (ends.mode == 0) {
+#pragma unroll
+        for (int j = 0; j < kFallbackCached; ++j) add_label(cm[j]);
+        for (int64_t k = k_rest; k < nsub; k += blockDim.x) {
+            int r, m;
+            lookup_rest(k, r, m);
+            add_label(m);
+        }
     }
     __syncthreads();
     const int nlab = *s_nlab;
     // distinct rows: the first claimant of each row adds its pairs
-    if (nlab > 0) {
-        for (int64_t k = threadIdx.x; k < nsub; k += blockDim.x) {
-            int r, m;
-            if (!sub_lookup<Lookup, SCALED>(pts, b0, k, up, scale, g, lk, r, m)) continue;
-            if (r >= 0) {
-                const uint32_t bitr = 1u << (r & 31);
-                if (!(atomicOr(&bmN[r >> 5], bitr) & bitr)) {
-                    int32_t *row = C + (uint32_t)r * si;
-                    for (int k = 0; k < nlab; ++k)
-                        atomicAdd(row + __hip_atomic_load(&labels[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) * sm, 1);
-                }
+    auto add_row = [&](int r) {
+        if (r >= 0) {
+            const uint32_t bitr = 1u << (r & 31);
+            if (!(atomicOr(&bmN[r >> 5], bitr) & bitr)) {
+                int32_t *row = C + (uint32_t)r * si;
+                for (int k = 0; k < nlab; ++k)
+                    atomicAdd(row + __hip_atomic_load(&labels[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) * sm, 1);
             }
+        }
+    };
+    if (nlab > 0) {
+#pragma unroll
+        for (int j = 0; j < kFallbackCached; ++j) add_row(cr[j]);
+        for (int64_t k = k_rest; k < nsub; k += blockDim.x) {
+            int r, m;
+            lookup_rest(k, r, m);
+            add_row(r);
         }
     }
     __syncthreads();
     // restore the all-zero scratch (bit maps and label list)
-    for (int64_t k = threadIdx.x; k < nsub; k += blockDim.x) {
-        int r, m;
-        if (!sub_lookup<Lookup, SCALED>(pts, b0, k, up, scale, g, lk, r, m)) continue;
+    auto clear = [&](int r, int m) {
         if (r >= 0) atomicExch(&bmN[r >> 5], 0u);
         if (m >= 0) atomicExch(&bmM[m >> 5], 0u);
+    };
+#pragma unroll
+    for (int j = 0; j < kFallbackCached; ++j) clear(cr[j], cm[j]);
+    for (int64_t k = k_rest; k < nsub; k += blockDim.x) {
+        int r, m;
+        lookup_rest(k, r, m);
+        clear(r, m);
     }
     for (int k = threadIdx.x; k < nlab; k += blockDim.x) atomicExch(&labels[k], 0u);
     __syncthreads();
