@@ -371,16 +371,33 @@ struct DeferredSet {
                 if (in_mask(ok)) labs[k] = in_mask(fresh) ? slot : kEmpty;
                 nU += __popcll(fresh);
             }
+            const float rcp = 1.0f / (float)nU;
             for (int b = 0; b < nR; b += kWave) {
                 const int k = b + lane;
                 const uint64_t ok = __ballot(k < nR);
                 const uint32_t i = in_mask(ok) ? rows[k] : 0u;
                 uint32_t slot = 0;
                 const uint64_t fresh = insert(ok, i, slot);
-                const uint32_t row = i * si;   // N*M < 2^31
-                for (int j = 0; j < nU; ++j)
-                    sink.push_lanes(fresh, row + __builtin_amdgcn_readfirstlane(ulab[j]) * sm);
                 if (in_mask(ok)) rows[k] = in_mask(fresh) ? slot : kEmpty;
+                // the nF new rows x the nU distinct labels, 64 pairs per push.  The new rows move to
+                // lanes 0 .. nF-1 (a permutation of all 64 lanes: the others fill nF .. 63); pair q is
+                // row q / nU and label q % nU.  q < 4096, so the float quotient is at most one low,
+                // and only at exact multiples of nU.
+                const int nF = __popcll(fresh);
+                if (nF == 0) continue;
+                const int to = in_mask(fresh) ? mbcnt(fresh) : nF + mbcnt(~fresh);
+                const int frow = __builtin_amdgcn_ds_permute(to << 2, (int)(i * si));   // N*M < 2^31
+                const int tot = nF * nU;
+                for (int q0 = 0; q0 < tot; q0 += kWave) {
+                    const int q = q0 + lane;
+                    const uint64_t live = __ballot(q < tot);
+                    int rq = (int)((float)q * rcp);
+                    rq += (rq + 1) * nU <= q ? 1 : 0;
+                    const int uq = q - rq * nU;
+                    const uint32_t row = (uint32_t)__builtin_amdgcn_ds_bpermute((in_mask(live) ? rq : 0) << 2, frow);
+                    const uint32_t lab = ulab[in_mask(live) ? uq : 0];
+                    sink.push_lanes(live, row + lab * sm);
+                }
             }
             for (int k = lane; k < nL; k += kWave)
                 if (labs[k] != kEmpty) tab[labs[k]] = kEmpty;
