@@ -1,0 +1,55 @@
+"""Host checks of two arithmetic arguments the counting kernels rely on (no GPU).
+
+* A streamline's close splits pair q of its (new rows) x (distinct labels) product into row q / nU
+  and label q % nU with a float32 quotient, q * fl32(1 / nU), truncated and raised by one where
+  (r + 1) * nU <= q.  The kernel relies on this being exact for every q < 4096 and 1 <= nU <= 64:
+  checked here exhaustively in float32.
+* The fallback finds the streamline holding point p (the last s with offsets[s] <= p) by testing
+  256 evenly spaced offsets per round and narrowing [lo, hi) by the count of those at or below p.
+  Over nondecreasing offsets, with runs of empty streamlines, this must give the serial search's
+  answer: checked here against numpy's searchsorted on random offsets.
+"""
+import numpy as np
+import pytest
+
+
+def test_float_quotient_is_exact_for_the_close_products():
+    q = np.arange(4096, dtype=np.int64)
+    qf = q.astype(np.float32)
+    for nu in range(1, 65):
+        rcp = np.float32(1.0) / np.float32(nu)
+        r = (qf * rcp).astype(np.float32).astype(np.int64)   # float32 product, truncated
+        r = r + ((r + 1) * nu <= q)
+        np.testing.assert_array_equal(r, q // nu, err_msg=f"nU = {nu}")
+        np.testing.assert_array_equal(q - r * nu, q % nu, err_msg=f"nU = {nu}")
+
+
+def _search_by_counts(offsets, p, width=256):
+    S = len(offsets) - 1
+    lo, hi = 0, S
+    while hi - lo > 1:
+        step = (hi - lo + width - 1) // width
+        idx = lo + np.arange(width, dtype=np.int64) * step
+        passing = (np.arange(width) > 0) & (idx < hi)
+        passing[passing] = offsets[idx[passing]] <= p
+        lo += int(passing.sum()) * step
+        hi = min(hi, lo + step)
+    return lo
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_count_search_finds_the_streamline_of_a_point(seed):
+    rng = np.random.default_rng(seed)
+    S = int(rng.choice([1, 2, 255, 256, 257, 70_000, 5_000_000]))
+    lengths = rng.integers(0, 400, S)
+    lengths[rng.random(S) < 0.2] = 0   # runs of empty streamlines share their start
+    offsets = np.concatenate([[0], np.cumsum(lengths)]).astype(np.int64)
+    P = int(offsets[-1])
+    if P == 0:
+        return
+    points = rng.integers(0, P, 200)
+    for p in points:
+        want = int(np.searchsorted(offsets, p, side="right")) - 1   # last s with offsets[s] <= p
+        got = _search_by_counts(offsets, int(p))
+        assert got == want, (S, int(p), got, want)
+        assert offsets[got] <= p < offsets[got + 1]
