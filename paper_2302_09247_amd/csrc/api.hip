@@ -125,7 +125,10 @@ int enqueue_count(Workspace &ws, int dev, const float *points, const int64_t *of
     const int64_t ntiles = (NM + (1 << fc::kPairTileLog2) - 1) >> fc::kPairTileLog2;
     const bool append = cv != nullptr && S > 0 && ntiles <= fc::kMaxPairTiles;
     const bool transposed = !append && cv != nullptr && S > 0 && M > 1 && N >= 64;
-    if (!(o.flags & FASTCOD_ACCUMULATE) && !transposed) FC_HIP(fc::launch_fill_i32(C, (int64_t)N * M, 0, cus, st));
+    const bool zero_c = !(o.flags & FASTCOD_ACCUMULATE) && !transposed;
+    // the compact path's partition launch zeroes C and the per-call counters itself
+    const bool fused_zero = cv != nullptr && S > 0;
+    if (zero_c && !fused_zero) FC_HIP(fc::launch_fill_i32(C, (int64_t)N * M, 0, cus, st));
     if (S == 0) {
         if (o.event_begin) FC_HIP(hipEventRecord((hipEvent_t)o.event_begin, st));
         if (o.event_end) FC_HIP(hipEventRecord((hipEvent_t)o.event_end, st));
@@ -165,7 +168,7 @@ int enqueue_count(Workspace &ws, int dev, const float *points, const int64_t *of
     fc::FallbackScratch fs;
     int rc = fallback_scratch(ws, N, M, fs);
     if (rc) return rc;
-    FC_HIP(fc::launch_fill_u64(a.ovf.count, 2, cus, st));   // overflow count and range counter
+    if (!fused_zero) FC_HIP(fc::launch_fill_u64(a.ovf.count, 2, cus, st));   // overflow count and range counter
     const int64_t resident = (int64_t)cus * kBlocksPerCU;
     if (cv) {
         const int batch = o.batch == 4 ? 4 : 2;
@@ -176,7 +179,6 @@ int enqueue_count(Workspace &ws, int dev, const float *points, const int64_t *of
         const int64_t nparts = blocks * fc::kWavesPerBlock * kRangesPerWave;
         FC_HIP(ws.first.ensure(4 * (size_t)(nparts + 1), false));
         int32_t *first = static_cast<int32_t *>(ws.first.p);
-        FC_HIP(fc::launch_partition(offsets, S, nparts, first, cus, st));
         // pair slices: pair_capacity entries in all (default 8 per streamline, between 2^20 and
         // 2^28), split evenly between the wavefronts; a full slice sends the rest of its
         // wavefront's updates to C as atomics
@@ -194,6 +196,18 @@ int enqueue_count(Workspace &ws, int dev, const float *points, const int64_t *of
         po.counts = reinterpret_cast<uint32_t *>(pb);
         po.pairs = reinterpret_cast<uint32_t *>(pb + off_pairs);
         po.cap = (uint32_t)cap;
+        fc::ZeroRanges z;
+        if (zero_c) {
+            z.w32[0] = C;
+            z.n32[0] = NM;
+        }
+        if (append) {
+            z.w32[1] = reinterpret_cast<int32_t *>(pb + off_hist);
+            z.n32[1] = fc::pair_hist_cursor_words(ntiles);
+        }
+        z.w64 = a.ovf.count;   // overflow count and range counter
+        z.n64 = 2;
+        FC_HIP(fc::launch_partition(offsets, S, nparts, first, z, cus, st));
         if (o.event_begin) FC_HIP(hipEventRecord((hipEvent_t)o.event_begin, st));
         FC_HIP(fc::launch_count_stream(a, *cv, first, nparts, (int)blocks, batch, po, st));
         if (o.event_end) FC_HIP(hipEventRecord((hipEvent_t)o.event_end, st));

@@ -134,9 +134,18 @@ hipError_t launch_compact_build(const int32_t *roi, const int32_t *lab, Grid g, 
                                 CompactVol cv, uint32_t *mb, void *codes, uint32_t *tile_sums, uint32_t *coarse,
                                 int64_t W, int cus, hipStream_t st);
 
-// nparts point-balanced ranges of whole streamlines: first[nparts + 1]
-hipError_t launch_partition(const int64_t *offsets, int64_t S, int64_t nparts, int32_t *first, int cus,
-                            hipStream_t st);
+// Per-call state zeroed by the partition launch, so that it needs no launches of its own: C when
+// it is not accumulated into, the pair histogram's tile cursors, the overflow and range counters.
+// Each range may be empty.
+struct ZeroRanges {
+    int32_t *w32[2] = {nullptr, nullptr};
+    int64_t n32[2] = {0, 0};
+    unsigned long long *w64 = nullptr;
+    int64_t n64 = 0;
+};
+// nparts point-balanced ranges of whole streamlines: first[nparts + 1]; also zeroes `z`
+hipError_t launch_partition(const int64_t *offsets, int64_t S, int64_t nparts, int32_t *first, const ZeroRanges &z,
+                            int cus, hipStream_t st);
 // resident 256-thread workgroups per CU of the flat-stream kernel
 int count_stream_blocks_per_cu(bool scaled, bool packed, int batch, bool ends, int up, size_t dyn_lds);
 
@@ -156,10 +165,12 @@ hipError_t launch_count_seed_end(const CountArgs &a, const RasterVol *rv, const 
 hipError_t launch_count_stream(const CountArgs &a, const CompactVol &cv, const int32_t *first, int64_t nparts,
                                int blocks, int batch, const PairOut &po, hipStream_t st);
 // C[NM] += histogram of the updates in the slices (nwaves slices of po.cap entries, lengths in
-// po.counts), ntiles = ceil(NM / 16K).  hist: pair_hist_words(ntiles) words; sorted: nwaves * po.cap
+// po.counts), ntiles = ceil(NM / 16K).  hist: pair_hist_words(ntiles) words, of which the first
+// pair_hist_cursor_words(ntiles) (the tile cursors) must be zero on entry; sorted: nwaves * po.cap
 // words.
 hipError_t launch_pair_histogram(const PairOut &po, int32_t nwaves, int32_t ntiles, int32_t *C, int64_t NM,
                                  uint32_t *hist, uint32_t *sorted, int cus, hipStream_t st);
+inline int64_t pair_hist_cursor_words(int64_t ntiles) { return 32 * ntiles; }   // one 128-byte line per tile
 inline int64_t pair_hist_words(int64_t ntiles) {
     return 32 * (int64_t)kMaxPairTiles + kMaxPairTiles + 64 + pair_hist_blocks(ntiles) * ntiles;
 }

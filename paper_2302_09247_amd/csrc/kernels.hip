@@ -5,14 +5,21 @@
 // (loc2region applied to its points) are formed, and every (row, label) pair of the two sets adds
 // one to C.  The stages here:
 //   * compact volume build: one read of both volumes -> occupancy bits + packed codes;
-//   * partition: point-balanced chunks of whole streamlines (a binary search per chunk);
+//   * partition: point-balanced chunks of whole streamlines (a binary search per chunk); the same
+//     launch zeroes the call's per-call state;
 //   * count kernels (wave-per-streamline over raster volumes, or flat point stream over the
 //     compact volume): voxelise each point, look it up, de-duplicate the hits of each streamline
-//     in a per-wavefront LDS hash set, and add its |I| x |M| pairs into C with global atomics;
+//     in a per-wavefront LDS hash set, and emit its |I| x |M| pair updates: the flat-stream
+//     kernel appends them to per-wavefront slices of a pair buffer, the others (and a full slice)
+//     add them into C with global atomics;
+//   * pair histogram: a counting sort of the appended updates by tile of C, then one LDS
+//     histogram per tile added into C;
 //   * fallback: streamlines with more distinct keys than the LDS set holds, one workgroup each,
 //     with global bit maps.
-// Integer counting is exact and atomics commute, so every variant gives the same C.
+// Integer counting is exact and additions commute, so every variant gives the same C.
 #include "internal.h"
+
+#include <algorithm>
 
 namespace fc {
 
@@ -718,11 +725,17 @@ hipError_t launch_compact_build(const int32_t *roi, const int32_t *lab, Grid g, 
 // first[nparts] = S, with P = offsets[S] read on the device (launches stay asynchronous)
 // ---------------------------------------------------------------------------------------------
 
-__global__ void k_partition(const int64_t *__restrict__ offsets, int64_t S, int64_t nparts, int32_t *__restrict__ first) {
+__global__ void k_partition(const int64_t *__restrict__ offsets, int64_t S, int64_t nparts, int32_t *__restrict__ first,
+                            ZeroRanges z) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+        for (int64_t i = t0; i < z.n32[r]; i += stride) z.w32[r][i] = 0;
+    for (int64_t i = t0; i < z.n64; i += stride) z.w64[i] = 0ull;
     int64_t P = offsets[S];
     if (P < 0) P = 0;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= nparts; i += stride) {
+    for (int64_t i = t0; i <= nparts; i += stride) {
         if (i == nparts) {
             first[i] = (int32_t)S;
             continue;
@@ -738,8 +751,10 @@ __global__ void k_partition(const int64_t *__restrict__ offsets, int64_t S, int6
     }
 }
 
-hipError_t launch_partition(const int64_t *offsets, int64_t S, int64_t nparts, int32_t *first, int cus, hipStream_t st) {
-    k_partition<<<fill_blocks(nparts + 1, cus), kBlock, 0, st>>>(offsets, S, nparts, first);
+hipError_t launch_partition(const int64_t *offsets, int64_t S, int64_t nparts, int32_t *first, const ZeroRanges &z,
+                            int cus, hipStream_t st) {
+    const int64_t n = std::max<int64_t>(std::max<int64_t>(nparts + 1, z.n64), std::max(z.n32[0], z.n32[1]));
+    k_partition<<<fill_blocks(n, cus), kBlock, 0, st>>>(offsets, S, nparts, first, z);
     return hipGetLastError();
 }
 
@@ -2171,12 +2186,11 @@ hipError_t launch_pair_histogram(const PairOut &po, int32_t nwaves, int32_t ntil
     if (ntiles < 1 || ntiles > kMaxPairTiles || nwaves < 1) return hipErrorInvalidValue;
     const int nblk = pair_hist_blocks(ntiles);
     if ((int64_t)nblk * kMaxSlicesPerBlock < nwaves) return hipErrorInvalidValue;
-    // hist: cursors (32 words per tile) | tile bases (ntiles + 1) | per-workgroup offsets
+    // hist: cursors (32 words per tile, zero on entry) | tile bases (ntiles + 1) | per-workgroup offsets
     uint32_t *cursor = hist;
     uint32_t *base = cursor + 32 * (size_t)kMaxPairTiles;
     uint32_t *boff = base + kMaxPairTiles + 64;
-    const hipError_t fe = launch_fill_i32(reinterpret_cast<int32_t *>(cursor), 32 * (int64_t)ntiles, 0, cus, st);
-    if (fe != hipSuccess) return fe;
+    (void)cus;
     k_pair_tile_counts<<<nblk, 1024, 0, st>>>(po, nwaves, ntiles, cursor, boff);
     k_pair_tile_base<<<1, 1024, 0, st>>>(cursor, ntiles, base);
     k_pair_scatter<<<nblk, 1024, 0, st>>>(po, nwaves, ntiles, base, boff, sorted);
