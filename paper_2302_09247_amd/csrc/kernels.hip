@@ -563,15 +563,36 @@ __device__ uint32_t block_scan_incl(uint32_t v, uint32_t *lds4, uint32_t &total)
 
 constexpr int kWordsPerThread = kScanTile / kBlock;  // 8
 
-__global__ void k_compact_tile_sums(const uint32_t *__restrict__ mb, int64_t W, uint32_t *__restrict__ tile_sums) {
+// Popcount of each kScanTile-word tile.  With `brick_coarse` (a coarse map of one bit per 16x8x8
+// super-brick, 32 words each) it also writes the map: tile b is super-bricks 64b .. 64b+63, words
+// 2b and 2b+1 of the map, four threads per super-brick.
+__global__ void k_compact_tile_sums(const uint32_t *__restrict__ mb, int64_t W, uint32_t *__restrict__ tile_sums,
+                                    uint32_t *__restrict__ brick_coarse) {
+    static_assert(kScanTile == 64 * 32 && kWordsPerThread * 4 == 32, "a tile is 64 super-bricks, 4 threads each");
     __shared__ uint32_t lds4[4];
+    __shared__ uint32_t bits16[4];
     const int64_t w0 = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kWordsPerThread;
-    uint32_t s = 0;
+    uint32_t s = 0, any = 0;
     for (int k = 0; k < kWordsPerThread; ++k)
-        if (w0 + k < W) s += __popc(mb[2 * (w0 + k)]);
+        if (w0 + k < W) {
+            const uint32_t wd = mb[2 * (w0 + k)];
+            s += __popc(wd);
+            any |= wd;
+        }
+    if (brick_coarse) {
+        // lanes 4q .. 4q+3 of a wavefront cover super-brick q of its 16
+        uint64_t occ = __ballot(any != 0u);
+        occ |= occ >> 1;
+        occ |= occ >> 2;
+        uint32_t b16 = 0u;
+        for (int q = 0; q < 16; ++q) b16 |= (uint32_t)((occ >> (4 * q)) & 1ull) << q;
+        if ((threadIdx.x & 63) == 0) bits16[threadIdx.x >> 6] = b16;
+    }
     uint32_t total;
-    block_scan_incl(s, lds4, total);
+    block_scan_incl(s, lds4, total);   // (its barriers also publish bits16)
     if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
+    if (brick_coarse && threadIdx.x < 2)
+        brick_coarse[2 * blockIdx.x + threadIdx.x] = bits16[2 * threadIdx.x] | (bits16[2 * threadIdx.x + 1] << 16);
 }
 
 // one block: exclusive scan of the tile sums in place
@@ -705,7 +726,9 @@ hipError_t launch_compact_build(const int32_t *roi, const int32_t *lab, Grid g, 
     const bool vec = ((reinterpret_cast<uintptr_t>(roi) | reinterpret_cast<uintptr_t>(lab)) & 15u) == 0;
     if (vec) k_compact_mark<true><<<fill_blocks(nvox / 4, cus * 2), kBlock, 0, st>>>(roi, lab, g, N, M, cv.SBX, cv.SBXY, mb);
     else k_compact_mark<false><<<fill_blocks(nvox, cus * 2), kBlock, 0, st>>>(roi, lab, g, N, M, cv.SBX, cv.SBXY, mb);
-    k_compact_tile_sums<<<(unsigned)ntiles, kBlock, 0, st>>>(mb, W, tile_sums);
+    // the brick layout's coarse map (one bit per super-brick) comes from the tile sums pass
+    const bool brick = cv.csx == 4 && cv.csyz == 3;
+    k_compact_tile_sums<<<(unsigned)ntiles, kBlock, 0, st>>>(mb, W, tile_sums, brick ? coarse : nullptr);
     k_compact_scan_tiles<<<1, kBlock, 0, st>>>(tile_sums, ntiles);
     k_compact_bases<<<(unsigned)ntiles, kBlock, 0, st>>>(mb, tile_sums, W);
     const int64_t groups = (W + kWave - 1) / kWave;
@@ -715,8 +738,9 @@ hipError_t launch_compact_build(const int32_t *roi, const int32_t *lab, Grid g, 
     const int32_t SBZ = (int32_t)(W / 32 / cv.SBXY);
     const int32_t CBY = (g.Y + (1 << cv.csyz) - 1) >> cv.csyz, CBZ = (g.Z + (1 << cv.csyz) - 1) >> cv.csyz;
     const int64_t nthreads = (int64_t)cv.ncoarse_words * 32;
-    k_compact_coarse<<<(unsigned)((nthreads + kBlock - 1) / kBlock), kBlock, 0, st>>>(mb, cv.SBX, SBY, SBZ, cv.csx, cv.csyz,
-                                                                                    cv.CBX, CBY, CBZ, coarse);
+    if (!brick)
+        k_compact_coarse<<<(unsigned)((nthreads + kBlock - 1) / kBlock), kBlock, 0, st>>>(
+            mb, cv.SBX, SBY, SBZ, cv.csx, cv.csyz, cv.CBX, CBY, CBZ, coarse);
     return hipGetLastError();
 }
 
