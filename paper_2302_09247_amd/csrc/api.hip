@@ -171,7 +171,9 @@ int enqueue_count(Workspace &ws, int dev, const float *points, const int64_t *of
     if (!fused_zero) FC_HIP(fc::launch_fill_u64(a.ovf.count, 2, cus, st));   // overflow count and range counter
     const int64_t resident = (int64_t)cus * kBlocksPerCU;
     if (cv) {
-        const int batch = o.batch == 4 ? 4 : 2;
+        // 4-window batches keep more loads in flight per wavefront; they pay off once each
+        // wavefront's point ranges are long enough to amortise their deeper pipeline start
+        const int batch = o.batch != 0 ? o.batch : (S >= (int64_t(1) << 21) ? 4 : 2);
         int per_cu = fc::count_stream_blocks_per_cu(o.scale != 1.0f, cv->packed != 0, batch, a.ends.mode != 0,
                                                     a.up, 4 * (size_t)cv->ncoarse_words);
         if (o.blocks_per_cu > 0 && o.blocks_per_cu < per_cu) per_cu = o.blocks_per_cu;
