@@ -1774,20 +1774,45 @@ hipError_t launch_count_seed_end(const CountArgs &a, const RasterVol *rv, const 
 // label[i] = lowest m holding the row's maximum (-1 when no entry is positive), sums[i] = row sum,
 // frac[i][m] = C[i][m] / sums[i] taken in double and rounded to float (0 when the sum is not
 // positive).  Any output may be null.
+constexpr int kParcVals = 6;   // row entries per lane kept in registers (rows of up to 384 labels)
+
 __global__ void __launch_bounds__(kBlock) k_parcellate(const int32_t *__restrict__ C, int32_t N, int32_t M,
                                                        int32_t *__restrict__ label, float *__restrict__ frac,
                                                        int64_t *__restrict__ sums) {
     const int lane = lane_id();
     const int64_t nw = (int64_t)gridDim.x * kWavesPerBlock;
-    for (int64_t i = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6); i < N; i += nw) {
+    // each lane keeps entries lane + 64 q (q < kParcVals) of its wavefront's row in registers, and
+    // the next row's are loaded while this one is reduced; entries past kParcVals * 64 are read
+    // from memory
+    int v[kParcVals], vn[kParcVals];
+    auto load_row = [&](int64_t i, int (&dst)[kParcVals]) {
+#pragma unroll
+        for (int q = 0; q < kParcVals; ++q) {
+            const int m = lane + q * kWave;
+            dst[q] = (i < N && m < M) ? C[i * (int64_t)M + m] : 0;
+        }
+    };
+    int64_t i = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    load_row(i, v);
+    for (; i < N; i += nw) {
+        load_row(i + nw, vn);
         const int32_t *row = C + i * (int64_t)M;
         long long total = 0;
         int best = 0, bidx = -1;   // largest positive value seen and its lowest column
-        for (int m = lane; m < M; m += kWave) {
-            const int v = row[m];
-            total += v;
-            if (v > best) {
-                best = v;
+#pragma unroll
+        for (int q = 0; q < kParcVals; ++q) {
+            const int m = lane + q * kWave;
+            total += v[q];
+            if (m < M && v[q] > best) {
+                best = v[q];
+                bidx = m;
+            }
+        }
+        for (int m = lane + kParcVals * kWave; m < M; m += kWave) {
+            const int x = row[m];
+            total += x;
+            if (x > best) {
+                best = x;
                 bidx = m;
             }
         }
@@ -1805,9 +1830,17 @@ __global__ void __launch_bounds__(kBlock) k_parcellate(const int32_t *__restrict
         }
         if (frac) {
             const double d = (double)total;
-            for (int m = lane; m < M; m += kWave)
-                frac[i * (int64_t)M + m] = total > 0 ? (float)((double)row[m] / d) : 0.0f;
+            float *out = frac + i * (int64_t)M;
+#pragma unroll
+            for (int q = 0; q < kParcVals; ++q) {
+                const int m = lane + q * kWave;
+                if (m < M) out[m] = total > 0 ? (float)((double)v[q] / d) : 0.0f;
+            }
+            for (int m = lane + kParcVals * kWave; m < M; m += kWave)
+                out[m] = total > 0 ? (float)((double)row[m] / d) : 0.0f;
         }
+#pragma unroll
+        for (int q = 0; q < kParcVals; ++q) v[q] = vn[q];
     }
 }
 

@@ -36,7 +36,10 @@ def test_golden_rows(fc):
 
 @pytest.mark.parametrize("shape,hi", [((1, 1), 5), ((7, 64), 3), ((100, 65), 1000), ((333, 180), 1 << 24),
                                       ((50, 360), (1 << 31) // 400), ((4000, 7), 2), ((3, 1000), 1 << 20),
-                                      ((5, 128), 9), ((9, 256), 50), ((6, 257), 50), ((10, 129), 4)])
+                                      ((5, 128), 9), ((9, 256), 50), ((6, 257), 50), ((10, 129), 4),
+                                      # more rows than the grid has wavefronts: each takes several,
+                                      # the next one's entries loaded while the current is reduced
+                                      ((20000, 37), 100), ((9000, 400), 1000)])
 def test_random(fc, shape, hi):
     rng = np.random.default_rng(shape[0] * 7 + shape[1])
     C = rng.integers(0, hi, size=shape).astype(np.int64)
