@@ -631,16 +631,22 @@ __global__ void k_compact_bases(uint32_t *__restrict__ mb, const uint32_t *__res
 // Codes of the occupied voxels, in rank order.  A wavefront takes 64 words at a time and fills the
 // occupied ones two by two: word w covers x in [16 sbx, 16 sbx + 16) of rows y and y + 1 (y even) of
 // one z, so its 32 lanes read two runs of 16 consecutive voxels.
+// Occupancy words per wavefront group of the code fill: small, so that a solidly occupied region
+// (an ROI, a whole group of occupied words) is spread over many wavefronts.
+constexpr int kFillGroup = 16;
+
 template <bool PACKED>
 __global__ void k_compact_fill_codes(const uint32_t *__restrict__ mb, int64_t W, const int32_t *__restrict__ roi,
                                      const int32_t *__restrict__ lab, Grid g, CompactVol cv, int32_t SBY,
                                      void *__restrict__ codes) {
     const int lane = lane_id();
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / kWave);
-    for (int64_t grp = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x >> 6); grp * kWave < W; grp += nwaves) {
-        const int64_t w = grp * kWave + lane;
+    for (int64_t grp = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x >> 6); grp * kFillGroup < W;
+         grp += nwaves) {
+        // lanes 0 .. kFillGroup-1 read the group's words; lane k then names word k in the loop below
+        const int64_t w = grp * kFillGroup + lane;
         uint32_t word = 0u, base = 0u;
-        if (w < W) {
+        if (lane < kFillGroup && w < W) {
             word = mb[2 * w];
             base = mb[2 * w + 1];
         }
@@ -659,7 +665,7 @@ __global__ void k_compact_fill_codes(const uint32_t *__restrict__ mb, int64_t W,
             const uint32_t wd = upper ? wdb : wda, bs = upper ? bsb : bsa;
             const uint32_t j = (uint32_t)lane & 31u;
             if (((wd >> j) & 1u) && !(upper && kb == ka)) {
-                const uint32_t ww = (uint32_t)(grp * kWave + k);
+                const uint32_t ww = (uint32_t)(grp * kFillGroup + k);
                 const uint32_t sb = ww >> 5, wl = ww & 31u;
                 const uint32_t b = (wl << 5) | j;
                 const int x = (int)(sb % (uint32_t)cv.SBX) * 16 + (int)(b & 15u);
@@ -731,7 +737,7 @@ hipError_t launch_compact_build(const int32_t *roi, const int32_t *lab, Grid g, 
     k_compact_tile_sums<<<(unsigned)ntiles, kBlock, 0, st>>>(mb, W, tile_sums, brick ? coarse : nullptr);
     k_compact_scan_tiles<<<1, kBlock, 0, st>>>(tile_sums, ntiles);
     k_compact_bases<<<(unsigned)ntiles, kBlock, 0, st>>>(mb, tile_sums, W);
-    const int64_t groups = (W + kWave - 1) / kWave;
+    const int64_t groups = (W + kFillGroup - 1) / kFillGroup;
     const unsigned fblocks = (unsigned)std::min<int64_t>((groups + kWavesPerBlock - 1) / kWavesPerBlock, (int64_t)cus * 8);
     if (cv.packed) k_compact_fill_codes<true><<<fblocks, kBlock, 0, st>>>(mb, W, roi, lab, g, cv, SBY, codes);
     else k_compact_fill_codes<false><<<fblocks, kBlock, 0, st>>>(mb, W, roi, lab, g, cv, SBY, codes);
