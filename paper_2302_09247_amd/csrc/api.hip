@@ -61,7 +61,10 @@ int check_stream_args(const float *points, const int64_t *offsets, int64_t S, in
 }
 
 constexpr int kBlocksPerCU = 8;            // resident 256-thread workgroups per CU (count kernels)
-constexpr int kRangesPerWave = 4;          // flat-stream point ranges per wavefront, handed out dynamically
+constexpr int kRangesPerWave = 4;          // flat-stream point ranges per wavefront (on average), handed out
+                                           // dynamically
+constexpr int64_t kLongRangesFrom = int64_t(1) << 21;   // streamlines from which each wavefront's ranges
+                                                       // are long: 4-window batches, tapering ranges
 
 int fallback_scratch(Workspace &ws, int32_t N, int32_t M, fc::FallbackScratch &fs) {
     fs.nwordsN = (N + 31) / 32;
@@ -173,7 +176,8 @@ int enqueue_count(Workspace &ws, int dev, const float *points, const int64_t *of
     if (cv) {
         // 4-window batches keep more loads in flight per wavefront; they pay off once each
         // wavefront's point ranges are long enough to amortise their deeper pipeline start
-        const int batch = o.batch != 0 ? o.batch : (S >= (int64_t(1) << 21) ? 4 : 2);
+        const bool long_ranges = S >= kLongRangesFrom;
+        const int batch = o.batch != 0 ? o.batch : (long_ranges ? 4 : 2);
         int per_cu = fc::count_stream_blocks_per_cu(o.scale != 1.0f, cv->packed != 0, batch, a.ends.mode != 0,
                                                     a.up, 4 * (size_t)cv->ncoarse_words);
         if (o.blocks_per_cu > 0 && o.blocks_per_cu < per_cu) per_cu = o.blocks_per_cu;
@@ -209,7 +213,9 @@ int enqueue_count(Workspace &ws, int dev, const float *points, const int64_t *of
         }
         z.w64 = a.ovf.count;   // overflow count and range counter
         z.n64 = 2;
-        FC_HIP(fc::launch_partition(offsets, S, nparts, first, z, cus, st));
+        // tapering ranges (largest first) end the launch evenly when ranges are long; short ones
+        // would only add per-range work
+        FC_HIP(fc::launch_partition(offsets, S, nparts, first, z, long_ranges, cus, st));
         if (o.event_begin) FC_HIP(hipEventRecord((hipEvent_t)o.event_begin, st));
         FC_HIP(fc::launch_count_stream(a, *cv, first, nparts, (int)blocks, batch, po, st));
         if (o.event_end) FC_HIP(hipEventRecord((hipEvent_t)o.event_end, st));

@@ -143,9 +143,10 @@ struct ZeroRanges {
     unsigned long long *w64 = nullptr;
     int64_t n64 = 0;
 };
-// nparts point-balanced ranges of whole streamlines: first[nparts + 1]; also zeroes `z`
+// nparts ranges of whole streamlines, of equal point counts or (taper) of point counts falling
+// linearly from 1.5x to 0.5x the mean in range order: first[nparts + 1]; also zeroes `z`
 hipError_t launch_partition(const int64_t *offsets, int64_t S, int64_t nparts, int32_t *first, const ZeroRanges &z,
-                            int cus, hipStream_t st);
+                            bool taper, int cus, hipStream_t st);
 // resident 256-thread workgroups per CU of the flat-stream kernel
 int count_stream_blocks_per_cu(bool scaled, bool packed, int batch, bool ends, int up, size_t dyn_lds);
 

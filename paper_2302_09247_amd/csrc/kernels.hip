@@ -5,7 +5,7 @@
 // (loc2region applied to its points) are formed, and every (row, label) pair of the two sets adds
 // one to C.  The stages here:
 //   * compact volume build: one read of both volumes -> occupancy bits + packed codes;
-//   * partition: point-balanced chunks of whole streamlines (a binary search per chunk); the same
+//   * partition: chunks of whole streamlines, equal or tapering (a binary search per chunk); the same
 //     launch zeroes the call's per-call state;
 //   * count kernels (wave-per-streamline over raster volumes, or flat point stream over the
 //     compact volume): voxelise each point, look it up, de-duplicate the hits of each streamline
@@ -756,7 +756,7 @@ hipError_t launch_compact_build(const int32_t *roi, const int32_t *lab, Grid g, 
 // ---------------------------------------------------------------------------------------------
 
 __global__ void k_partition(const int64_t *__restrict__ offsets, int64_t S, int64_t nparts, int32_t *__restrict__ first,
-                            ZeroRanges z) {
+                            ZeroRanges z, int taper) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
 #pragma unroll
@@ -770,7 +770,12 @@ __global__ void k_partition(const int64_t *__restrict__ offsets, int64_t S, int6
             first[i] = (int32_t)S;
             continue;
         }
-        const int64_t target = (int64_t)(((__int128)i * P) / nparts);
+        // range i starts at the streamline holding point P * g(i / nparts).  Equal ranges: g(x) = x.
+        // Tapered: g(x) = 1.5 x - 0.5 x^2, the ranges shrinking linearly from 1.5x to 0.5x the mean
+        // in the order they are handed out, so that the last ones to start end close together.
+        const int64_t target =
+            taper ? (int64_t)(((__int128)P * i * (3 * nparts - i)) / ((__int128)2 * nparts * nparts))
+                  : (int64_t)(((__int128)i * P) / nparts);
         int64_t lo = 0, hi = S;
         while (lo < hi) {
             const int64_t mid = (lo + hi) >> 1;
@@ -782,9 +787,9 @@ __global__ void k_partition(const int64_t *__restrict__ offsets, int64_t S, int6
 }
 
 hipError_t launch_partition(const int64_t *offsets, int64_t S, int64_t nparts, int32_t *first, const ZeroRanges &z,
-                            int cus, hipStream_t st) {
+                            bool taper, int cus, hipStream_t st) {
     const int64_t n = std::max<int64_t>(std::max<int64_t>(nparts + 1, z.n64), std::max(z.n32[0], z.n32[1]));
-    k_partition<<<fill_blocks(n, cus), kBlock, 0, st>>>(offsets, S, nparts, first, z);
+    k_partition<<<fill_blocks(n, cus), kBlock, 0, st>>>(offsets, S, nparts, first, z, taper ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -906,7 +911,7 @@ hipError_t launch_count_wave(const CountArgs &a, const RasterVol &rv, int blocks
 }
 
 // ---------------------------------------------------------------------------------------------
-// count, variant 2: flat point stream over point-balanced ranges of whole streamlines
+// count, variant 2: flat point stream over ranges of whole streamlines
 // ---------------------------------------------------------------------------------------------
 //
 // Wavefront w owns the streamlines [first[w], first[w+1]): one contiguous range of about P/W
