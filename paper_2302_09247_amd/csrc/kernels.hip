@@ -2134,9 +2134,9 @@ constexpr int kScatterRound = kScatterUnroll * 1024;   // updates staged in LDS 
 // kScatterRound updates is first grouped by tile in LDS; the stores then go out in that order, so
 // neighbouring lanes write neighbouring entries of a run instead of one entry per run each.  Two
 // workgroups per CU: 64 VGPRs and 57.9 KB of LDS each.
-__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) k_pair_scatter(PairOut po, int32_t nwaves, int32_t ntiles,
-                                                       const uint32_t *__restrict__ base,
-                                                       const uint32_t *__restrict__ boff, uint32_t *__restrict__ sorted) {
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)))
+k_pair_scatter(PairOut po, int32_t nwaves, int32_t ntiles, const uint32_t *__restrict__ base,
+               const uint32_t *__restrict__ boff, uint32_t *__restrict__ sorted) {
     __shared__ uint32_t cur[kMaxPairTiles];     // next entry of this workgroup's run in each tile
     __shared__ uint32_t cnt[kMaxPairTiles];     // the round's count per tile, then its offset in stage
     __shared__ uint32_t stage[kScatterRound];   // the round's updates, grouped by tile
