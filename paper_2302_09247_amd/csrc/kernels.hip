@@ -610,8 +610,20 @@ __global__ void k_compact_scan_tiles(uint32_t *__restrict__ tile_sums, int64_t n
 }
 
 // Rank base of every occupancy word: the number of occupied voxels in the words before it.
+// Rank bases of tile b's words.  kSumTiles: tile_base holds the tiles' popcounts, and the workgroup
+// sums those before b itself (for up to kBasesSumTiles tiles); else tile_base holds their scan.
+constexpr int64_t kBasesSumTiles = 1024;
+template <bool kSumTiles>
 __global__ void k_compact_bases(uint32_t *__restrict__ mb, const uint32_t *__restrict__ tile_base, int64_t W) {
     __shared__ uint32_t lds4[4];
+    uint32_t tbase;
+    if (kSumTiles) {
+        uint32_t part = 0u;
+        for (int64_t t = threadIdx.x; t < (int64_t)blockIdx.x; t += blockDim.x) part += tile_base[t];
+        block_scan_incl(part, lds4, tbase);   // tbase = the sum over the workgroup
+    } else {
+        tbase = tile_base[blockIdx.x];
+    }
     const int64_t w0 = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kWordsPerThread;
     uint32_t words[kWordsPerThread];
     uint32_t s = 0;
@@ -620,7 +632,7 @@ __global__ void k_compact_bases(uint32_t *__restrict__ mb, const uint32_t *__res
         s += __popc(words[k]);
     }
     uint32_t total;
-    uint32_t run = tile_base[blockIdx.x] + block_scan_incl(s, lds4, total) - s;
+    uint32_t run = tbase + block_scan_incl(s, lds4, total) - s;
     for (int k = 0; k < kWordsPerThread; ++k) {
         if (w0 + k >= W) break;
         mb[2 * (w0 + k) + 1] = run;
@@ -735,8 +747,12 @@ hipError_t launch_compact_build(const int32_t *roi, const int32_t *lab, Grid g, 
     // the brick layout's coarse map (one bit per super-brick) comes from the tile sums pass
     const bool brick = cv.csx == 4 && cv.csyz == 3;
     k_compact_tile_sums<<<(unsigned)ntiles, kBlock, 0, st>>>(mb, W, tile_sums, brick ? coarse : nullptr);
-    k_compact_scan_tiles<<<1, kBlock, 0, st>>>(tile_sums, ntiles);
-    k_compact_bases<<<(unsigned)ntiles, kBlock, 0, st>>>(mb, tile_sums, W);
+    if (ntiles <= kBasesSumTiles) {
+        k_compact_bases<true><<<(unsigned)ntiles, kBlock, 0, st>>>(mb, tile_sums, W);
+    } else {
+        k_compact_scan_tiles<<<1, kBlock, 0, st>>>(tile_sums, ntiles);
+        k_compact_bases<false><<<(unsigned)ntiles, kBlock, 0, st>>>(mb, tile_sums, W);
+    }
     const int64_t groups = (W + kFillGroup - 1) / kFillGroup;
     const unsigned fblocks = (unsigned)std::min<int64_t>((groups + kWavesPerBlock - 1) / kWavesPerBlock, (int64_t)cus * 8);
     if (cv.packed) k_compact_fill_codes<true><<<fblocks, kBlock, 0, st>>>(mb, W, roi, lab, g, cv, SBY, codes);
@@ -2059,38 +2075,6 @@ __global__ void __launch_bounds__(1024) k_pair_tile_counts(PairOut po, int32_t n
         boff[(size_t)blockIdx.x * ntiles + t] = h[t] ? atomicAdd(&cursor[32 * t], h[t]) : 0u;
 }
 
-// base[t] = exclusive scan of the tile totals (cursor[32 t]), base[ntiles] = the total; one
-// workgroup of 1024 threads, ntiles <= kMaxPairTiles.
-__global__ void __launch_bounds__(1024) k_pair_tile_base(const uint32_t *__restrict__ cursor, int32_t ntiles,
-                                                         uint32_t *__restrict__ base) {
-    __shared__ uint32_t part[1024];
-    constexpr int kPer = kMaxPairTiles / 1024;
-    uint32_t v[kPer];
-    uint32_t sum = 0u;
-#pragma unroll
-    for (int j = 0; j < kPer; ++j) {
-        const int t = threadIdx.x * kPer + j;
-        v[j] = t < ntiles ? cursor[32 * t] : 0u;
-        sum += v[j];
-    }
-    part[threadIdx.x] = sum;
-    __syncthreads();
-    for (int d = 1; d < 1024; d <<= 1) {   // inclusive scan of the per-thread sums
-        const uint32_t x = threadIdx.x >= (unsigned)d ? part[threadIdx.x - d] : 0u;
-        __syncthreads();
-        part[threadIdx.x] += x;
-        __syncthreads();
-    }
-    uint32_t run = part[threadIdx.x] - sum;
-#pragma unroll
-    for (int j = 0; j < kPer; ++j) {
-        const int t = threadIdx.x * kPer + j;
-        if (t < ntiles) base[t] = run;
-        run += v[j];
-    }
-    if (threadIdx.x == 1023) base[ntiles] = part[1023];
-}
-
 // Exclusive scan of c[0 .. n) in LDS (n <= kMaxPairTiles) by a 1024-thread workgroup; thread i
 // owns entries 4i .. 4i+3 and gets their counts back in own[].  wsum: 16 words of LDS.
 __device__ __forceinline__ uint32_t block_scan_tiles(uint32_t *c, int32_t n, uint32_t (&own)[4], uint32_t *wsum) {
@@ -2130,21 +2114,33 @@ __device__ __forceinline__ uint32_t block_scan_tiles(uint32_t *c, int32_t n, uin
 constexpr int kScatterUnroll = 6;                      // loads in flight per thread (64 VGPRs in all)
 constexpr int kScatterRound = kScatterUnroll * 1024;   // updates staged in LDS per round
 
-// Each update into its tile's run of `sorted`, at workgroup b's reserved offset.  A round of up to
-// kScatterRound updates is first grouped by tile in LDS; the stores then go out in that order, so
-// neighbouring lanes write neighbouring entries of a run instead of one entry per run each.  Two
-// workgroups per CU: 64 VGPRs and 57.9 KB of LDS each.
+// Each update into its tile's run of `sorted`, at workgroup b's reserved offset.  Every workgroup
+// first scans the tile totals (cursor[32 t]) into the tiles' bases; workgroup 0 also stores them in
+// base[0 .. ntiles] for the tile pass.  A round of up to kScatterRound updates is then grouped by
+// tile in LDS and the stores go out in that order, so neighbouring lanes write neighbouring entries
+// of a run instead of one entry per run each.  Two workgroups per CU: 64 VGPRs and 57.9 KB of LDS
+// each.
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)))
-k_pair_scatter(PairOut po, int32_t nwaves, int32_t ntiles, const uint32_t *__restrict__ base,
-               const uint32_t *__restrict__ boff, uint32_t *__restrict__ sorted) {
+k_pair_scatter(PairOut po, int32_t nwaves, int32_t ntiles, const uint32_t *__restrict__ cursor,
+               uint32_t *__restrict__ base, const uint32_t *__restrict__ boff, uint32_t *__restrict__ sorted) {
     __shared__ uint32_t cur[kMaxPairTiles];     // next entry of this workgroup's run in each tile
     __shared__ uint32_t cnt[kMaxPairTiles];     // the round's count per tile, then its offset in stage
     __shared__ uint32_t stage[kScatterRound];   // the round's updates, grouped by tile
     __shared__ uint32_t pre[kMaxSlicesPerBlock + 1];
     __shared__ uint32_t wsum[16];
-    for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
-        cur[t] = base[t] + boff[(size_t)blockIdx.x * ntiles + t];
-        cnt[t] = 0u;
+    for (int t = threadIdx.x; t < ntiles; t += blockDim.x) cnt[t] = cursor[32 * t];   // tile totals
+    __syncthreads();
+    {
+        uint32_t own[4];
+        const uint32_t all = block_scan_tiles(cnt, ntiles, own, wsum);   // cnt: the tiles' bases
+        __syncthreads();
+        for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
+            cur[t] = cnt[t] + boff[(size_t)blockIdx.x * ntiles + t];
+            if (blockIdx.x == 0) base[t] = cnt[t];
+        }
+        if (blockIdx.x == 0 && threadIdx.x == 0) base[ntiles] = all;
+        __syncthreads();
+        for (int t = threadIdx.x; t < ntiles; t += blockDim.x) cnt[t] = 0u;
     }
     int32_t w0, w1;
     slice_range(nwaves, blockIdx.x, gridDim.x, w0, w1);
@@ -2260,8 +2256,7 @@ hipError_t launch_pair_histogram(const PairOut &po, int32_t nwaves, int32_t ntil
     uint32_t *boff = base + kMaxPairTiles + 64;
     (void)cus;
     k_pair_tile_counts<<<nblk, 1024, 0, st>>>(po, nwaves, ntiles, cursor, boff);
-    k_pair_tile_base<<<1, 1024, 0, st>>>(cursor, ntiles, base);
-    k_pair_scatter<<<nblk, 1024, 0, st>>>(po, nwaves, ntiles, base, boff, sorted);
+    k_pair_scatter<<<nblk, 1024, 0, st>>>(po, nwaves, ntiles, cursor, base, boff, sorted);
     k_pair_tile_add<<<ntiles, 512, 0, st>>>(sorted, base, C, NM);
     return hipGetLastError();
 }
