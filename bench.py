@@ -179,7 +179,7 @@ def main():
     if not torch.equal(Cr, C):
         raise SystemExit("resident-volume count differs from the plain count")
     resident = {"ms_per_step": 1e3 * res_elapsed / args.steps, "value": P * args.steps / res_elapsed,
-                "unit": "points/s", "step": "zero C + partition + count + overflow fallback (volume resident)"}
+                "unit": "points/s", "step": "partition (zeroes C) + count + overflow fallback + pair histogram (volume resident)"}
     vol.close()
     del Cr
     log(f"resident-volume step {resident['ms_per_step']:.3f} ms")
@@ -254,7 +254,7 @@ def main():
         "config": {"workload": "0.7mm-like subject: 260x311x260 grid, two-ellipsoid ROI, 180 shell labels, "
                                "random-walk streamlines (step 0.5 voxel, lognormal lengths median 270 in [30,1000])",
                    "S": S, "P": P, "N": w.N, "M": w.M, "pairs": pair_total,
-                   "step": "compact volume build + zero C + partition + count + overflow fallback",
+                   "step": "compact volume build + partition (zeroes C) + count + overflow fallback + pair histogram",
                    "parallelism": "1 GPU"},
         "roofline": {"bound": "hbm", "kernel": KERNEL_NAME, "achieved": achieved, "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic_per_launch(),
