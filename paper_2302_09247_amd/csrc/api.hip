@@ -507,7 +507,7 @@ int plan_build(const fastcod_subject *subjects, int32_t n, uint32_t flags, const
             const int occ = fc::count_batched_blocks_per_cu(batch, kBatchedCoarseWords);
             for (int bpc : {occ, occ - 1, occ - 2}) {
                 if (bpc < 1) continue;
-                for (int ipw : {2, 4, 8}) {
+                for (int ipw : {2, 4, 8, 16}) {
                     PlanSched c;
                     c.batch = batch;
                     c.blocks_per_cu = bpc;
