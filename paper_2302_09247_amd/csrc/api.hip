@@ -61,10 +61,13 @@ int check_stream_args(const float *points, const int64_t *offsets, int64_t S, in
 }
 
 constexpr int kBlocksPerCU = 8;            // resident 256-thread workgroups per CU (count kernels)
-constexpr int kRangesPerWave = 4;          // flat-stream point ranges per wavefront (on average), handed out
-                                           // dynamically
-constexpr int64_t kLongRangesFrom = int64_t(1) << 21;   // streamlines from which each wavefront's ranges
-                                                       // are long: 4-window batches, tapering ranges
+// Flat-stream point ranges per wavefront (on average), handed out dynamically.  Each range start
+// costs a few dependent loads and a pipeline fill, so smaller calls take fewer, longer ranges; from
+// kLongRangesFrom streamlines the ranges are long anyway, and more of them (tapering, largest
+// first) let the wavefronts finish together.
+constexpr int kRangesPerWave = 4;
+constexpr int kRangesPerWaveShort = 2;
+constexpr int64_t kLongRangesFrom = int64_t(1) << 21;   // also the threshold for 4-window batches
 
 int fallback_scratch(Workspace &ws, int32_t N, int32_t M, fc::FallbackScratch &fs) {
     fs.nwordsN = (N + 31) / 32;
@@ -182,7 +185,7 @@ int enqueue_count(Workspace &ws, int dev, const float *points, const int64_t *of
                                                     a.up, 4 * (size_t)cv->ncoarse_words);
         if (o.blocks_per_cu > 0 && o.blocks_per_cu < per_cu) per_cu = o.blocks_per_cu;
         const int64_t blocks = (int64_t)cus * per_cu;
-        const int64_t nparts = blocks * fc::kWavesPerBlock * kRangesPerWave;
+        const int64_t nparts = blocks * fc::kWavesPerBlock * (long_ranges ? kRangesPerWave : kRangesPerWaveShort);
         FC_HIP(ws.first.ensure(4 * (size_t)(nparts + 1), false));
         int32_t *first = static_cast<int32_t *>(ws.first.p);
         // pair slices: pair_capacity entries in all (default 8 per streamline, between 2^20 and
