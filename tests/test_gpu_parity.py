@@ -307,3 +307,40 @@ def test_giant_streamline_range(fc):
     del pts_cpu
     for v in (0, 2):
         np.testing.assert_array_equal(_run(fc, w, v), exp, err_msg=f"variant {v}")
+
+
+def test_many_short_streamlines(fc):
+    # more than 2^21 streamlines, of 1 to 12 points or empty: the schedule of large calls (4-window
+    # batches, 4 tapering ranges per wavefront, largest first) over ranges of a few hundred points
+    vols = synth.volumes_tiny64()
+    g = torch.Generator(device="cuda").manual_seed(31)
+    n = 1_900_000
+    seeds = synth.uniform_in_ellipsoid(n, (32.0, 32.0, 32.0), (30.0, 30.0, 30.0), g, "cuda")
+    T = torch.randint(1, 13, (n,), generator=g, device="cuda")
+    pts, L = synth.random_walks(n, seeds, T, g, None)
+    # 210k empty streamlines between the walks (they share their start with the next one)
+    lens = torch.zeros(n + 210_000, dtype=torch.int64, device="cuda")
+    walk_at = torch.sort(torch.randperm(lens.shape[0], generator=g, device="cuda")[:n]).values
+    lens[walk_at] = L
+    off = torch.zeros(lens.shape[0] + 1, dtype=torch.int64, device="cuda")
+    off[1:] = torch.cumsum(lens, 0)
+    S = lens.shape[0]
+    assert S >= (1 << 21) + 4096
+    w = synth.Workload("short", pts.contiguous(), off, torch.from_numpy(vols.roi).cuda(),
+                       torch.from_numpy(vols.lab).cuda(), vols.N, vols.M, 1.0)
+    _say(f"[parity] many short streamlines: S={S} P={int(off[-1])}")
+    pc, oc = w.points.cpu().numpy(), w.offsets.cpu().numpy()
+    for mode in (0, 1):
+        exp = oracle.count_chunked(pc, oc, vols.roi, vols.lab, vols.N, vols.M, mode=mode,
+                                   streamlines_per_chunk=1 << 16, workers=16)
+        for batch in (0, 2):
+            C = fc.count(w.points, w.offsets, w.roi, w.lab, w.N, w.M, mode=mode, batch=batch)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(C.cpu().numpy().astype(np.int64), exp,
+                                          err_msg=f"mode {mode} batch {batch}")
+        if mode == 0:
+            C = fc.count(w.points, w.offsets, w.roi, w.lab, w.N, w.M)
+            fc.count(w.points, w.offsets, w.roi, w.lab, w.N, w.M, accumulate=True, out=C)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(C.cpu().numpy().astype(np.int64), 2 * exp)
+    _say("[parity] many short streamlines bit-exact")
