@@ -8,6 +8,8 @@
   256 evenly spaced offsets per round and narrowing [lo, hi) by the count of those at or below p.
   Over nondecreasing offsets, with runs of empty streamlines, this must give the serial search's
   answer: checked here against numpy's searchsorted on random offsets.
+* Large calls split their points into ranges that taper from 1.5x to 0.5x the mean, in exact
+  integer arithmetic: checked here for the sizes of the benchmark subjects and small corner cases.
 """
 import numpy as np
 import pytest
@@ -53,3 +55,17 @@ def test_count_search_finds_the_streamline_of_a_point(seed):
         got = _search_by_counts(offsets, int(p))
         assert got == want, (S, int(p), got, want)
         assert offsets[got] <= p < offsets[got + 1]
+
+
+@pytest.mark.parametrize("P,n", [(1_097_713_418, 28_672), (112_532_461, 14_336), (1000, 7), (5, 9), (0, 4)])
+def test_tapering_range_targets(P, n):
+    # range i of the flat-stream partition starts at point P * g(i / n), g(x) = 1.5 x - 0.5 x^2, in
+    # exact integer arithmetic: targets start at 0, end at P, never decrease, and the ranges shrink
+    # linearly from 1.5x to 0.5x the mean (up to rounding)
+    i = np.arange(n + 1, dtype=object)
+    t = np.array([(P * k * (3 * n - k)) // (2 * n * n) for k in i], dtype=object)
+    assert t[0] == 0 and t[-1] == P
+    sizes = np.diff(t).astype(np.float64)
+    assert (sizes >= 0).all()
+    want = (1.5 - (np.arange(n) + 0.5) / n) * P / n   # the mean of g' over range i, times P / n
+    assert np.abs(sizes - want).max() <= 1.0 + 1e-9 * P
