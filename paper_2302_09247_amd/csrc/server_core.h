@@ -118,7 +118,11 @@ using Token = uint64_t;   // 0 = none
 
 struct Config {
     uint64_t budget = 0;              // arena bytes
-    int64_t tick_points = 1 << 25;    // points per counting launch, over all requests
+    // points per counting launch, over all requests: each launch has a fixed cost (partition,
+    // fallback, histogram and completion work), so a busy server gains from long ones (2^27: about
+    // twice the requests per second of 2^25 on a mixed stream); a lone request's launch holds only
+    // its own points either way
+    int64_t tick_points = int64_t(1) << 27;
     int64_t tick_streamlines = 1 << 20;
     int64_t chunk_points = 1 << 20;   // points per host upload piece, and the smallest share of a tick
     int32_t max_active = 64;          // requests admitted at once
