@@ -147,6 +147,24 @@ def volumes_tiny64() -> Volumes:
     return Volumes(roi, lab, N, 8, c, None, [(c, (10.0, 8.0, 7.0))])
 
 
+def volumes_interleaved64() -> Volumes:
+    """64^3 grid where ROI and labels alternate in 4-voxel cubes inside a ball of radius 30: the
+    cubes with an even (x//4 + y//4 + z//4) are ROI voxels, the odd ones carry one of M=8 labels,
+    (3 (x//4) + 5 (y//4) + 7 (z//4)) mod 8.  A walk of a few points already crosses both, so short
+    streamlines produce pairs (unlike the shell layout, where ROI and labels are 16 voxels apart)."""
+    dims = (64, 64, 64)
+    c = (32.0, 32.0, 32.0)
+    ball = ellipsoid(dims, c, (30.0, 30.0, 30.0))
+    z = np.arange(64)[:, None, None] // 4
+    y = np.arange(64)[None, :, None] // 4
+    x = np.arange(64)[None, None, :] // 4
+    even = ((x + y + z) % 2 == 0)
+    roi, N = index_in_raster_order(ball & even)
+    code = ((3 * x + 5 * y + 7 * z) % 8).astype(np.int32)
+    lab = np.where(ball & ~even, np.broadcast_to(code, ball.shape), -1).astype(np.int32)
+    return Volumes(roi, lab, N, 8, c, None, [(c, (30.0, 30.0, 30.0))])
+
+
 def volumes_subject(dims, centre, brain, roi_semi, roi_centres, M: int, shell_thickness: float,
                     rng: np.random.Generator) -> Volumes:
     """Ellipsoidal brain mask, two ROI ellipsoids (bilateral seed ROI), and M labels tiling the

@@ -311,8 +311,9 @@ def test_giant_streamline_range(fc):
 
 def test_many_short_streamlines(fc):
     # more than 2^21 streamlines, of 1 to 12 points or empty: the schedule of large calls (4-window
-    # batches, 4 tapering ranges per wavefront, largest first) over ranges of a few hundred points
-    vols = synth.volumes_tiny64()
+    # batches, 4 tapering ranges per wavefront, largest first) over ranges of a few hundred points;
+    # on a volume where short walks reach both ROI voxels and labels
+    vols = synth.volumes_interleaved64()
     g = torch.Generator(device="cuda").manual_seed(31)
     n = 1_900_000
     seeds = synth.uniform_in_ellipsoid(n, (32.0, 32.0, 32.0), (30.0, 30.0, 30.0), g, "cuda")
@@ -333,6 +334,7 @@ def test_many_short_streamlines(fc):
     for mode in (0, 1):
         exp = oracle.count_chunked(pc, oc, vols.roi, vols.lab, vols.N, vols.M, mode=mode,
                                    streamlines_per_chunk=1 << 16, workers=16)
+        assert exp.sum() > 100_000, "the case must produce pairs"
         for batch in (0, 2):
             C = fc.count(w.points, w.offsets, w.roi, w.lab, w.N, w.M, mode=mode, batch=batch)
             torch.cuda.synchronize()
@@ -344,3 +346,37 @@ def test_many_short_streamlines(fc):
             torch.cuda.synchronize()
             np.testing.assert_array_equal(C.cpu().numpy().astype(np.int64), 2 * exp)
     _say("[parity] many short streamlines bit-exact")
+
+
+def test_schedule_threshold(fc):
+    # exactly 2^21 streamlines (the smallest call on the large-call schedule: 4-window batches and
+    # 4 tapering ranges per wavefront) and the same input less its last streamline (2^21 - 1: the
+    # short-call schedule, 2-window batches and 2 even ranges per wavefront)
+    vols = synth.volumes_interleaved64()
+    g = torch.Generator(device="cuda").manual_seed(47)
+    S = 1 << 21
+    n = S - 150_000
+    seeds = synth.uniform_in_ellipsoid(n, (32.0, 32.0, 32.0), (30.0, 30.0, 30.0), g, "cuda")
+    T = torch.randint(1, 25, (n,), generator=g, device="cuda")
+    pts, L = synth.random_walks(n, seeds, T, g, None)
+    lens = torch.zeros(S, dtype=torch.int64, device="cuda")
+    walk_at = torch.sort(torch.randperm(S, generator=g, device="cuda")[:n]).values
+    lens[walk_at] = L
+    lens[-1] = 7 if int(lens[-1]) == 0 else lens[-1]   # the dropped streamline is never empty
+    off = torch.zeros(S + 1, dtype=torch.int64, device="cuda")
+    off[1:] = torch.cumsum(lens, 0)
+    need = int(off[-1])
+    if pts.shape[0] < need:
+        pts = torch.cat([pts, pts[: need - pts.shape[0]]])
+    pts = pts.contiguous()
+    roi, lab = torch.from_numpy(vols.roi).cuda(), torch.from_numpy(vols.lab).cuda()
+    pc, oc = pts.cpu().numpy(), off.cpu().numpy()
+    for s in (S, S - 1):
+        _say(f"[parity] schedule threshold: S={s} P={int(oc[s])}")
+        exp = oracle.count_chunked(pc, oc[: s + 1], vols.roi, vols.lab, vols.N, vols.M, mode=0,
+                                   streamlines_per_chunk=1 << 16, workers=16)
+        assert exp.sum() > 100_000, "the case must produce pairs"
+        C = fc.count(pts, off[: s + 1], roi, lab, vols.N, vols.M)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(C.cpu().numpy().astype(np.int64), exp, err_msg=f"S = {s}")
+    _say("[parity] schedule threshold bit-exact")
