@@ -150,7 +150,7 @@ def volumes_tiny64() -> Volumes:
 def volumes_interleaved64() -> Volumes:
     """64^3 grid where ROI and labels alternate in 4-voxel cubes inside a ball of radius 30: the
     cubes with an even (x//4 + y//4 + z//4) are ROI voxels, the odd ones carry one of M=8 labels,
-    (3 (x//4) + 5 (y//4) + 7 (z//4)) mod 8.  A walk of a few points already crosses both, so short
+    (x//4 + 2 (y//4) + 4 (z//4)) mod 8.  A walk of a few points already crosses both, so short
     streamlines produce pairs (unlike the shell layout, where ROI and labels are 16 voxels apart)."""
     dims = (64, 64, 64)
     c = (32.0, 32.0, 32.0)
@@ -160,7 +160,7 @@ def volumes_interleaved64() -> Volumes:
     x = np.arange(64)[None, None, :] // 4
     even = ((x + y + z) % 2 == 0)
     roi, N = index_in_raster_order(ball & even)
-    code = ((3 * x + 5 * y + 7 * z) % 8).astype(np.int32)
+    code = ((x + 2 * y + 4 * z) % 8).astype(np.int32)
     lab = np.where(ball & ~even, np.broadcast_to(code, ball.shape), -1).astype(np.int32)
     return Volumes(roi, lab, N, 8, c, None, [(c, (30.0, 30.0, 30.0))])
 
