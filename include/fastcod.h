@@ -173,7 +173,9 @@ typedef struct fastcod_plan fastcod_plan;
 /*
  * Builds a plan (synchronous on `stream`): compact volumes of every distinct volume pair (built
  * once, kept by the plan; the source volumes may be freed afterwards), work-item tables, scratch,
- * and the captured graph.  Points, offsets and C_out are read/written by every launch, so their
+ * and the captured graph.  A subject with streamlines, N >= 64, M >= 2 and a C_out that no other
+ * subject of the plan writes is counted into a plan-owned transposed copy [M][N] (4*N*M bytes),
+ * transposed into C_out at the end of each launch; the others count into C_out directly.  Points, offsets and C_out are read/written by every launch, so their
  * contents may change between launches but their addresses and sizes may not.
  * tune_cache: optional HOST path of a text file of tuned schedules (read, and appended to when
  * FASTCOD_PLAN_TUNE times a new kind of batch); NULL = no file.

@@ -297,7 +297,9 @@ struct fastcod_plan {
     std::vector<fc::StreamSubject> subs;   // host copy of the descriptor table
     std::vector<int64_t> points;           // P of every subject (read at creation)
     std::vector<int64_t> sizes;            // N*M of every subject
-    std::vector<void *> volumes;           // owned compact volumes
+    std::vector<void *> volumes;           // owned compact volumes and the transposed copies of C
+    struct Transposed { int32_t *ct; int32_t *C; int32_t N, M; };
+    std::vector<Transposed> transposed;    // subjects counted into CT[M][N], transposed into C_out
     DevBuf d_subs, d_sizes, d_item_base, d_items, d_ovf, d_fallback;
     fc::FallbackScratch fs{};
     fc::Overflow ovf{};
@@ -348,6 +350,7 @@ int plan_enqueue(fastcod_plan &pl, int cus, hipStream_t st) {
                                         kBatchedCoarseWords, pl.blocks, pl.sched.batch, st));
         FC_HIP(fc::launch_fallback_batched(subs, pl.n, pl.ovf, pl.fs, st));
     }
+    for (const auto &t : pl.transposed) FC_HIP(fc::launch_transpose(t.ct, t.C, t.N, t.M, false, st));
     return FASTCOD_OK;
 }
 
@@ -469,6 +472,38 @@ int plan_build(const fastcod_subject *subjects, int32_t n, uint32_t flags, const
         if (pl->subs[k].S > 0)
             FC_HIP(hipMemcpyAsync(&pl->points[k], pl->subs[k].offsets + pl->subs[k].S, 8, hipMemcpyDeviceToHost, st));
     FC_HIP(hipStreamSynchronize(st));
+    // Subjects with a C of their own (no other subject writes its C_out) count into a transposed
+    // copy CT[M][N] in one plan-owned allocation, transposed into C_out at the end of each launch:
+    // a streamline's rows are neighbouring ROI indices, so its updates under one label share memory
+    // lines there, where C[N][M] spreads them one row apart.
+    {
+        std::map<const int32_t *, int> writers;
+        for (const auto &ss : pl->subs) writers[ss.C]++;
+        std::vector<int32_t> pick;
+        size_t words = 0;
+        for (int32_t k = 0; k < n; ++k) {
+            const fastcod_subject &u = subjects[k];
+            if (pl->subs[k].S > 0 && u.M > 1 && u.N >= 64 && writers[u.C_out] == 1) {
+                pick.push_back(k);
+                words += (size_t)u.N * (size_t)u.M;
+            }
+        }
+        if (words > 0) {
+            void *buf = nullptr;
+            hipError_t e = hipMalloc(&buf, 4 * words);
+            if (e != hipSuccess) return fail(FASTCOD_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+            pl->volumes.push_back(buf);
+            int32_t *ct = static_cast<int32_t *>(buf);
+            for (int32_t k : pick) {
+                const fastcod_subject &u = subjects[k];
+                pl->transposed.push_back({ct, u.C_out, u.N, u.M});
+                pl->subs[k].C = ct;
+                pl->subs[k].si = 1u;
+                pl->subs[k].sm = (uint32_t)u.N;
+                ct += (size_t)u.N * (size_t)u.M;
+            }
+        }
+    }
     // device tables
     FC_HIP(pl->d_subs.ensure(sizeof(fc::StreamSubject) * (size_t)n, false));
     FC_HIP(pl->d_sizes.ensure(8 * (size_t)n, false));
