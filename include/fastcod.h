@@ -155,7 +155,9 @@ typedef struct fastcod_subject {
     int32_t dims[3];                  /* {X, Y, Z}, each >= 1, X*Y*Z < 2^31                              */
     int32_t N, M;                     /* N, M >= 1, N*M < 2^31                                           */
     float scale;                      /* coordinate scale, finite and > 0 (1.0f = none)                  */
-    int32_t *C_out;                   /* [N][M] int32, device; overwritten by every launch               */
+    int32_t *C_out;                   /* [N][M] int32, device; overwritten by every launch.  Subjects of
+                                         one plan may share a C_out only with equal N and M: it then
+                                         receives the sum of their counts                            */
 } fastcod_subject;
 
 /* Schedule of the batched kernel (chosen by the tuner or the defaults). */

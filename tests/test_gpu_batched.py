@@ -133,3 +133,25 @@ def test_count_batched_one_shot(fc, subjects):
         d["C"].fill_(-1)
     fc.count_batched(subjects)
     _check_all(subjects)
+
+
+def test_subjects_sharing_one_C_receive_the_sum(fc):
+    # two subjects on the same volumes writing one C_out (counted straight into it, no transposed
+    # copy) and a third with a C of its own (counted through the transposed copy), in one plan,
+    # launched twice: the shared C holds the sum of both subjects' counts after every launch
+    a = synth.make_tiny64(seed=21, S=3000, device="cuda")
+    b = synth.make_tiny64(seed=22, S=2000, device="cuda")
+    c = synth.make_tiny64(seed=23, S=2500, device="cuda")
+    shared = torch.full((a.N, a.M), -3, dtype=torch.int32, device="cuda")
+    subs = [_subject(a), _subject(b), _subject(c)]
+    subs[0]["C"] = shared
+    subs[1]["C"] = shared
+    exp_ab = sum(oracle.count(w.points, w.offsets, w.roi, w.lab, w.N, w.M) for w in (a, b))
+    exp_c = oracle.count(c.points, c.offsets, c.roi, c.lab, c.N, c.M)
+    assert exp_ab.sum() > 0 and exp_c.sum() > 0
+    plan = fc.Plan(subs)
+    for _ in range(2):
+        plan.launch()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(shared.cpu().numpy(), exp_ab)
+        np.testing.assert_array_equal(subs[2]["C"].cpu().numpy(), exp_c)
