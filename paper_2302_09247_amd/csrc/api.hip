@@ -298,8 +298,9 @@ struct fastcod_plan {
     std::vector<int64_t> points;           // P of every subject (read at creation)
     std::vector<int64_t> sizes;            // N*M of every subject
     std::vector<void *> volumes;           // owned compact volumes and the transposed copies of C
-    struct Transposed { int32_t *ct; int32_t *C; int32_t N, M; };
-    std::vector<Transposed> transposed;    // subjects counted into CT[M][N], transposed into C_out
+    std::vector<fc::TransposeJob> transposed;   // subjects counted into CT[M][N], transposed into C_out
+    int64_t transpose_tiles = 0;
+    DevBuf d_transposed;                        // device copy of `transposed`
     DevBuf d_subs, d_sizes, d_item_base, d_items, d_ovf, d_fallback;
     fc::FallbackScratch fs{};
     fc::Overflow ovf{};
@@ -350,7 +351,8 @@ int plan_enqueue(fastcod_plan &pl, int cus, hipStream_t st) {
                                         kBatchedCoarseWords, pl.blocks, pl.sched.batch, st));
         FC_HIP(fc::launch_fallback_batched(subs, pl.n, pl.ovf, pl.fs, st));
     }
-    for (const auto &t : pl.transposed) FC_HIP(fc::launch_transpose(t.ct, t.C, t.N, t.M, false, st));
+    FC_HIP(fc::launch_transpose_many(static_cast<const fc::TransposeJob *>(pl.d_transposed.p),
+                                     (int32_t)pl.transposed.size(), pl.transpose_tiles, cus, st));
     return FASTCOD_OK;
 }
 
@@ -384,6 +386,7 @@ void plan_free(fastcod_plan *pl) {
     pl->d_items.release();
     pl->d_ovf.release();
     pl->d_fallback.release();
+    pl->d_transposed.release();
     delete pl;
 }
 
@@ -496,7 +499,8 @@ int plan_build(const fastcod_subject *subjects, int32_t n, uint32_t flags, const
             int32_t *ct = static_cast<int32_t *>(buf);
             for (int32_t k : pick) {
                 const fastcod_subject &u = subjects[k];
-                pl->transposed.push_back({ct, u.C_out, u.N, u.M});
+                pl->transposed.push_back({ct, u.C_out, u.N, u.M, pl->transpose_tiles});
+                pl->transpose_tiles += (int64_t)((u.N + 31) / 32) * (int64_t)((u.M + 31) / 32);
                 pl->subs[k].C = ct;
                 pl->subs[k].si = 1u;
                 pl->subs[k].sm = (uint32_t)u.N;
@@ -505,6 +509,11 @@ int plan_build(const fastcod_subject *subjects, int32_t n, uint32_t flags, const
         }
     }
     // device tables
+    if (!pl->transposed.empty()) {
+        const size_t tb = sizeof(fc::TransposeJob) * pl->transposed.size();
+        FC_HIP(pl->d_transposed.ensure(tb, false));
+        FC_HIP(hipMemcpyAsync(pl->d_transposed.p, pl->transposed.data(), tb, hipMemcpyHostToDevice, st));
+    }
     FC_HIP(pl->d_subs.ensure(sizeof(fc::StreamSubject) * (size_t)n, false));
     FC_HIP(pl->d_sizes.ensure(8 * (size_t)n, false));
     FC_HIP(hipMemcpyAsync(pl->d_subs.p, pl->subs.data(), sizeof(fc::StreamSubject) * (size_t)n, hipMemcpyHostToDevice, st));

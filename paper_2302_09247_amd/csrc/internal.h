@@ -183,6 +183,17 @@ hipError_t launch_fallback_compact(const CountArgs &a, const CompactVol &cv, Fal
 // C[i][m] = CT[m][i] (or += with accumulate), C [N][M], CT [M][N]
 hipError_t launch_transpose(const int32_t *CT, int32_t *C, int32_t N, int32_t M, bool accumulate, hipStream_t st);
 
+// One transpose of a batch: C[i][m] = CT[m][i] over 32x32 tiles, tiles numbered from first_tile
+// (the running sum of ceil(N/32) * ceil(M/32) over the jobs before it)
+struct TransposeJob {
+    const int32_t *CT;
+    int32_t *C;
+    int32_t N, M;
+    int64_t first_tile;
+};
+// every job of `jobs` (device array of njobs, first_tile increasing from 0; ntiles tiles in all)
+hipError_t launch_transpose_many(const TransposeJob *jobs, int32_t njobs, int64_t ntiles, int cus, hipStream_t st);
+
 // batched form
 hipError_t launch_zero_subjects(const StreamSubject *subs, const int64_t *sizes, int32_t nsub, int cus, hipStream_t st);
 hipError_t launch_partition_batched(const StreamSubject *subs, const int64_t *item_base, int32_t nsub, int64_t nitems,

@@ -2007,6 +2007,44 @@ hipError_t launch_transpose(const int32_t *CT, int32_t *C, int32_t N, int32_t M,
     return hipGetLastError();
 }
 
+// Grid-stride over the tiles of all jobs; each tile finds its job by a binary search over
+// first_tile (block-uniform, so the barriers stay uniform).
+__global__ void __launch_bounds__(256) k_transpose_many(const TransposeJob *__restrict__ jobs, int32_t njobs,
+                                                        int64_t ntiles) {
+    __shared__ int32_t tile[32][33];
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        int lo = 0, hi = njobs;   // jobs[lo].first_tile <= t, and t < jobs[hi].first_tile (or ntiles)
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (jobs[mid].first_tile <= t) lo = mid;
+            else hi = mid;
+        }
+        const TransposeJob j = jobs[lo];
+        const int64_t local = t - j.first_tile;
+        const int64_t tn = (j.N + 31) / 32;
+        const int i0 = (int)(local % tn) * 32, m0 = (int)(local / tn) * 32;
+        for (int k = ty; k < 32; k += 8) {
+            const int m = m0 + k, i = i0 + tx;
+            tile[k][tx] = (m < j.M && i < j.N) ? j.CT[(int64_t)m * j.N + i] : 0;
+        }
+        __syncthreads();
+        for (int k = ty; k < 32; k += 8) {
+            const int i = i0 + k, m = m0 + tx;
+            if (i < j.N && m < j.M) j.C[(int64_t)i * j.M + m] = tile[tx][k];
+        }
+        __syncthreads();   // the tile is rewritten by the next iteration
+    }
+}
+
+hipError_t launch_transpose_many(const TransposeJob *jobs, int32_t njobs, int64_t ntiles, int cus, hipStream_t st) {
+    if (njobs <= 0 || ntiles <= 0) return hipSuccess;
+    const int64_t cap = (int64_t)(cus > 0 ? cus : 64) * 16;
+    const unsigned blocks = (unsigned)std::min<int64_t>(ntiles, cap);
+    k_transpose_many<<<blocks, 256, 0, st>>>(jobs, njobs, ntiles);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------------------------
 // histogram of appended C updates: a counting sort by tile of C, then one LDS histogram per tile
 // ---------------------------------------------------------------------------------------------
