@@ -500,7 +500,8 @@ int plan_build(const fastcod_subject *subjects, int32_t n, uint32_t flags, const
             for (int32_t k : pick) {
                 const fastcod_subject &u = subjects[k];
                 pl->transposed.push_back({ct, u.C_out, u.N, u.M, pl->transpose_tiles});
-                pl->transpose_tiles += (int64_t)((u.N + 31) / 32) * (int64_t)((u.M + 31) / 32);
+                pl->transpose_tiles += (int64_t)((u.N + fc::kTransposeTile - 1) / fc::kTransposeTile) *
+                                       (int64_t)((u.M + fc::kTransposeTile - 1) / fc::kTransposeTile);
                 pl->subs[k].C = ct;
                 pl->subs[k].si = 1u;
                 pl->subs[k].sm = (uint32_t)u.N;

@@ -183,8 +183,9 @@ hipError_t launch_fallback_compact(const CountArgs &a, const CompactVol &cv, Fal
 // C[i][m] = CT[m][i] (or += with accumulate), C [N][M], CT [M][N]
 hipError_t launch_transpose(const int32_t *CT, int32_t *C, int32_t N, int32_t M, bool accumulate, hipStream_t st);
 
-// One transpose of a batch: C[i][m] = CT[m][i] over 32x32 tiles, tiles numbered from first_tile
-// (the running sum of ceil(N/32) * ceil(M/32) over the jobs before it)
+// One transpose of a batch: C[i][m] = CT[m][i] over kTransposeTile^2 tiles, tiles numbered from
+// first_tile (the running sum of ceil(N/kTransposeTile) * ceil(M/kTransposeTile) over the jobs before it)
+constexpr int kTransposeTile = 64;
 struct TransposeJob {
     const int32_t *CT;
     int32_t *C;

@@ -2008,11 +2008,14 @@ hipError_t launch_transpose(const int32_t *CT, int32_t *C, int32_t N, int32_t M,
 }
 
 // Grid-stride over the tiles of all jobs; each tile finds its job by a binary search over
-// first_tile (block-uniform, so the barriers stay uniform).
+// first_tile (block-uniform, so the barriers stay uniform).  A 64x64 tile gives every thread 16
+// loads in flight before its stores.
 __global__ void __launch_bounds__(256) k_transpose_many(const TransposeJob *__restrict__ jobs, int32_t njobs,
                                                         int64_t ntiles) {
-    __shared__ int32_t tile[32][33];
-    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+    constexpr int T = kTransposeTile;
+    __shared__ int32_t tile[T][T + 1];
+    const int tx = threadIdx.x & (T - 1), ty = threadIdx.x / T;   // T x (256 / T)
+    constexpr int R = 256 / T;
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         int lo = 0, hi = njobs;   // jobs[lo].first_tile <= t, and t < jobs[hi].first_tile (or ntiles)
         while (hi - lo > 1) {
@@ -2022,14 +2025,16 @@ __global__ void __launch_bounds__(256) k_transpose_many(const TransposeJob *__re
         }
         const TransposeJob j = jobs[lo];
         const int64_t local = t - j.first_tile;
-        const int64_t tn = (j.N + 31) / 32;
-        const int i0 = (int)(local % tn) * 32, m0 = (int)(local / tn) * 32;
-        for (int k = ty; k < 32; k += 8) {
+        const int64_t tn = (j.N + T - 1) / T;
+        const int i0 = (int)(local % tn) * T, m0 = (int)(local / tn) * T;
+#pragma unroll
+        for (int k = ty; k < T; k += R) {
             const int m = m0 + k, i = i0 + tx;
             tile[k][tx] = (m < j.M && i < j.N) ? j.CT[(int64_t)m * j.N + i] : 0;
         }
         __syncthreads();
-        for (int k = ty; k < 32; k += 8) {
+#pragma unroll
+        for (int k = ty; k < T; k += R) {
             const int i = i0 + k, m = m0 + tx;
             if (i < j.N && m < j.M) j.C[(int64_t)i * j.M + m] = tile[tx][k];
         }
