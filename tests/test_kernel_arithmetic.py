@@ -10,6 +10,10 @@
   answer: checked here against numpy's searchsorted on random offsets.
 * Large calls split their points into ranges that taper from 1.5x to 0.5x the mean, in exact
   integer arithmetic: checked here for the sizes of the benchmark subjects and small corner cases.
+* A batched plan transposes all subjects' copies of C in one grid of 64x64 tiles, numbered subject
+  after subject; each tile finds its subject by a binary search over the subjects' first tiles and
+  its corner from its local number.  Every entry of every subject must be written by exactly one
+  tile: checked here for ragged N and M.
 """
 import numpy as np
 import pytest
@@ -69,3 +73,32 @@ def test_tapering_range_targets(P, n):
     assert (sizes >= 0).all()
     want = (1.5 - (np.arange(n) + 0.5) / n) * P / n   # the mean of g' over range i, times P / n
     assert np.abs(sizes - want).max() <= 1.0 + 1e-9 * P
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_transpose_tiles_cover_every_entry_once(seed):
+    T = 64
+    rng = np.random.default_rng(seed)
+    shapes = [(int(rng.integers(64, 700)), int(rng.integers(2, 200))) for _ in range(int(rng.integers(1, 9)))]
+    shapes += [(64, 2), (65, 64), (128, 65)]
+    first, total = [], 0
+    for N, M in shapes:
+        first.append(total)
+        total += ((N + T - 1) // T) * ((M + T - 1) // T)
+    hits = [np.zeros((N, M), np.int64) for N, M in shapes]
+    for t in range(total):
+        lo, hi = 0, len(shapes)
+        while hi - lo > 1:
+            mid = (lo + hi) >> 1
+            if first[mid] <= t:
+                lo = mid
+            else:
+                hi = mid
+        N, M = shapes[lo]
+        local = t - first[lo]
+        tn = (N + T - 1) // T
+        i0, m0 = (local % tn) * T, (local // tn) * T
+        assert i0 < N and m0 < M
+        hits[lo][i0:min(i0 + T, N), m0:min(m0 + T, M)] += 1
+    for h in hits:
+        assert (h == 1).all()
