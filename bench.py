@@ -78,6 +78,120 @@ def traffic_per_launch():
     return t.get("bytes_per_launch")
 
 
+def host_info() -> dict:
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "cpus_usable": len(os.sched_getaffinity(0)), "nproc": os.cpu_count()}
+
+
+def oracle_workers() -> int:
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def cpu_config_baselines(fastcod, synth, vols07, w07, C07):
+    """The oracle on the 64^3 and 1.25 mm subjects (in full, 1 thread and all usable threads) and on the
+    0.7 mm subject (in full on all usable threads), each result compared element by element with the
+    GPU's C of the same input."""
+    import numpy as np
+    import torch
+    import oracle
+    workers = oracle_workers()
+    rows = []
+    for name, make in (("64^3", lambda: synth.make_tiny64(seed=1, S=10_000, device="cuda")),
+                       ("1.25mm", lambda: synth.make_125mm(S=1_000_000, device="cuda"))):
+        w = make()
+        C = fastcod.count(w.points, w.offsets, w.roi, w.lab, w.N, w.M)
+        pts, off = w.points.cpu().numpy(), w.offsets.cpu().numpy()
+        roi, lab = w.roi.cpu().numpy(), w.lab.cpu().numpy()
+        t0 = time.perf_counter()
+        e1 = oracle.count(pts, off, roi, lab, w.N, w.M)
+        d1 = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        ea = oracle.count_chunked(pts, off, roi, lab, w.N, w.M, streamlines_per_chunk=1 << 14, workers=workers)
+        da = time.perf_counter() - t0
+        got = C.cpu().numpy().astype(np.int64)
+        rows.append({"config": name, "S": w.S, "P": w.P, "points_per_s_1core": w.P / d1,
+                     "points_per_s_all_cores": w.P / da, "threads": workers,
+                     "bit_exact": bool(np.array_equal(got, e1) and np.array_equal(got, ea))})
+        log(f"cpu oracle {name}: {w.P / d1:.3e} points/s (1 thread), {w.P / da:.3e} ({workers} threads), "
+            f"bit_exact={rows[-1]['bit_exact']}")
+        del w, C
+    t0 = time.perf_counter()
+    pts = w07.points.cpu().numpy()
+    off = w07.offsets.cpu().numpy()
+    t_copy = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    e = oracle.count_chunked(pts, off, vols07.roi, vols07.lab, w07.N, w07.M, streamlines_per_chunk=1 << 16,
+                             workers=workers)
+    da = time.perf_counter() - t0
+    ok = bool(np.array_equal(C07.cpu().numpy().astype(np.int64), e))
+    rows.append({"config": "0.7mm", "S": w07.S, "P": w07.P, "points_per_s_1core": None,
+                 "points_per_s_all_cores": w07.P / da, "threads": workers, "bit_exact": ok,
+                 "note": f"1-thread rate: cpu_baseline (a 3M-streamline sample); points copied to the host in "
+                         f"{t_copy:.1f} s (outside the timing)"})
+    log(f"cpu oracle 0.7mm (whole subject): {w07.P / da:.3e} points/s on {workers} threads, bit_exact={ok}")
+    return rows
+
+
+def run_ceilings(fastcod, points, vol, scale=1.0, nwords_small=45808 * 180, reps=5) -> dict:
+    """The ceiling probes (include/fastcod_probe.h) on this device: the read-only point stream and the
+    stream plus every point's compact-volume lookups over `points`, and no-return int32 atomics at
+    2^26 indices in three patterns -- uniform over a C of the 0.7 mm size (33 MB), uniform over 710 MB
+    (the batched subjects' matrices together), and runs of 8 consecutive entries (one streamline's
+    neighbouring ROI rows under one label in a transposed C) over 33 MB."""
+    import torch
+    ev = HipEvents()
+    hip = ev.hip
+    hip.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        fn()
+        a, b = ev.create(), ev.create()
+        hip.hipEventRecord(a, stream.cuda_stream)
+        for _ in range(reps):
+            fn()
+        hip.hipEventRecord(b, stream.cuda_stream)
+        ms = ev.elapsed_ms(a, b) / reps
+        ev.destroy(a)
+        ev.destroy(b)
+        return ms
+
+    P = int(points.shape[0])
+    out = {}
+    ms = timed(lambda: fastcod.probe_stream(points))
+    out["stream"] = {"ms": ms, "GBps": 12 * P / (ms * 1e-3) / 1e9, "bytes": 12 * P}
+    ms = timed(lambda: fastcod.probe_lookup(vol, points, scale=scale))
+    out["stream_lookup"] = {"ms": ms, "GBps": 12 * P / (ms * 1e-3) / 1e9, "points_per_s": P / (ms * 1e-3)}
+    n = 1 << 26
+    g = torch.Generator(device="cuda")
+    g.manual_seed(123)
+    pats = {}
+    big = 710 * (1 << 20) // 4
+    for name, nwords in (("random_33MB", nwords_small), ("random_710MB", big), ("runs8_33MB", nwords_small)):
+        if name.startswith("runs8"):
+            base = torch.randint(0, nwords // 8, (n // 8, 1), generator=g, device="cuda", dtype=torch.int64) * 8
+            idx = (base + torch.arange(8, device="cuda")).reshape(-1).to(torch.int32)
+        else:
+            idx = torch.randint(0, nwords, (n,), generator=g, device="cuda", dtype=torch.int32)
+        target = torch.zeros(nwords, dtype=torch.int32, device="cuda")
+        ms = timed(lambda: fastcod.probe_atomics(target, idx))
+        pats[name] = {"ms": ms, "atomics_per_s": n / (ms * 1e-3), "atomics": n, "target_bytes": 4 * nwords}
+        del idx, target
+    out["atomics"] = pats
+    torch.cuda.empty_cache()
+    for k, v in out.items():
+        log(f"ceiling {k}: {v}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,10 +199,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--streamlines", type=int, default=5_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-form keys of the default line")
+    ap.add_argument("--no-served", action="store_true", help="skip the served-form keys of the default line")
     ap.add_argument("--cpu-sample-streamlines", type=int, default=3_000_000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (for rocprofv3 counter scaling)")
-    ap.add_argument("--form", choices=("plain", "batched", "served", "sr"), default="plain",
+    ap.add_argument("--form", choices=("plain", "batched", "served", "sr", "ceilings"), default="plain",
                     help="plain: the 0.7 mm subject (default); batched: many subjects in one graph launch; "
                          "served: Poisson request stream")
     ap.add_argument("--subjects", type=int, default=32)
@@ -123,6 +239,8 @@ def main():
         return bench_served(args)
     if args.form == "sr":
         return bench_sr(args)
+    if args.form == "ceilings":
+        return bench_ceilings(args)
     t0 = time.time()
     vols = synth.volumes_07mm()
     log(f"volumes: N={vols.N} M={vols.M} dims={vols.dims} ({time.time() - t0:.1f}s)")
@@ -130,16 +248,15 @@ def main():
     w = synth.make_07mm(S=args.streamlines, device="cuda", vols=vols)
     torch.cuda.synchronize()
     S, P = w.S, w.P
+    X, Y, Z = vols.dims
     log(f"workload: S={S} P={P} ({12 * P / 1e9:.2f} GB of points) generated in {time.time() - t0:.1f}s")
 
     ev = HipEvents()
     stream = torch.cuda.current_stream()
     C = torch.empty((w.N, w.M), dtype=torch.int32, device="cuda")
-    pairs = []
     for i in range(args.warmup):
         fastcod.count(w.points, w.offsets, w.roi, w.lab, w.N, w.M, out=C, stream=stream)
     torch.cuda.synchronize()
-    pair_total = int(C.sum(dtype=torch.int64).item()) if args.warmup else None
 
     evs = [(ev.create(), ev.create()) for _ in range(args.steps)]
     torch.cuda.synchronize()
@@ -152,14 +269,13 @@ def main():
     for a, b in evs:
         ev.destroy(a)
         ev.destroy(b)
-    if pair_total is None:
-        pair_total = int(C.sum(dtype=torch.int64).item())
-    pairs.append(pair_total)
+    pair_total = int(C.sum(dtype=torch.int64).item())
 
     ms_per_step = 1e3 * elapsed / args.steps
     value = P * args.steps / elapsed
     k_ms = sum(kernel_ms) / len(kernel_ms)
-    alg_bytes = 12 * P + 8 * (S + 1) + 4 * pair_total
+    # algorithmic bytes of one step: points, offsets, both volumes read once, C written once
+    alg_bytes = 12 * P + 8 * (S + 1) + 8 * X * Y * Z + 4 * w.N * w.M
     achieved = alg_bytes / (k_ms * 1e-3) / 1e9
     log(f"step {ms_per_step:.3f} ms, {KERNEL_NAME} avg {k_ms:.3f} ms (min {min(kernel_ms):.3f}), "
         f"{achieved:.0f} GB/s algorithmic, pairs {pair_total}")
@@ -178,11 +294,16 @@ def main():
     res_elapsed = time.perf_counter() - t_start
     if not torch.equal(Cr, C):
         raise SystemExit("resident-volume count differs from the plain count")
-    resident = {"ms_per_step": 1e3 * res_elapsed / args.steps, "value": P * args.steps / res_elapsed,
+    res_ms = 1e3 * res_elapsed / args.steps
+    resident = {"ms_per_step": res_ms, "value": P * args.steps / res_elapsed,
                 "unit": "points/s", "step": "partition (zeroes C) + count + overflow fallback + pair histogram (volume resident)"}
     vol.close()
     del Cr
-    log(f"resident-volume step {resident['ms_per_step']:.3f} ms")
+    log(f"resident-volume step {res_ms:.3f} ms")
+
+    vol = fastcod.Volume(w.roi, w.lab, w.N, w.M, stream=stream)
+    ceilings = run_ceilings(fastcod, w.points, vol)
+    vol.close()
 
     # the parcellation outputs of this C (single-colour labels, pie-glyph fractions, row sums)
     pa = []
@@ -215,29 +336,54 @@ def main():
     log(f"device copy: {copy_gbps:.0f} GB/s (read + write)")
 
     cpu = cpu_parallel = None
+    cpu_configs = None
+    bit_exact = None
     if not args.no_cpu_baseline:
+        import numpy as np
         import oracle
         ns = min(args.cpu_sample_streamlines, S)
         p_end = int(w.offsets[ns].item())
+        # the GPU's C of the same sample, for the element-by-element check
+        Cs = fastcod.count(w.points[:p_end], w.offsets[:ns + 1].contiguous(), w.roi, w.lab, w.N, w.M)
+        got = Cs.cpu().numpy().astype(np.int64)
+        del Cs
         pts = w.points[:p_end].cpu().numpy()
         off = w.offsets[:ns + 1].cpu().numpy()
         roi, lab = vols.roi, vols.lab
         t0 = time.perf_counter()
-        oracle.count(pts, off, roi, lab, w.N, w.M)
+        exp = oracle.count(pts, off, roi, lab, w.N, w.M)
         dt = time.perf_counter() - t0
+        sample_exact = bool(np.array_equal(got, exp))
         cpu = {"value": p_end / dt, "unit": "points/s", "cores": 1, "kind": "oracle",
                "sample": f"first {ns} of {S} streamlines ({p_end} points) of the same workload, "
-                         f"single-threaded C oracle, {dt:.1f} s on {os.cpu_count()} visible host CPUs"}
-        log(f"cpu oracle: {p_end / dt:.3e} points/s over {dt:.1f}s")
-        # the same sample on all host cores (the oracle is additive over streamline ranges)
-        workers = max(1, min(16, os.cpu_count() or 1))
+                         f"single-threaded C oracle, {dt:.1f} s",
+               "bit_exact": sample_exact, **host_info()}
+        log(f"cpu oracle: {p_end / dt:.3e} points/s over {dt:.1f}s, GPU C of the sample bit-exact: {sample_exact}")
+        # the same sample on all usable host cores (the oracle is additive over streamline ranges)
+        workers = oracle_workers()
         t0 = time.perf_counter()
-        oracle.count_chunked(pts, off, roi, lab, w.N, w.M, streamlines_per_chunk=1 << 16, workers=workers)
+        exp2 = oracle.count_chunked(pts, off, roi, lab, w.N, w.M, streamlines_per_chunk=1 << 16, workers=workers)
         dtp = time.perf_counter() - t0
         cpu_parallel = {"value": p_end / dtp, "unit": "points/s", "cores": workers, "kind": "oracle",
-                        "sample": f"the same {p_end} points, 2^16-streamline ranges on {workers} threads, {dtp:.1f} s"}
+                        "sample": f"the same {p_end} points, 2^16-streamline ranges on {workers} threads, {dtp:.1f} s",
+                        "bit_exact": bool(np.array_equal(got, exp2))}
         log(f"cpu oracle on {workers} threads: {p_end / dtp:.3e} points/s over {dtp:.1f}s")
+        del pts, off, exp, exp2, got
+        cpu_configs = cpu_config_baselines(fastcod, synth, vols, w, C)
+        bit_exact = sample_exact and all(r["bit_exact"] for r in cpu_configs)
 
+    roofline = {"bound": "hbm", "kernel": KERNEL_NAME, "achieved": achieved, "peak": HBM_PEAK_GBPS,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic_per_launch(),
+                "kernel_ms": k_ms, "algorithmic_bytes": alg_bytes,
+                "bytes_model": "12 P + 8 (S+1) + 8 X Y Z + 4 N M",
+                "frac_resident_step": alg_bytes / (res_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+                "frac_step": alg_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+                "pair_updates_per_s": pair_total / (k_ms * 1e-3),
+                "copy_GBps": copy_gbps,
+                "stream_ceiling_GBps": ceilings["stream"]["GBps"],
+                "stream_lookup_ceiling_GBps": ceilings["stream_lookup"]["GBps"],
+                "frac_of_stream_ceiling": (12 * P / (k_ms * 1e-3) / 1e9) / ceilings["stream"]["GBps"],
+                "atomic_ceiling_per_s": ceilings["atomics"]["random_33MB"]["atomics_per_s"]}
     out = {
         "metric": "streamline points/s into bit-exact C[NxM]; HBM GB/s as % of MI355X peak",
         "value": value,
@@ -256,29 +402,47 @@ def main():
                    "S": S, "P": P, "N": w.N, "M": w.M, "pairs": pair_total,
                    "step": "compact volume build + partition (zeroes C) + count + overflow fallback + pair histogram",
                    "parallelism": "1 GPU"},
-        "roofline": {"bound": "hbm", "kernel": KERNEL_NAME, "achieved": achieved, "peak": HBM_PEAK_GBPS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic_per_launch(),
-                     "kernel_ms": k_ms, "algorithmic_bytes": alg_bytes,
-                     "copy_GBps": copy_gbps},
+        "bit_exact": bit_exact,
+        "roofline": roofline,
         "cpu_baseline": cpu,
         "cpu_baseline_all_cores": cpu_parallel,
+        "cpu_baseline_configs": cpu_configs,
         "resident_volume": resident,
         "parcellate": parcellate,
+        "ceilings": ceilings,
     }
+    del w, C
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    if not args.no_batched:
+        b = run_batched(args, fastcod, synth)
+        out["batched"] = {k: b[k] for k in ("batched_ms", "plain_ms", "batched_over_plain", "bit_identical",
+                                             "points_per_s", "plain_points_per_s", "algorithmic_GBps", "frac",
+                                             "pair_updates_per_s", "schedule", "S", "P")}
+        # every pair update of the batched kernel is a no-return atomic into its subject's C
+        out["batched"]["atomics_per_s"] = b["pair_updates_per_s"]
+        out["batched"]["atomic_ceiling_per_s"] = ceilings["atomics"]["random_710MB"]["atomics_per_s"]
+        torch.cuda.empty_cache()
+    if not args.no_served:
+        r = run_served(args, fastcod, synth, [0.5, 0.9])
+        out["served"] = {"saturation_requests_per_s": r["saturation"],
+                         "points_per_s_at_saturation": r["points_per_s_at_saturation"],
+                         "rates": [{k: row[k] for k in ("rate_frac", "rate", "p50_ms", "p99_ms", "throughput")}
+                                   for row in r["sweep"]],
+                         "bit_identical": r["bit_identical"], "requests_per_rate": args.served_requests}
     print(json.dumps(out), flush=True)
 
 
-def bench_batched(args):
+def run_batched(args, fastcod, synth) -> dict:
     """All subjects of the batched workload counted by one tuned, graph-captured plan launch, against
     the same subjects counted one by one with resident volumes (plain path) on the same GPU."""
     import torch
-    from paper_2302_09247_amd import fastcod, synth
     t0 = time.time()
     subs = []
     for k in range(args.subjects):
         w = synth.make_batch_subject(k, device="cuda")
         subs.append(dict(points=w.points, offsets=w.offsets, roi=w.roi, lab=w.lab, N=w.N, M=w.M, scale=1.0,
-                         C=torch.empty((w.N, w.M), dtype=torch.int32, device="cuda")))
+                         C=torch.empty((w.N, w.M), dtype=torch.int32, device="cuda"), dims=w.dims))
         log(f"subject {k}: dims {w.dims} N={w.N} M={w.M} S={w.S} P={w.P}")
     torch.cuda.synchronize()
     P = sum(int(d["points"].shape[0]) for d in subs)
@@ -322,20 +486,53 @@ def bench_batched(args):
     for v in vols:
         v.close()
     plan.close()
-    alg_bytes = 12 * P + 8 * (S + len(subs)) + 4 * pairs
+    vox = sum(d["dims"][0] * d["dims"][1] * d["dims"][2] for d in subs)
+    nm = sum(d["N"] * d["M"] for d in subs)
+    alg_bytes = 12 * P + 8 * (S + len(subs)) + 8 * vox + 4 * nm
     log(f"batched {batched_ms:.3f} ms per launch, plain sum {plain_ms:.3f} ms, identical={identical}")
+    del subs, batched_C, outs
+    return {"batched_ms": batched_ms, "plain_ms": plain_ms, "batched_over_plain": plain_ms / batched_ms,
+            "bit_identical": identical, "points_per_s": P / (batched_ms * 1e-3),
+            "plain_points_per_s": P / (plain_ms * 1e-3), "algorithmic_bytes": alg_bytes,
+            "algorithmic_GBps": alg_bytes / (batched_ms * 1e-3) / 1e9,
+            "frac": alg_bytes / (batched_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+            "pair_updates_per_s": pairs / (batched_ms * 1e-3), "pairs": pairs, "schedule": sched, "S": S, "P": P,
+            "subjects": args.subjects}
+
+
+def bench_batched(args):
+    from paper_2302_09247_amd import fastcod, synth
+    r = run_batched(args, fastcod, synth)
     out = {
         "metric": "batched streamline points/s (all subjects, one graph launch) vs the plain per-subject path",
-        "value": P / (batched_ms * 1e-3), "unit": "points/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": batched_ms, "higher_is_better": True, "scaling": "weak",
+        "value": r["points_per_s"], "unit": "points/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": r["batched_ms"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"{len(subs)} subjects, grids between 64^3 and 145x174x145, N 5k-45k, "
-                               f"M in {{70,180,360}}, S 100k-2M", "S": S, "P": P, "pairs": pairs,
-                   "schedule": sched},
-        "algorithmic_GBps": alg_bytes / (batched_ms * 1e-3) / 1e9,
-        "plain_value": P / (plain_ms * 1e-3), "plain_ms": plain_ms,
-        "batched_over_plain": plain_ms / batched_ms, "bit_identical": identical,
+        "config": {"workload": f"{r['subjects']} subjects, grids between 64^3 and 145x174x145, N 5k-45k, "
+                               f"M in {{70,180,360}}, S 100k-2M", "S": r["S"], "P": r["P"], "pairs": r["pairs"],
+                   "schedule": r["schedule"]},
+        "algorithmic_GBps": r["algorithmic_GBps"], "frac": r["frac"], "pair_updates_per_s": r["pair_updates_per_s"],
+        "plain_value": r["plain_points_per_s"], "plain_ms": r["plain_ms"],
+        "batched_over_plain": r["batched_over_plain"], "bit_identical": r["bit_identical"],
     }
+    print(json.dumps(out), flush=True)
+
+
+def bench_ceilings(args):
+    """The ceiling probes alone on the 0.7 mm subject's points and volumes (for rocprofv3)."""
+    import torch
+    from paper_2302_09247_amd import fastcod, synth
+    w = synth.make_07mm(S=args.streamlines, device="cuda")
+    vol = fastcod.Volume(w.roi, w.lab, w.N, w.M)
+    torch.cuda.synchronize()
+    c = run_ceilings(fastcod, w.points, vol)
+    vol.close()
+    out = {"metric": "ceiling probes: read-only point stream, stream + compact-volume lookups (GB/s of points), "
+                     "no-return int32 atomics/s", "value": c["stream"]["GBps"], "unit": "GB/s", "n_gpus": 1,
+           "steps": 5, "warmup": 1, "ms_per_step": c["stream"]["ms"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "0.7mm-like subject points (S=5M) and volumes; 2^26 atomics per pattern",
+                      "P": w.P}, "ceilings": c}
     print(json.dumps(out), flush=True)
 
 
@@ -381,7 +578,7 @@ def bench_sr(args):
     print(json.dumps(out), flush=True)
 
 
-def bench_served(args):
+def run_served(args, fastcod, synth, rates) -> dict:
     """Served form: a request server with resident volumes receives a Poisson stream of requests --
     37.5% 64^3-grid subjects (10k streamlines), 37.5% 1.25 mm-grid subjects (1M streamlines), 25%
     super-resolution jobs (1.25 mm streamlines scaled by fl32(1.25/0.7) onto the 0.7 mm volumes).
@@ -391,7 +588,6 @@ def bench_served(args):
     import threading
     import numpy as np
     import torch
-    from paper_2302_09247_amd import fastcod, synth
     t0 = time.time()
     ns = args.served_subjects
     vA, vB, vC = synth.volumes_tiny64(), synth.volumes_125mm(2), synth.volumes_07mm(3)
@@ -452,6 +648,8 @@ def bench_served(args):
         th.start()
         start = time.monotonic_ns() + 2_000_000
         for i in range(nreq):
+            outs[i].fill_(-1)          # a request that wrote nothing cannot match an earlier result
+        for i in range(nreq):
             due = start + int(arrive[i] * 1e9)
             while True:
                 now = time.monotonic_ns()
@@ -477,7 +675,7 @@ def bench_served(args):
         f"exact={burst['exact']} ok={burst['ok']}")
     sweep = []
     exact = burst["exact"] and burst["ok"]
-    for j, frac in enumerate(float(x) for x in args.rates.split(",")):
+    for j, frac in enumerate(rates):
         r = run(frac * sat, args.served_requests, 10 + j)
         exact &= r["exact"] and r["ok"]
         row = {"rate_frac": frac, "rate": frac * sat, "p50_ms": float(np.percentile(r["lat"], 50)),
@@ -488,6 +686,14 @@ def bench_served(args):
             f"{row['throughput']:.1f} req/s, exact={row['exact']}")
     st = srv.stats()
     srv.close()
+    return {"saturation": sat, "points_per_s_at_saturation": burst["points"] / burst["span_s"], "sweep": sweep,
+            "bit_identical": exact, "server": st, "subjects": ns}
+
+
+def bench_served(args):
+    from paper_2302_09247_amd import fastcod, synth
+    r = run_served(args, fastcod, synth, [float(x) for x in args.rates.split(",")])
+    sat = r["saturation"]
     out = {
         "metric": "served requests/s at saturation (Poisson request stream, resident volumes, C to pinned host); "
                   "p50/p99 latency per rate",
@@ -495,9 +701,9 @@ def bench_served(args):
         "ms_per_step": 1e3 / sat, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"37.5% 64^3 (S=10k), 37.5% 1.25 mm (S=1M), 25% SR 1.25->0.7 mm; "
-                               f"{ns} resident subjects per shape", "requests_per_rate": args.served_requests},
-        "points_per_s_at_saturation": burst["points"] / burst["span_s"],
-        "sweep": sweep, "bit_identical": exact, "server": st,
+                               f"{r['subjects']} resident subjects per shape", "requests_per_rate": args.served_requests},
+        "points_per_s_at_saturation": r["points_per_s_at_saturation"],
+        "sweep": r["sweep"], "bit_identical": r["bit_identical"], "server": r["server"],
     }
     print(json.dumps(out), flush=True)
 

@@ -29,8 +29,11 @@
  *     (thread-local).  No C++ exception crosses this interface.
  *   - Counting calls are asynchronous on `stream` (a hipStream_t; NULL = the null stream):
  *     results are valid once the stream is synchronised.  Calls on one stream are serialised by
- *     the stream; the library keeps a workspace per (device, stream) and grows it with hipMalloc
- *     on first use (that growth synchronises the device).
+ *     the stream; the library keeps a workspace per (device, stream) -- per calling thread for
+ *     hipStreamPerThread, which names a different stream in every thread -- and grows it with
+ *     hipMalloc on first use (that growth synchronises the device).  At most 8 workspaces are kept
+ *     per device: a call on a ninth stream first frees the least recently used idle one (after a
+ *     device synchronisation).  fastcod_release() frees them all.
  *   - C is int32; one call adds at most S to any entry, and S <= INT32_MAX is enforced.
  */
 #ifndef FASTCOD_H
@@ -140,11 +143,14 @@ int fastcod_volume_count(const fastcod_volume *vol, const float *points, const i
 int fastcod_volume_destroy(fastcod_volume *vol);
 
 /*
- * Batched form: many subjects (each its own streamlines, volumes, N, M, scale and C) counted by one
- * persistent kernel that takes (subject, point range) work items from a single counter, the whole
- * sequence (zero every C, partition, count, overflow fallback) captured once in a hipGraph and
- * replayed by every launch.  Each subject's C is identical to what fastcod_count_ex gives for it
- * (counts are exact integers and C is additive over streamline ranges).
+ * Batched form: many subjects (each its own streamlines, volumes, N, M, scale, mode, upsampling and
+ * C) counted by persistent kernels that take (subject, point range) work items from a counter, the
+ * whole sequence (zero every C, end labels, partition, count, overflow fallback, transposes) captured
+ * once in a hipGraph and replayed by every launch.  Subjects of one kind share one launch: all the
+ * pass-through subjects (the usual case) one, the endpoint-mode subjects (Alg. 2 as printed,
+ * Section 2) another, upsampled ones (Section 3) a third, Alg. 1's seed-to-end subjects a fourth.
+ * Each subject's C is identical to what fastcod_count_ex gives for it with the same scale, mode and
+ * upsample (counts are exact integers and C is additive over streamline ranges).
  */
 typedef struct fastcod_subject {
     const float *points;              /* [P][3] float32, device                                         */
@@ -158,6 +164,8 @@ typedef struct fastcod_subject {
     int32_t *C_out;                   /* [N][M] int32, device; overwritten by every launch.  Subjects of
                                          one plan may share a C_out only with equal N and M: it then
                                          receives the sum of their counts                            */
+    int32_t mode;                     /* FASTCOD_MODE_* of this subject (0 = pass-through)               */
+    int32_t upsample;                 /* u in 1..4 as fastcod_opts.upsample (0 = 1); u > 1 needs mode 0  */
 } fastcod_subject;
 
 /* Schedule of the batched kernel (chosen by the tuner or the defaults). */
@@ -197,9 +205,9 @@ int fastcod_count_batched(const fastcod_subject *subjects, int32_t n, void *stre
 
 /*
  * Served form: a server that keeps volume pairs resident on one device and counts requests as
- * they arrive, each request's C identical to fastcod_count_ex on the same inputs (C is a sum of
- * exact per-streamline terms, Section 2, so cutting a request into streamline ranges and
- * interleaving them with other requests changes nothing).
+ * they arrive, each request's C identical to fastcod_count_ex on the same inputs, scale, mode and
+ * upsampling (C is a sum of exact per-streamline terms, Section 2, so cutting a request into
+ * streamline ranges and interleaving them with other requests changes nothing).
  *
  * The server takes one device allocation of memory_budget bytes at creation and places in it the
  * compact volumes and every admitted request's device data: its offsets, its points unless they
@@ -226,6 +234,8 @@ typedef struct fastcod_server_config {
 
 #define FASTCOD_REQ_DEVICE_POINTS 1u  /* request.points is a device pointer (else host)             */
 #define FASTCOD_REQ_DEVICE_C 2u       /* request.C_out is a device pointer (else host)              */
+#define FASTCOD_REQ_AFTER_STREAM 4u   /* order every device access of the request after the work    */
+                                      /* enqueued on request.stream before the submission            */
 
 typedef struct fastcod_request {
     int32_t volume_id;         /* from fastcod_server_add_volume                                    */
@@ -236,6 +246,10 @@ typedef struct fastcod_request {
     float scale;               /* coordinate scale, finite and > 0 (1.0f = none)                    */
     int32_t *C_out;            /* [N][M] int32 of the volume, HOST unless FASTCOD_REQ_DEVICE_C;     */
                                /* overwritten with the result when the request finishes             */
+    int32_t mode;              /* FASTCOD_MODE_* (0 = pass-through)                                 */
+    int32_t upsample;          /* u in 1..4 as fastcod_opts.upsample (0 = 1); u > 1 needs mode 0    */
+    void *stream;              /* with FASTCOD_REQ_AFTER_STREAM: the hipStream_t (NULL = the null   */
+                               /* stream) whose work produced device-resident points or C_out       */
 } fastcod_request;
 
 typedef struct fastcod_request_info {
@@ -270,9 +284,14 @@ int fastcod_server_add_volume(fastcod_server *srv, const int32_t *roi_index_vol_
                               const int32_t *target_label_vol_host, const int32_t dims[3], int32_t N,
                               int32_t M, int32_t *volume_id);
 /* Queues a request.  Its points, offsets and C_out must stay valid and unchanged until it has
- * finished (fastcod_server_wait returned its status).  The offsets are checked here: ERANGE if
- * offsets[0] != 0 or they decrease.  Errors: EINVAL, ERANGE, ENOMEM (can never fit the budget),
- * EBUSY (server shutting down), or the status that failed the server. */
+ * finished (fastcod_server_wait returned its status).  Host arrays must hold their data at
+ * submission.  The server's device work runs on streams of its own: for device-resident points
+ * or C_out written by work still in flight on some stream, set FASTCOD_REQ_AFTER_STREAM and name
+ * that stream -- an event recorded on it here orders every device access of the request after
+ * that work (without the flag the caller must have completed that work before submitting).  The
+ * offsets are checked here: ERANGE if offsets[0] != 0 or they decrease.  Errors: EINVAL, ERANGE,
+ * ENOMEM (can never fit the budget), EBUSY (server shutting down), EHIP (the event could not be
+ * recorded on request.stream), or the status that failed the server. */
 int fastcod_server_submit(fastcod_server *srv, const fastcod_request *req, uint64_t *request_id);
 /* Waits up to timeout_us microseconds (< 0: no limit) for a request to finish.  Returns its
  * status (FASTCOD_OK: C_out holds the result) and fills *info (may be NULL); the request's record
@@ -318,7 +337,9 @@ int fastcod_validate(const int64_t *offsets, int64_t n_streamlines, const int32_
 const char *fastcod_strerror(int status);
 /* Detail of the last failing call on this thread ("" if none). */
 const char *fastcod_last_error(void);
-/* Frees every cached workspace (synchronises the devices that own them). */
+/* Frees every cached workspace that no call is using (synchronises the devices that own them
+ * first).  FASTCOD_EBUSY: a call on another thread was enqueueing with one of them at that moment;
+ * that workspace was kept (the others are freed) -- call again once that call has returned. */
 int fastcod_release(void);
 
 #ifdef __cplusplus

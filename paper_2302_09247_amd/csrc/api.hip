@@ -10,9 +10,11 @@
 #include <vector>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <utility>
 
 #include "fastcod.h"
+#include "fastcod_probe.h"
 #include "host.h"
 #include "internal.h"
 
@@ -22,6 +24,8 @@ namespace {
 
 struct Workspace {
     std::mutex mu;      // held for the whole enqueue of one call
+    int refs = 0;       // calls holding the workspace (guarded by g_ws_mu)
+    uint64_t last_use = 0;   // (guarded by g_ws_mu)
     DevBuf compact;     // fastcod_count's per-call compact volume
     DevBuf first;       // chunk -> first streamline
     DevBuf ovf;         // overflow counter + queue
@@ -30,18 +34,74 @@ struct Workspace {
     DevBuf ct;          // transposed accumulation copy of C (C beyond the histogram's tiles)
     DevBuf ends;        // per-streamline end labels of the endpoint modes
     DevBuf pairs;       // appended C updates: slice lengths, tile histogram, slices, sorted copy
+    void free_buffers() {
+        for (DevBuf *b : {&compact, &first, &ovf, &fallback, &flags, &ct, &ends, &pairs}) b->release();
+    }
 };
 
+// Workspaces are kept per (device, stream): calls on one stream are serialised by that stream, so
+// they can reuse one set of buffers.  hipStreamPerThread names a different stream in every thread,
+// so for that handle the calling thread is part of the key.  At most kMaxWorkspacesPerDevice are
+// kept per device; a new one then replaces the least recently used idle one, after a device
+// synchronisation (its stream may still be using it).
+struct WsKey {
+    int dev;
+    hipStream_t st;
+    std::thread::id tid;
+    bool operator<(const WsKey &o) const { return std::tie(dev, st, tid) < std::tie(o.dev, o.st, o.tid); }
+};
+constexpr int kMaxWorkspacesPerDevice = 8;
 std::mutex g_ws_mu;
-std::map<std::pair<int, hipStream_t>, Workspace *> g_ws;
+std::map<WsKey, Workspace *> g_ws;
+uint64_t g_ws_clock = 0;
 
-
-Workspace *workspace_for(int dev, hipStream_t st) {
-    std::lock_guard<std::mutex> g(g_ws_mu);
-    auto &w = g_ws[{dev, st}];
-    if (!w) w = new Workspace();
-    return w;
+// with g_ws_mu held and `dev` current: frees idle workspaces of dev until fewer than the limit remain
+void evict_workspaces(int dev) {
+    for (;;) {
+        int n = 0;
+        auto lru = g_ws.end();
+        for (auto it = g_ws.begin(); it != g_ws.end(); ++it) {
+            if (it->first.dev != dev) continue;
+            ++n;
+            if (it->second->refs == 0 && (lru == g_ws.end() || it->second->last_use < lru->second->last_use)) lru = it;
+        }
+        if (n < kMaxWorkspacesPerDevice || lru == g_ws.end()) return;
+        (void)hipDeviceSynchronize();
+        lru->second->free_buffers();
+        delete lru->second;
+        g_ws.erase(lru);
+    }
 }
+
+// A workspace held for the duration of one call (dev must be the current device).
+class WsRef {
+  public:
+    WsRef(int dev, hipStream_t st) {
+        std::lock_guard<std::mutex> g(g_ws_mu);
+        const WsKey k{dev, st, st == hipStreamPerThread ? std::this_thread::get_id() : std::thread::id()};
+        auto it = g_ws.find(k);
+        if (it != g_ws.end()) {
+            w_ = it->second;
+        } else {
+            evict_workspaces(dev);
+            w_ = new Workspace();
+            g_ws[k] = w_;
+        }
+        ++w_->refs;
+        w_->last_use = ++g_ws_clock;
+    }
+    ~WsRef() {
+        std::lock_guard<std::mutex> g(g_ws_mu);
+        --w_->refs;
+    }
+    WsRef(const WsRef &) = delete;
+    WsRef &operator=(const WsRef &) = delete;
+    Workspace &operator*() const { return *w_; }
+    Workspace *operator->() const { return w_; }
+
+  private:
+    Workspace *w_;
+};
 
 int check_stream_args(const float *points, const int64_t *offsets, int64_t S, int32_t *C, const fastcod_opts &o) {
     if (S < 0 || S > INT32_MAX) return fail(FASTCOD_EINVAL, "n_streamlines must be in [0, INT32_MAX]");
@@ -69,17 +129,17 @@ constexpr int kRangesPerWave = 4;
 constexpr int kRangesPerWaveShort = 2;
 constexpr int64_t kLongRangesFrom = int64_t(1) << 21;   // also the threshold for 4-window batches
 
-int fallback_scratch(Workspace &ws, int32_t N, int32_t M, fc::FallbackScratch &fs) {
+// Fallback scratch layout for a C of N rows and M labels: per workgroup an N-bit map, an M-bit map
+// and an M-entry label list, as many workgroups (<= 64) as fit `max_bytes`; false if not even one.
+bool fallback_layout(int32_t N, int32_t M, int64_t max_bytes, fc::FallbackScratch &fs) {
     fs.nwordsN = (N + 31) / 32;
     fs.nwordsM = (M + 31) / 32;
     fs.stride = ((int64_t)fs.nwordsN + fs.nwordsM + M + 63) & ~int64_t(63);
-    int64_t blocks = (int64_t(256) << 20) / (4 * fs.stride);   // <= 256 MiB of scratch
+    int64_t blocks = max_bytes / (4 * fs.stride);
     if (blocks > 64) blocks = 64;
-    if (blocks < 1) blocks = 1;
-    fs.blocks = (int32_t)blocks;
-    FC_HIP(ws.fallback.ensure((size_t)(4 * fs.stride * blocks), true));
-    fs.words = static_cast<uint32_t *>(ws.fallback.p);
-    return FASTCOD_OK;
+    fs.blocks = (int32_t)(blocks < 1 ? 1 : blocks);
+    fs.words = nullptr;
+    return blocks >= 1;
 }
 
 int run_validate(Workspace &ws, const int64_t *offsets, int64_t S, const int32_t *roi, const int32_t *lab,
@@ -101,12 +161,104 @@ int run_validate(Workspace &ws, const int64_t *offsets, int64_t S, const int32_t
     return FASTCOD_OK;
 }
 
-// The counting sequence on one stream, against a raster or a compact volume.
-int enqueue_count(Workspace &ws, int dev, const float *points, const int64_t *offsets, int64_t S,
-                  const fc::Grid &g, int32_t N, int32_t M, const fc::RasterVol *rv, const fc::CompactVol *cv,
-                  int32_t *C, const fastcod_opts &o, hipStream_t st) {
-    const int cus = cu_count(dev);
+// Decisions and scratch sizes of one counting call, fixed before anything is enqueued.
+struct CountPlan {
+    bool seed_end = false;     // Alg. 1's count: one update per streamline straight into C
+    bool append = false;       // pair updates appended to slices, added into C by the tile histogram
+    bool transposed = false;   // counted atomically into a transposed copy CT[M][N], then transposed
+    bool zero_c = false;       // C overwritten (zeroed first)
+    bool fused_zero = false;   // the partition launch does the zeroing
+    int nl = 0;                // end labels per streamline (endpoint modes)
+    int64_t NM = 0, ntiles = 0;
+    int batch = 2;
+    int64_t blocks = 0, nparts = 0, nwaves = 0, cap = 0;
+    fc::FallbackScratch fs{};
+    size_t off_hist = 0, off_pairs = 0, off_sorted = 0;
+    // bytes of each scratch region (0 = not needed)
+    size_t ovf_bytes = 0, ct_bytes = 0, ends_bytes = 0, fb_bytes = 0, first_bytes = 0, pairs_bytes = 0;
+};
+
+// Scratch regions of one call (device pointers, sized by CountPlan).  `fallback` must be all-zero.
+struct CountScratch {
+    void *ovf = nullptr;        // overflow count, range counter (256 B), then the overflow queue
+    int32_t *ct = nullptr;      // transposed copy of C
+    int32_t *ends = nullptr;    // end labels: last[S] (and first[S])
+    uint32_t *fallback = nullptr;
+    int32_t *first = nullptr;   // nparts + 1 range starts
+    char *pairs = nullptr;      // slice lengths | tile histogram | slices | sorted copy
+};
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// noalloc: a variant for a fixed scratch area -- no transposed copy of C (updates beyond the tile
+// histogram go to C as atomics) and at most max_pairs appended updates.
+int make_count_plan(int64_t S, int32_t N, int32_t M, const fc::CompactVol *cv, const fastcod_opts &o, int cus,
+                    bool noalloc, int64_t max_pairs, int64_t max_fallback_bytes, CountPlan &cp) {
+    cp = CountPlan{};
     if (o.mode == FASTCOD_MODE_SEED_END) {
+        cp.seed_end = true;
+        return FASTCOD_OK;
+    }
+    // The flat-stream path appends its pair updates to per-wavefront slices and adds their
+    // histogram into C tile by tile.  Past kMaxPairTiles tiles it accumulates atomically into a
+    // transposed workspace copy CT[M][N] instead: the rows of one streamline are neighbouring ROI
+    // indices, so its pair updates share memory lines there.
+    cp.NM = (int64_t)N * M;
+    cp.ntiles = (cp.NM + (1 << fc::kPairTileLog2) - 1) >> fc::kPairTileLog2;
+    cp.append = cv != nullptr && S > 0 && cp.ntiles <= fc::kMaxPairTiles;
+    cp.transposed = !noalloc && !cp.append && cv != nullptr && S > 0 && M > 1 && N >= 64;
+    cp.zero_c = !(o.flags & FASTCOD_ACCUMULATE) && !cp.transposed;
+    cp.fused_zero = cv != nullptr && S > 0;
+    if (S == 0) return FASTCOD_OK;
+    cp.ovf_bytes = 256 + 8 * (size_t)S;
+    if (cp.transposed) cp.ct_bytes = 4 * (size_t)N * (size_t)M;
+    if (o.mode == FASTCOD_MODE_END || o.mode == FASTCOD_MODE_BOTH_ENDS) {
+        cp.nl = o.mode == FASTCOD_MODE_BOTH_ENDS ? 2 : 1;
+        cp.ends_bytes = 4 * (size_t)S * cp.nl;
+    }
+    if (!fallback_layout(N, M, max_fallback_bytes, cp.fs))
+        return fail(FASTCOD_ENOMEM, "the overflow fallback's bit maps for this N and M exceed the scratch area");
+    cp.fb_bytes = 4 * (size_t)cp.fs.stride * (size_t)cp.fs.blocks;
+    if (!cv) {
+        int64_t blocks = (S + fc::kWavesPerBlock - 1) / fc::kWavesPerBlock;
+        cp.blocks = std::min<int64_t>(blocks, (int64_t)cus * kBlocksPerCU);
+        return FASTCOD_OK;
+    }
+    // 4-window batches keep more loads in flight per wavefront; they pay off once each
+    // wavefront's point ranges are long enough to amortise their deeper pipeline start
+    const bool long_ranges = S >= kLongRangesFrom;
+    cp.batch = o.batch != 0 ? o.batch : (long_ranges ? 4 : 2);
+    int per_cu = fc::count_stream_blocks_per_cu(o.scale != 1.0f, cv->packed != 0, cp.batch, cp.nl != 0, o.upsample,
+                                                4 * (size_t)cv->ncoarse_words);
+    if (o.blocks_per_cu > 0 && o.blocks_per_cu < per_cu) per_cu = o.blocks_per_cu;
+    cp.blocks = (int64_t)cus * per_cu;
+    cp.nparts = cp.blocks * fc::kWavesPerBlock * (long_ranges ? kRangesPerWave : kRangesPerWaveShort);
+    cp.first_bytes = 4 * (size_t)(cp.nparts + 1);
+    // pair slices: pair_capacity entries in all (default 8 per streamline, between 2^20 and
+    // 2^28), split evenly between the wavefronts; a full slice sends the rest of its
+    // wavefront's updates to C as atomics
+    cp.nwaves = cp.blocks * fc::kWavesPerBlock;
+    int64_t total = o.pair_capacity > 0 ? o.pair_capacity : std::min<int64_t>(std::max<int64_t>(8 * S, 1 << 20), 1 << 28);
+    total = std::min<int64_t>(std::min<int64_t>(total, INT32_MAX), max_pairs);
+    cp.cap = cp.append ? total / cp.nwaves : 0;
+    if (cp.append) {
+        cp.off_hist = align256(4 * (size_t)cp.nwaves);
+        cp.off_pairs = align256(cp.off_hist + 4 * (size_t)fc::pair_hist_words(cp.ntiles));
+        cp.off_sorted = align256(cp.off_pairs + 4 * (size_t)(cp.nwaves * cp.cap));
+        cp.pairs_bytes = cp.off_sorted + 4 * (size_t)(cp.nwaves * cp.cap);
+    } else {
+        cp.pairs_bytes = 4 * (size_t)cp.nwaves;   // slice lengths only (every update is an atomic)
+    }
+    return FASTCOD_OK;
+}
+
+// The counting sequence on one stream, against a raster or a compact volume, with the scratch
+// regions of `sc` (sized by `cp`).
+int enqueue_count(const CountPlan &cp, const CountScratch &sc, int dev, const float *points, const int64_t *offsets,
+                  int64_t S, const fc::Grid &g, int32_t N, int32_t M, const fc::RasterVol *rv,
+                  const fc::CompactVol *cv, int32_t *C, const fastcod_opts &o, hipStream_t st) {
+    const int cus = cu_count(dev);
+    if (cp.seed_end) {
         // Alg. 1's count: one update per streamline, straight into C
         if (!(o.flags & FASTCOD_ACCUMULATE)) FC_HIP(fc::launch_fill_i32(C, (int64_t)N * M, 0, cus, st));
         fc::CountArgs a{};
@@ -123,24 +275,12 @@ int enqueue_count(Workspace &ws, int dev, const float *points, const int64_t *of
         if (o.event_end) FC_HIP(hipEventRecord((hipEvent_t)o.event_end, st));
         return FASTCOD_OK;
     }
-    // The flat-stream path appends its pair updates to per-wavefront slices and adds their
-    // histogram into C tile by tile.  Past kMaxPairTiles tiles it accumulates atomically into a
-    // transposed workspace copy CT[M][N] instead: the rows of one streamline are neighbouring ROI
-    // indices, so its pair updates share memory lines there.
-    const int64_t NM = (int64_t)N * M;
-    const int64_t ntiles = (NM + (1 << fc::kPairTileLog2) - 1) >> fc::kPairTileLog2;
-    const bool append = cv != nullptr && S > 0 && ntiles <= fc::kMaxPairTiles;
-    const bool transposed = !append && cv != nullptr && S > 0 && M > 1 && N >= 64;
-    const bool zero_c = !(o.flags & FASTCOD_ACCUMULATE) && !transposed;
-    // the compact path's partition launch zeroes C and the per-call counters itself
-    const bool fused_zero = cv != nullptr && S > 0;
-    if (zero_c && !fused_zero) FC_HIP(fc::launch_fill_i32(C, (int64_t)N * M, 0, cus, st));
+    if (cp.zero_c && !cp.fused_zero) FC_HIP(fc::launch_fill_i32(C, cp.NM, 0, cus, st));
     if (S == 0) {
         if (o.event_begin) FC_HIP(hipEventRecord((hipEvent_t)o.event_begin, st));
         if (o.event_end) FC_HIP(hipEventRecord((hipEvent_t)o.event_end, st));
         return FASTCOD_OK;
     }
-    FC_HIP(ws.ovf.ensure(256 + 8 * (size_t)S, false));
     fc::CountArgs a;
     a.pts = points;
     a.offsets = offsets;
@@ -150,94 +290,98 @@ int enqueue_count(Workspace &ws, int dev, const float *points, const int64_t *of
     a.C = C;
     a.si = (uint32_t)M;
     a.sm = 1u;
-    if (transposed) {
-        FC_HIP(ws.ct.ensure(4 * (size_t)N * (size_t)M, false));
-        a.C = static_cast<int32_t *>(ws.ct.p);
+    if (cp.transposed) {
+        a.C = sc.ct;
         a.si = 1u;
         a.sm = (uint32_t)N;
-        FC_HIP(fc::launch_fill_i32(a.C, (int64_t)N * M, 0, cus, st));
+        FC_HIP(fc::launch_fill_i32(a.C, cp.NM, 0, cus, st));
     }
     a.up = o.upsample;
     a.ends = fc::EndLabels{0, nullptr, nullptr};
-    if (o.mode == FASTCOD_MODE_END || o.mode == FASTCOD_MODE_BOTH_ENDS) {
-        const int nl = o.mode == FASTCOD_MODE_BOTH_ENDS ? 2 : 1;
-        FC_HIP(ws.ends.ensure(4 * (size_t)S * nl, false));
-        int32_t *last = static_cast<int32_t *>(ws.ends.p);
-        int32_t *first = nl == 2 ? last + S : nullptr;
+    if (cp.nl > 0) {
+        int32_t *last = sc.ends;
+        int32_t *first = cp.nl == 2 ? last + S : nullptr;
         a.ends = fc::EndLabels{o.mode, last, first};
         FC_HIP(fc::launch_end_labels(a, rv, cv, o.mode, last, first, cus, st));
     }
-    a.ovf.count = static_cast<unsigned long long *>(ws.ovf.p);
-    a.ovf.list = reinterpret_cast<int64_t *>(static_cast<char *>(ws.ovf.p) + 256);
+    a.ovf.count = static_cast<unsigned long long *>(sc.ovf);
+    a.ovf.list = reinterpret_cast<int64_t *>(static_cast<char *>(sc.ovf) + 256);
     a.ovf.cap = S;
-    a.ovf.work = static_cast<unsigned long long *>(ws.ovf.p) + 1;
-    fc::FallbackScratch fs;
-    int rc = fallback_scratch(ws, N, M, fs);
-    if (rc) return rc;
-    if (!fused_zero) FC_HIP(fc::launch_fill_u64(a.ovf.count, 2, cus, st));   // overflow count and range counter
-    const int64_t resident = (int64_t)cus * kBlocksPerCU;
+    a.ovf.work = static_cast<unsigned long long *>(sc.ovf) + 1;
+    fc::FallbackScratch fs = cp.fs;
+    fs.words = sc.fallback;
+    if (!cp.fused_zero) FC_HIP(fc::launch_fill_u64(a.ovf.count, 2, cus, st));   // overflow count and range counter
     if (cv) {
-        // 4-window batches keep more loads in flight per wavefront; they pay off once each
-        // wavefront's point ranges are long enough to amortise their deeper pipeline start
-        const bool long_ranges = S >= kLongRangesFrom;
-        const int batch = o.batch != 0 ? o.batch : (long_ranges ? 4 : 2);
-        int per_cu = fc::count_stream_blocks_per_cu(o.scale != 1.0f, cv->packed != 0, batch, a.ends.mode != 0,
-                                                    a.up, 4 * (size_t)cv->ncoarse_words);
-        if (o.blocks_per_cu > 0 && o.blocks_per_cu < per_cu) per_cu = o.blocks_per_cu;
-        const int64_t blocks = (int64_t)cus * per_cu;
-        const int64_t nparts = blocks * fc::kWavesPerBlock * (long_ranges ? kRangesPerWave : kRangesPerWaveShort);
-        FC_HIP(ws.first.ensure(4 * (size_t)(nparts + 1), false));
-        int32_t *first = static_cast<int32_t *>(ws.first.p);
-        // pair slices: pair_capacity entries in all (default 8 per streamline, between 2^20 and
-        // 2^28), split evenly between the wavefronts; a full slice sends the rest of its
-        // wavefront's updates to C as atomics
-        const int64_t nwaves = blocks * fc::kWavesPerBlock;
-        int64_t total = o.pair_capacity > 0 ? o.pair_capacity : std::min<int64_t>(std::max<int64_t>(8 * S, 1 << 20), 1 << 28);
-        total = std::min<int64_t>(total, INT32_MAX);
-        const int64_t cap = append ? total / nwaves : 0;
-        auto align = [](size_t v) { return (v + 255) & ~size_t(255); };
-        const size_t off_hist = align(4 * (size_t)nwaves);
-        const size_t off_pairs = align(off_hist + 4 * (size_t)fc::pair_hist_words(ntiles));
-        const size_t off_sorted = align(off_pairs + 4 * (size_t)(nwaves * cap));
-        FC_HIP(ws.pairs.ensure(off_sorted + 4 * (size_t)(nwaves * cap), false));
-        char *pb = static_cast<char *>(ws.pairs.p);
+        char *pb = sc.pairs;
         fc::PairOut po;
         po.counts = reinterpret_cast<uint32_t *>(pb);
-        po.pairs = reinterpret_cast<uint32_t *>(pb + off_pairs);
-        po.cap = (uint32_t)cap;
+        po.pairs = cp.append ? reinterpret_cast<uint32_t *>(pb + cp.off_pairs) : nullptr;
+        po.cap = (uint32_t)cp.cap;
         fc::ZeroRanges z;
-        if (zero_c) {
+        if (cp.zero_c) {
             z.w32[0] = C;
-            z.n32[0] = NM;
+            z.n32[0] = cp.NM;
         }
-        if (append) {
-            z.w32[1] = reinterpret_cast<int32_t *>(pb + off_hist);
-            z.n32[1] = fc::pair_hist_cursor_words(ntiles);
+        if (cp.append) {
+            z.w32[1] = reinterpret_cast<int32_t *>(pb + cp.off_hist);
+            z.n32[1] = fc::pair_hist_cursor_words(cp.ntiles);
         }
         z.w64 = a.ovf.count;   // overflow count and range counter
         z.n64 = 2;
         // tapering ranges (largest first) end the launch evenly when ranges are long; short ones
         // would only add per-range work
-        FC_HIP(fc::launch_partition(offsets, S, nparts, first, z, long_ranges, cus, st));
+        FC_HIP(fc::launch_partition(offsets, S, cp.nparts, sc.first, z, S >= kLongRangesFrom, cus, st));
         if (o.event_begin) FC_HIP(hipEventRecord((hipEvent_t)o.event_begin, st));
-        FC_HIP(fc::launch_count_stream(a, *cv, first, nparts, (int)blocks, batch, po, st));
+        FC_HIP(fc::launch_count_stream(a, *cv, sc.first, cp.nparts, (int)cp.blocks, cp.batch, po, st));
         if (o.event_end) FC_HIP(hipEventRecord((hipEvent_t)o.event_end, st));
         FC_HIP(fc::launch_fallback_compact(a, *cv, fs, st));
-        if (append)
-            FC_HIP(fc::launch_pair_histogram(po, (int32_t)nwaves, (int32_t)ntiles, C, NM,
-                                             reinterpret_cast<uint32_t *>(pb + off_hist),
-                                             reinterpret_cast<uint32_t *>(pb + off_sorted), cus, st));
-        if (transposed) FC_HIP(fc::launch_transpose(a.C, C, N, M, (o.flags & FASTCOD_ACCUMULATE) != 0, st));
+        if (cp.append)
+            FC_HIP(fc::launch_pair_histogram(po, (int32_t)cp.nwaves, (int32_t)cp.ntiles, C, cp.NM,
+                                             reinterpret_cast<uint32_t *>(pb + cp.off_hist),
+                                             reinterpret_cast<uint32_t *>(pb + cp.off_sorted), cus, st));
+        if (cp.transposed) FC_HIP(fc::launch_transpose(a.C, C, N, M, (o.flags & FASTCOD_ACCUMULATE) != 0, st));
     } else {
-        int64_t blocks = (S + fc::kWavesPerBlock - 1) / fc::kWavesPerBlock;
-        if (blocks > resident) blocks = resident;
         if (o.event_begin) FC_HIP(hipEventRecord((hipEvent_t)o.event_begin, st));
-        FC_HIP(fc::launch_count_wave(a, *rv, (int)blocks, st));
+        FC_HIP(fc::launch_count_wave(a, *rv, (int)cp.blocks, st));
         if (o.event_end) FC_HIP(hipEventRecord((hipEvent_t)o.event_end, st));
         FC_HIP(fc::launch_fallback_raster(a, *rv, fs, st));
     }
-    (void)N;
     return FASTCOD_OK;
+}
+
+// The counting sequence with the scratch regions taken from (and grown in) the stream's workspace.
+int enqueue_count_ws(Workspace &ws, int dev, const float *points, const int64_t *offsets, int64_t S,
+                     const fc::Grid &g, int32_t N, int32_t M, const fc::RasterVol *rv, const fc::CompactVol *cv,
+                     int32_t *C, const fastcod_opts &o, hipStream_t st) {
+    CountPlan cp;
+    int rc = make_count_plan(S, N, M, cv, o, cu_count(dev), false, INT32_MAX, int64_t(256) << 20, cp);
+    if (rc) return rc;
+    CountScratch sc;
+    if (cp.ovf_bytes) {
+        FC_HIP(ws.ovf.ensure(cp.ovf_bytes, false));
+        sc.ovf = ws.ovf.p;
+    }
+    if (cp.ct_bytes) {
+        FC_HIP(ws.ct.ensure(cp.ct_bytes, false));
+        sc.ct = static_cast<int32_t *>(ws.ct.p);
+    }
+    if (cp.ends_bytes) {
+        FC_HIP(ws.ends.ensure(cp.ends_bytes, false));
+        sc.ends = static_cast<int32_t *>(ws.ends.p);
+    }
+    if (cp.fb_bytes) {
+        FC_HIP(ws.fallback.ensure(cp.fb_bytes, true));   // zeroed once; the fallback keeps it zero
+        sc.fallback = static_cast<uint32_t *>(ws.fallback.p);
+    }
+    if (cp.first_bytes) {
+        FC_HIP(ws.first.ensure(cp.first_bytes, false));
+        sc.first = static_cast<int32_t *>(ws.first.p);
+    }
+    if (cp.pairs_bytes) {
+        FC_HIP(ws.pairs.ensure(cp.pairs_bytes, false));
+        sc.pairs = static_cast<char *>(ws.pairs.p);
+    }
+    return enqueue_count(cp, sc, dev, points, offsets, S, g, N, M, rv, cv, C, o, st);
 }
 
 // ---- batched plans ----
@@ -306,25 +450,37 @@ struct fastcod_plan {
     fc::Overflow ovf{};
     PlanSched sched;
     int64_t nitems = 0;
-    int blocks = 0;
+    int blocks = 0;                             // workgroups of the pass-through launch (the schedule's)
+    // Table entries are grouped by kind of subject (fc::BatchedKind): entries [kind_lo[k], kind_lo[k+1])
+    // and their work items [item_lo[k], item_lo[k+1]) are counted by launch k
+    int32_t kind_lo[fc::kBatchedKinds + 1] = {};
+    int64_t item_lo[fc::kBatchedKinds + 1] = {};
+    int kind_blocks[fc::kBatchedKinds] = {};
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
 
 namespace {
 
-// Work-item split for a schedule: items in proportion to every subject's points.
+// Work-item split for a schedule: items in proportion to every subject's points (subjects of the
+// seed-to-end kind take none: their kernel walks their streamlines directly).
 int plan_items(fastcod_plan &pl, const PlanSched &ps, int cus, hipStream_t st) {
     int per_cu = fc::count_batched_blocks_per_cu(ps.batch, kBatchedCoarseWords);
     if (ps.blocks_per_cu > 0 && ps.blocks_per_cu < per_cu) per_cu = ps.blocks_per_cu;
     pl.blocks = cus * per_cu;
+    for (int k = 0; k < fc::kBatchedKinds; ++k) {
+        const int occ = fc::count_batched_blocks_per_cu(ps.batch, kBatchedCoarseWords, (fc::BatchedKind)k);
+        pl.kind_blocks[k] = cus * std::max(1, std::min(per_cu, occ));
+    }
+    pl.kind_blocks[0] = pl.blocks;
     const int64_t total = (int64_t)pl.blocks * fc::kWavesPerBlock * ps.items_per_wave;
     double ptot = 0;
-    for (int64_t p : pl.points) ptot += (double)p;
+    for (int32_t k = 0; k < pl.n; ++k)
+        if (k < pl.kind_lo[(int)fc::BatchedKind::kSeedEnd]) ptot += (double)pl.points[k];
     std::vector<int64_t> base(pl.n + 1, 0);
     for (int32_t k = 0; k < pl.n; ++k) {
         int64_t ni = 0;
-        if (pl.subs[k].S > 0) {
+        if (pl.subs[k].S > 0 && k < pl.kind_lo[(int)fc::BatchedKind::kSeedEnd]) {
             ni = ptot > 0 ? (int64_t)((double)total * (double)pl.points[k] / ptot + 0.5) : 1;
             if (ni < 1) ni = 1;
             if (ni > pl.subs[k].S) ni = pl.subs[k].S;
@@ -332,6 +488,7 @@ int plan_items(fastcod_plan &pl, const PlanSched &ps, int cus, hipStream_t st) {
         base[k + 1] = base[k] + ni;
     }
     pl.nitems = base[pl.n];
+    for (int k = 0; k <= fc::kBatchedKinds; ++k) pl.item_lo[k] = base[pl.kind_lo[k]];
     FC_HIP(pl.d_item_base.ensure(8 * (size_t)(pl.n + 1), false));
     FC_HIP(pl.d_items.ensure(8 * (size_t)(pl.nitems + 1), false));
     FC_HIP(hipMemcpyAsync(pl.d_item_base.p, base.data(), 8 * (size_t)(pl.n + 1), hipMemcpyHostToDevice, st));
@@ -343,14 +500,24 @@ int plan_items(fastcod_plan &pl, const PlanSched &ps, int cus, hipStream_t st) {
 int plan_enqueue(fastcod_plan &pl, int cus, hipStream_t st) {
     const auto *subs = static_cast<const fc::StreamSubject *>(pl.d_subs.p);
     FC_HIP(fc::launch_zero_subjects(subs, static_cast<const int64_t *>(pl.d_sizes.p), pl.n, cus, st));
-    FC_HIP(fc::launch_fill_u64(pl.ovf.count, 2, cus, st));
+    FC_HIP(fc::launch_fill_u64(pl.ovf.count, 1 + fc::kBatchedKinds, cus, st));   // overflow count, work counters
+    const int32_t *kl = pl.kind_lo;
+    const int ends = (int)fc::BatchedKind::kEnds, seed = (int)fc::BatchedKind::kSeedEnd;
+    FC_HIP(fc::launch_end_labels_batched(subs, kl[ends], kl[ends + 1] - kl[ends], cus, st));
     if (pl.nitems > 0) {
         FC_HIP(fc::launch_partition_batched(subs, static_cast<const int64_t *>(pl.d_item_base.p), pl.n, pl.nitems,
                                             static_cast<int2 *>(pl.d_items.p), cus, st));
-        FC_HIP(fc::launch_count_batched(subs, static_cast<const int2 *>(pl.d_items.p), pl.nitems, pl.ovf,
-                                        kBatchedCoarseWords, pl.blocks, pl.sched.batch, st));
+        const int2 *items = static_cast<const int2 *>(pl.d_items.p);
+        for (int k = 0; k < seed; ++k) {
+            fc::Overflow o = pl.ovf;
+            o.work = pl.ovf.count + 1 + k;
+            FC_HIP(fc::launch_count_batched(subs, items + pl.item_lo[k], pl.item_lo[k + 1] - pl.item_lo[k], o,
+                                            kBatchedCoarseWords, pl.kind_blocks[k], pl.sched.batch,
+                                            (fc::BatchedKind)k, st));
+        }
         FC_HIP(fc::launch_fallback_batched(subs, pl.n, pl.ovf, pl.fs, st));
     }
+    FC_HIP(fc::launch_count_seed_end_batched(subs, kl[seed], kl[seed + 1] - kl[seed], cus, st));
     FC_HIP(fc::launch_transpose_many(static_cast<const fc::TransposeJob *>(pl.d_transposed.p),
                                      (int32_t)pl.transposed.size(), pl.transpose_tiles, cus, st));
     return FASTCOD_OK;
@@ -390,14 +557,21 @@ void plan_free(fastcod_plan *pl) {
     delete pl;
 }
 
+// Options of subject u as counting options (upsample 0 means 1).
+fastcod_opts subject_opts(const fastcod_subject &u) {
+    fastcod_opts o = fastcod_default_opts();
+    o.scale = u.scale;
+    o.mode = u.mode;
+    o.upsample = u.upsample == 0 ? 1 : u.upsample;
+    return o;
+}
+
 int plan_check(const fastcod_subject *subjects, int32_t n) {
     for (int32_t k = 0; k < n; ++k) {
         const fastcod_subject &u = subjects[k];
         int rc = check_volume_args(u.roi_index_vol, u.target_label_vol, u.dims, u.N, u.M);
         if (rc) return fail(rc, "subject " + std::to_string(k) + ": " + last_error());
-        fastcod_opts o = fastcod_default_opts();
-        o.scale = u.scale;
-        rc = check_stream_args(u.points, u.offsets, u.n_streamlines, u.C_out, o);
+        rc = check_stream_args(u.points, u.offsets, u.n_streamlines, u.C_out, subject_opts(u));
         if (rc) return fail(rc, "subject " + std::to_string(k) + ": " + last_error());
         CompactLayout L;
         if (!compact_layout(u.dims, u.N, u.M, L, kBatchedCoarseWords))
@@ -414,6 +588,20 @@ int plan_build(const fastcod_subject *subjects, int32_t n, uint32_t flags, const
     pl->device = dev;
     pl->n = n;
     const int cus = cu_count(dev);
+    // table order: subjects grouped by kind (stable), so that each kind's launch takes a contiguous
+    // range of entries and work items
+    std::vector<int32_t> order(n);
+    for (int32_t k = 0; k < n; ++k) order[k] = k;
+    auto kind_of = [&](int32_t k) {
+        const fastcod_opts o = subject_opts(subjects[k]);
+        return (int)fc::batched_kind(o.mode, o.upsample);
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return kind_of(a) < kind_of(b); });
+    for (int k = 0; k <= fc::kBatchedKinds; ++k) {
+        int32_t c = 0;
+        for (int32_t t = 0; t < n; ++t) c += kind_of(order[t]) < k ? 1 : 0;
+        pl->kind_lo[k] = c;
+    }
     // validate, and build one compact volume per distinct volume pair
     struct Key {
         const int32_t *roi, *lab;
@@ -424,12 +612,13 @@ int plan_build(const fastcod_subject *subjects, int32_t n, uint32_t flags, const
     };
     std::map<Key, fc::CompactVol> built;
     int64_t total_s = 0, max_nw_n = 1, max_nw_m = 1, max_m = 1;
-    for (int32_t k = 0; k < n; ++k) {
+    size_t ends_words = 0;
+    for (int32_t t = 0; t < n; ++t) {
+        const int32_t k = order[t];
         const fastcod_subject &u = subjects[k];
         rc = check_volume_args(u.roi_index_vol, u.target_label_vol, u.dims, u.N, u.M);
         if (rc) return fail(rc, "subject " + std::to_string(k) + ": " + last_error());
-        fastcod_opts o = fastcod_default_opts();
-        o.scale = u.scale;
+        const fastcod_opts o = subject_opts(u);
         rc = check_stream_args(u.points, u.offsets, u.n_streamlines, u.C_out, o);
         if (rc) return fail(rc, "subject " + std::to_string(k) + ": " + last_error());
         CompactLayout L;
@@ -461,13 +650,34 @@ int plan_build(const fastcod_subject *subjects, int32_t n, uint32_t flags, const
         ss.si = (uint32_t)u.M;
         ss.sm = 1u;
         ss.ends = fc::EndLabels{0, nullptr, nullptr};
-        ss.up = 1;
+        if (o.mode == FASTCOD_MODE_END || o.mode == FASTCOD_MODE_BOTH_ENDS) {
+            ss.ends.mode = o.mode;   // label arrays placed below
+            ends_words += (size_t)u.n_streamlines * (o.mode == FASTCOD_MODE_BOTH_ENDS ? 2 : 1);
+        }
+        ss.up = o.upsample;
         pl->subs.push_back(ss);
         pl->sizes.push_back((int64_t)u.N * u.M);
         total_s += u.n_streamlines;
         max_nw_n = std::max<int64_t>(max_nw_n, (u.N + 31) / 32);
         max_nw_m = std::max<int64_t>(max_nw_m, (u.M + 31) / 32);
         max_m = std::max<int64_t>(max_m, u.M);
+    }
+    // end labels of the endpoint-mode subjects: one plan-owned allocation, last[S] (and first[S]) each
+    if (ends_words > 0) {
+        void *buf = nullptr;
+        hipError_t e = hipMalloc(&buf, 4 * ends_words);
+        if (e != hipSuccess) return fail(FASTCOD_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        pl->volumes.push_back(buf);
+        int32_t *p = static_cast<int32_t *>(buf);
+        for (auto &ss : pl->subs) {
+            if (ss.ends.mode == 0) continue;
+            ss.ends.last = p;
+            p += ss.S;
+            if (ss.ends.mode == FASTCOD_MODE_BOTH_ENDS) {
+                ss.ends.first = p;
+                p += ss.S;
+            }
+        }
     }
     // point counts (the item split follows them)
     pl->points.assign(n, 0);
@@ -484,10 +694,10 @@ int plan_build(const fastcod_subject *subjects, int32_t n, uint32_t flags, const
         for (const auto &ss : pl->subs) writers[ss.C]++;
         std::vector<int32_t> pick;
         size_t words = 0;
-        for (int32_t k = 0; k < n; ++k) {
-            const fastcod_subject &u = subjects[k];
-            if (pl->subs[k].S > 0 && u.M > 1 && u.N >= 64 && writers[u.C_out] == 1) {
-                pick.push_back(k);
+        for (int32_t t = 0; t < n; ++t) {
+            const fastcod_subject &u = subjects[order[t]];
+            if (pl->subs[t].S > 0 && u.M > 1 && u.N >= 64 && writers[u.C_out] == 1) {
+                pick.push_back(t);
                 words += (size_t)u.N * (size_t)u.M;
             }
         }
@@ -498,7 +708,7 @@ int plan_build(const fastcod_subject *subjects, int32_t n, uint32_t flags, const
             pl->volumes.push_back(buf);
             int32_t *ct = static_cast<int32_t *>(buf);
             for (int32_t k : pick) {
-                const fastcod_subject &u = subjects[k];
+                const fastcod_subject &u = subjects[order[k]];
                 pl->transposed.push_back({ct, u.C_out, u.N, u.M, pl->transpose_tiles});
                 pl->transpose_tiles += (int64_t)((u.N + fc::kTransposeTile - 1) / fc::kTransposeTile) *
                                        (int64_t)((u.M + fc::kTransposeTile - 1) / fc::kTransposeTile);
@@ -539,9 +749,11 @@ int plan_build(const fastcod_subject *subjects, int32_t n, uint32_t flags, const
         nm += (double)pl->sizes[k];
         spts += (double)pl->subs[k].S;
     }
+    int kinds = 0;
+    for (int k = 0; k < fc::kBatchedKinds; ++k) kinds |= (pl->kind_lo[k + 1] > pl->kind_lo[k] ? 1 : 0) << k;
     const std::string key = arch_name(dev) + ":cu" + std::to_string(cus) + ":n" + std::to_string(log2_bucket(n)) +
                             ":P" + std::to_string(log2_bucket(ptot)) + ":NM" + std::to_string(log2_bucket(nm / n)) +
-                            ":T" + std::to_string(log2_bucket(spts > 0 ? ptot / spts : 0));
+                            ":T" + std::to_string(log2_bucket(spts > 0 ? ptot / spts : 0)) + ":K" + std::to_string(kinds);
     PlanSched ps;
     if (read_tune_cache(tune_cache, key, ps)) {
         pl->sched = ps;
@@ -645,7 +857,8 @@ int fastcod_count_ex(const float *points, const int64_t *offsets, int64_t S, con
     rc = current_device(&dev);
     if (rc) return rc;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    Workspace &ws = *workspace_for(dev, st);
+    WsRef ref(dev, st);
+    Workspace &ws = *ref;
     std::lock_guard<std::mutex> lock(ws.mu);
     if (o.flags & FASTCOD_VALIDATE) {
         rc = run_validate(ws, offsets, S, roi, lab, dims, N, M, st, dev);
@@ -658,12 +871,12 @@ int fastcod_count_ex(const float *points, const int64_t *offsets, int64_t S, con
         return fail(FASTCOD_EINVAL, "grid too thin for the compact volume; use FASTCOD_VARIANT_WAVE");
     if (o.variant == FASTCOD_VARIANT_WAVE || !compact_ok) {
         fc::RasterVol rv{roi, lab, dims[0], dims[0] * dims[1], N, M};
-        return enqueue_count(ws, dev, points, offsets, S, g, N, M, &rv, nullptr, C, o, st);
+        return enqueue_count_ws(ws, dev, points, offsets, S, g, N, M, &rv, nullptr, C, o, st);
     }
     FC_HIP(ws.compact.ensure(L.bytes, false));
     fc::CompactVol cv = compact_view(ws.compact.p, L, N, M);
     FC_HIP(enqueue_compact_build(roi, lab, dims, N, M, L, ws.compact.p, cu_count(dev), st));
-    return enqueue_count(ws, dev, points, offsets, S, g, N, M, nullptr, &cv, C, o, st);
+    return enqueue_count_ws(ws, dev, points, offsets, S, g, N, M, nullptr, &cv, C, o, st);
 }
 
 int fastcod_count(const float *points, const int64_t *offsets, int64_t S, const int32_t *roi, const int32_t *lab,
@@ -696,8 +909,8 @@ int fastcod_volume_create(const int32_t *roi, const int32_t *lab, const int32_t 
     v->buf = buf;
     v->ready = nullptr;
     {
-        Workspace &ws = *workspace_for(dev, st);
-        std::lock_guard<std::mutex> lock(ws.mu);
+        WsRef ref(dev, st);
+        std::lock_guard<std::mutex> lock(ref->mu);
         e = enqueue_compact_build(roi, lab, dims, N, M, L, buf, cu_count(dev), st);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&v->ready, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventRecord(v->ready, st);
@@ -728,12 +941,57 @@ int fastcod_volume_count(const fastcod_volume *vol, const float *points, const i
     if (rc) return rc;
     if (dev != vol->device) return fail(FASTCOD_EINVAL, "volume lives on another device");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    Workspace &ws = *workspace_for(dev, st);
+    WsRef ref(dev, st);
+    Workspace &ws = *ref;
     std::lock_guard<std::mutex> lock(ws.mu);
     FC_HIP(hipStreamWaitEvent(st, vol->ready, 0));
     const fc::Grid g = make_grid(vol->dims);
     fc::CompactVol cv = compact_view(vol->buf, vol->L, vol->N, vol->M);
-    return enqueue_count(ws, dev, points, offsets, S, g, vol->N, vol->M, nullptr, &cv, C, o, st);
+    return enqueue_count_ws(ws, dev, points, offsets, S, g, vol->N, vol->M, nullptr, &cv, C, o, st);
+}
+
+int fastcod_probe_stream(const float *points, int64_t P, uint32_t *sink, void *stream) {
+    last_error().clear();
+    if (P < 0 || P >= (int64_t(1) << 37)) return fail(FASTCOD_EINVAL, "n_points must be in [0, 2^37)");
+    if ((P > 0 && !points) || !sink) return fail(FASTCOD_EINVAL, "NULL pointer");
+    int dev;
+    const int rc = current_device(&dev);
+    if (rc) return rc;
+    FC_HIP(fc::launch_probe_stream(points, P, cu_count(dev), sink, static_cast<hipStream_t>(stream)));
+    return FASTCOD_OK;
+}
+
+int fastcod_probe_atomics(int32_t *target, int64_t n_words, const uint32_t *idx, int64_t n_idx, void *stream) {
+    last_error().clear();
+    if (n_words < 0 || n_idx < 0) return fail(FASTCOD_EINVAL, "sizes must be >= 0");
+    if ((n_idx > 0 && !idx) || (n_words > 0 && !target)) return fail(FASTCOD_EINVAL, "NULL pointer");
+    int dev;
+    const int rc = current_device(&dev);
+    if (rc) return rc;
+    FC_HIP(fc::launch_probe_atomics(target, n_words, idx, n_idx, cu_count(dev), static_cast<hipStream_t>(stream)));
+    return FASTCOD_OK;
+}
+
+int fastcod_probe_lookup(const fastcod_volume *vol, const float *points, int64_t P, float scale, uint32_t *sink,
+                         void *stream) {
+    last_error().clear();
+    if (!vol || !sink || (P > 0 && !points)) return fail(FASTCOD_EINVAL, "NULL pointer");
+    if (P < 0 || P >= (int64_t(1) << 37)) return fail(FASTCOD_EINVAL, "n_points must be in [0, 2^37)");
+    if (!(scale == scale) || scale <= 0.0f || isinf(scale)) return fail(FASTCOD_EINVAL, "scale must be finite and > 0");
+    int dev;
+    const int rc = current_device(&dev);
+    if (rc) return rc;
+    if (dev != vol->device) return fail(FASTCOD_EINVAL, "volume lives on another device");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    FC_HIP(hipStreamWaitEvent(st, vol->ready, 0));
+    fc::StreamSubject sub{};
+    sub.pts = points;
+    sub.g = make_grid(vol->dims);
+    sub.scale = scale;
+    sub.cv = compact_view(vol->buf, vol->L, vol->N, vol->M);
+    sub.up = 1;
+    FC_HIP(fc::launch_probe_lookup(sub, P, cu_count(dev), sink, st));
+    return FASTCOD_OK;
 }
 
 int fastcod_volume_destroy(fastcod_volume *vol) {
@@ -761,7 +1019,8 @@ int fastcod_validate(const int64_t *offsets, int64_t S, const int32_t *roi, cons
     rc = current_device(&dev);
     if (rc) return rc;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    Workspace &ws = *workspace_for(dev, st);
+    WsRef ref(dev, st);
+    Workspace &ws = *ref;
     std::lock_guard<std::mutex> lock(ws.mu);
     return run_validate(ws, offsets, S, roi, lab, dims, N, M, st, dev);
 }
@@ -785,21 +1044,25 @@ int fastcod_release(void) {
     std::lock_guard<std::mutex> g(g_ws_mu);
     int prev = 0;
     (void)hipGetDevice(&prev);
-    for (auto &kv : g_ws) {
-        (void)hipSetDevice(kv.first.first);
-        (void)hipDeviceSynchronize();
-        Workspace *w = kv.second;
-        w->compact.release();
-        w->first.release();
-        w->ovf.release();
-        w->fallback.release();
-        w->flags.release();
-        w->ct.release();
-        w->ends.release();
+    bool busy = false;
+    hipError_t err = hipSuccess;
+    for (auto it = g_ws.begin(); it != g_ws.end();) {
+        Workspace *w = it->second;
+        if (w->refs > 0) {   // a call is enqueueing with it right now
+            busy = true;
+            ++it;
+            continue;
+        }
+        (void)hipSetDevice(it->first.dev);
+        const hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess && err == hipSuccess) err = e;
+        w->free_buffers();
         delete w;
+        it = g_ws.erase(it);
     }
-    g_ws.clear();
     (void)hipSetDevice(prev);
+    if (busy) return fail(FASTCOD_EBUSY, "a workspace was in use by a call in progress; it was kept");
+    if (err != hipSuccess) return hip_fail(err, "hipDeviceSynchronize");
     return FASTCOD_OK;
 }
 

@@ -199,11 +199,33 @@ hipError_t launch_transpose_many(const TransposeJob *jobs, int32_t njobs, int64_
 hipError_t launch_zero_subjects(const StreamSubject *subs, const int64_t *sizes, int32_t nsub, int cus, hipStream_t st);
 hipError_t launch_partition_batched(const StreamSubject *subs, const int64_t *item_base, int32_t nsub, int64_t nitems,
                                     int2 *items, int cus, hipStream_t st);
-int count_batched_blocks_per_cu(int batch, int coarse_words);
+// Kinds of subject of the batched form, each counted by its own launch (subjects of one kind are
+// neighbours in the descriptor table): pass-through, endpoint modes 1/2 (end labels first),
+// upsampled pass-through (u = 2, or u = 3..4), Alg. 1's seed-to-end count (no work items).
+enum class BatchedKind : int { kPass = 0, kEnds = 1, kUp2 = 2, kUp4 = 3, kSeedEnd = 4 };
+constexpr int kBatchedKinds = 5;
+inline BatchedKind batched_kind(int mode, int up) {
+    if (mode == 3) return BatchedKind::kSeedEnd;
+    if (up > 2) return BatchedKind::kUp4;
+    if (up == 2) return BatchedKind::kUp2;
+    return mode == 1 || mode == 2 ? BatchedKind::kEnds : BatchedKind::kPass;
+}
+int count_batched_blocks_per_cu(int batch, int coarse_words, BatchedKind kind = BatchedKind::kPass);
+// items[0, nitems) of subjects of one kind (kPass, kEnds, kUp2, kUp4)
 hipError_t launch_count_batched(const StreamSubject *subs, const int2 *items, int64_t nitems, const Overflow &ovf,
-                                int32_t coarse_words, int blocks, int batch, hipStream_t st);
+                                int32_t coarse_words, int blocks, int batch, BatchedKind kind, hipStream_t st);
+// table entries [lo, lo + n): end labels of their streamlines [s_begin, S) (entries in an endpoint mode)
+hipError_t launch_end_labels_batched(const StreamSubject *subs, int32_t lo, int32_t n, int cus, hipStream_t st);
+// table entries [lo, lo + n): Alg. 1's count of their streamlines [s_begin, S)
+hipError_t launch_count_seed_end_batched(const StreamSubject *subs, int32_t lo, int32_t n, int cus, hipStream_t st);
 hipError_t launch_fallback_batched(const StreamSubject *subs, int32_t nsub, const Overflow &ovf, FallbackScratch fs,
                                    hipStream_t st);
+
+// ceiling probes (measurement only): the read-only point stream, no-return atomics C[idx[k]] += 1,
+// and the stream with the compact-volume lookups of every point; sink: one device word
+hipError_t launch_probe_stream(const float *pts, int64_t P, int cus, uint32_t *sink, hipStream_t st);
+hipError_t launch_probe_atomics(int32_t *C, int64_t n_words, const uint32_t *idx, int64_t n, int cus, hipStream_t st);
+hipError_t launch_probe_lookup(const StreamSubject &sub, int64_t P, int cus, uint32_t *sink, hipStream_t st);
 
 hipError_t launch_validate(const int64_t *offsets, int64_t S, const int32_t *roi, const int32_t *lab,
                            int64_t nvox, int32_t N, int32_t M, int32_t *flags, int cus, hipStream_t st);

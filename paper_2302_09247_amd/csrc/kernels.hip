@@ -1409,7 +1409,10 @@ __global__ void __launch_bounds__(kBlock) k_count_stream_up(StreamSubject sub, O
 // Batched form: work items (subject, first streamline) from every subject, handed out by one
 // counter; each wavefront keeps the coarse map of the subject it last worked on in its own LDS.
 // The scale is always applied (multiplying by 1.0f is exact), the code width is read per subject.
-template <int kBatch>
+// One instantiation per kind of subject: pass-through (kEnds false, kUp 1), the endpoint modes
+// (kEnds: labels from sub.ends at each close), and upsampled pass-through (kUp 2 or 4, with
+// sub.up <= kUp); a launch takes the items of subjects of one kind only.
+template <int kBatch, bool kEnds, int kUp>
 __global__ void __launch_bounds__(kBlock) k_count_batched(const StreamSubject *__restrict__ subs,
                                                           const int2 *__restrict__ items, int64_t nitems,
                                                           Overflow ovf, int32_t coarse_words) {
@@ -1445,7 +1448,7 @@ __global__ void __launch_bounds__(kBlock) k_count_batched(const StreamSubject *_
             loaded = subject;
         }
         sink.C = sub.C;
-        stream_range<true, 2, kBatch, false, 1, false>(sub, coarse, s0, s1, subject, ovf, set, sink);
+        stream_range<true, 2, kBatch, kEnds, kUp, false>(sub, coarse, s0, s1, subject, ovf, set, sink);
         sink.drain();   // the next item may belong to another subject's C
     }
 }
@@ -1934,24 +1937,100 @@ hipError_t launch_partition_batched(const StreamSubject *subs, const int64_t *it
     return hipGetLastError();
 }
 
-template <int B>
+template <int B, bool E, int U>
 static int batched_blocks_per_cu_of(size_t dyn) {
     int n = 0;
     const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &n, reinterpret_cast<const void *>(&k_count_batched<B>), kBlock, dyn);
+        &n, reinterpret_cast<const void *>(&k_count_batched<B, E, U>), kBlock, dyn);
     return (e == hipSuccess && n > 0) ? n : 4;
 }
 
-int count_batched_blocks_per_cu(int batch, int coarse_words) {
+int count_batched_blocks_per_cu(int batch, int coarse_words, BatchedKind kind) {
     const size_t dyn = 4 * (size_t)kWavesPerBlock * (size_t)coarse_words;
-    return batch == 2 ? batched_blocks_per_cu_of<2>(dyn) : batched_blocks_per_cu_of<4>(dyn);
+    switch (kind) {
+        case BatchedKind::kEnds:
+            return batch == 2 ? batched_blocks_per_cu_of<2, true, 1>(dyn) : batched_blocks_per_cu_of<4, true, 1>(dyn);
+        case BatchedKind::kUp2: return batched_blocks_per_cu_of<2, false, 2>(dyn);
+        case BatchedKind::kUp4: return batched_blocks_per_cu_of<1, false, 4>(dyn);
+        default:
+            return batch == 2 ? batched_blocks_per_cu_of<2, false, 1>(dyn) : batched_blocks_per_cu_of<4, false, 1>(dyn);
+    }
 }
 
 hipError_t launch_count_batched(const StreamSubject *subs, const int2 *items, int64_t nitems, const Overflow &ovf,
-                                int32_t coarse_words, int blocks, int batch, hipStream_t st) {
+                                int32_t coarse_words, int blocks, int batch, BatchedKind kind, hipStream_t st) {
+    if (nitems <= 0) return hipSuccess;
     const size_t dyn = 4 * (size_t)kWavesPerBlock * (size_t)coarse_words;
-    if (batch == 2) k_count_batched<2><<<blocks, kBlock, dyn, st>>>(subs, items, nitems, ovf, coarse_words);
-    else k_count_batched<4><<<blocks, kBlock, dyn, st>>>(subs, items, nitems, ovf, coarse_words);
+    switch (kind) {
+        case BatchedKind::kEnds:
+            if (batch == 2) k_count_batched<2, true, 1><<<blocks, kBlock, dyn, st>>>(subs, items, nitems, ovf, coarse_words);
+            else k_count_batched<4, true, 1><<<blocks, kBlock, dyn, st>>>(subs, items, nitems, ovf, coarse_words);
+            break;
+        case BatchedKind::kUp2:   // two windows of two lookups each per batch, as k_count_stream_up<2>
+            k_count_batched<2, false, 2><<<blocks, kBlock, dyn, st>>>(subs, items, nitems, ovf, coarse_words);
+            break;
+        case BatchedKind::kUp4:
+            k_count_batched<1, false, 4><<<blocks, kBlock, dyn, st>>>(subs, items, nitems, ovf, coarse_words);
+            break;
+        default:
+            if (batch == 2) k_count_batched<2, false, 1><<<blocks, kBlock, dyn, st>>>(subs, items, nitems, ovf, coarse_words);
+            else k_count_batched<4, false, 1><<<blocks, kBlock, dyn, st>>>(subs, items, nitems, ovf, coarse_words);
+            break;
+    }
+    return hipGetLastError();
+}
+
+// End labels of table entries [lo, lo + gridDim.y) in an endpoint mode: sub.ends.last[s] (and, mode 2,
+// sub.ends.first[s]) for streamlines [s_begin, S) of each, as k_end_labels for one subject.
+__global__ void k_end_labels_batched(const StreamSubject *__restrict__ subs, int32_t lo) {
+    const StreamSubject &sub = subs[lo + blockIdx.y];
+    const int mode = sub.ends.mode;
+    if (mode != 1 && mode != 2) return;
+    const int64_t Ptot = sub.offsets[sub.S] > 0 ? sub.offsets[sub.S] : 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const CompactLookup lk{sub.cv};
+    for (int64_t s = clamp64(sub.s_begin, 0, sub.S) + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < sub.S;
+         s += stride) {
+        const int64_t b0 = clamp64(sub.offsets[s], 0, Ptot);
+        const int64_t b1 = clamp64(sub.offsets[s + 1], b0, Ptot);
+        int r, ml = -1, mf = -1;
+        if (b1 > b0) {
+            lookup_point<CompactLookup, true>(sub.pts + 3 * (b1 - 1), sub.scale, sub.g, lk, r, ml);
+            if (mode == 2) lookup_point<CompactLookup, true>(sub.pts + 3 * b0, sub.scale, sub.g, lk, r, mf);
+        }
+        const_cast<int32_t *>(sub.ends.last)[s] = ml;   // the plan's or request's own label arrays
+        if (mode == 2) const_cast<int32_t *>(sub.ends.first)[s] = mf;
+    }
+}
+
+// Alg. 1's count for table entries [lo, lo + gridDim.y): C(row of the first point, label of the last
+// point) += 1 for streamlines [s_begin, S) of each, as k_count_seed_end for one subject.
+__global__ void k_count_seed_end_batched(const StreamSubject *__restrict__ subs, int32_t lo) {
+    const StreamSubject &sub = subs[lo + blockIdx.y];
+    const int64_t Ptot = sub.offsets[sub.S] > 0 ? sub.offsets[sub.S] : 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const CompactLookup lk{sub.cv};
+    for (int64_t s = clamp64(sub.s_begin, 0, sub.S) + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < sub.S;
+         s += stride) {
+        const int64_t b0 = clamp64(sub.offsets[s], 0, Ptot);
+        const int64_t b1 = clamp64(sub.offsets[s + 1], b0, Ptot);
+        if (b1 <= b0) continue;
+        int r, m, r2, m2;
+        lookup_point<CompactLookup, true>(sub.pts + 3 * b0, sub.scale, sub.g, lk, r, m);
+        lookup_point<CompactLookup, true>(sub.pts + 3 * (b1 - 1), sub.scale, sub.g, lk, r2, m2);
+        if (r >= 0 && m2 >= 0) atomicAdd(sub.C + (uint32_t)r * sub.si + (uint32_t)m2 * sub.sm, 1);
+    }
+}
+
+hipError_t launch_end_labels_batched(const StreamSubject *subs, int32_t lo, int32_t n, int cus, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    k_end_labels_batched<<<dim3((unsigned)(cus > 0 ? cus : 64) * 2, (unsigned)n), kBlock, 0, st>>>(subs, lo);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_seed_end_batched(const StreamSubject *subs, int32_t lo, int32_t n, int cus, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    k_count_seed_end_batched<<<dim3((unsigned)(cus > 0 ? cus : 64) * 2, (unsigned)n), kBlock, 0, st>>>(subs, lo);
     return hipGetLastError();
 }
 
@@ -2301,6 +2380,147 @@ hipError_t launch_pair_histogram(const PairOut &po, int32_t nwaves, int32_t ntil
     k_pair_tile_counts<<<nblk, 1024, 0, st>>>(po, nwaves, ntiles, cursor, boff);
     k_pair_scatter<<<nblk, 1024, 0, st>>>(po, nwaves, ntiles, cursor, base, boff, sorted);
     k_pair_tile_add<<<ntiles, 512, 0, st>>>(sorted, base, C, NM);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------------
+// ceiling probes: what the counting path can reach on this device at best
+// ---------------------------------------------------------------------------------------------
+
+constexpr uint32_t kProbeMagic = 0x9E3779B9u;   // a folded value that (practically) never occurs
+
+// Points [P][3] streamed read-only with the counting kernel's access pattern: one contiguous range
+// per wavefront, 64 x 12-byte non-temporal buffer loads, kBatch windows per step.  The loaded bits
+// are folded into one word per lane, stored only if it equals kProbeMagic, so the loads stay.
+template <int kBatch>
+__global__ void __launch_bounds__(kBlock) k_probe_stream(const float *__restrict__ pts, int64_t P, int64_t nwaves,
+                                                         uint32_t *__restrict__ sink) {
+    const int lane = lane_id();
+    const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    const int64_t per = (P + nwaves - 1) / nwaves;
+    const int64_t p0 = min(P, wave * per), p1 = min(P, p0 + per);
+    const uint32_t L = (uint32_t)(p1 - p0);
+    const __amdgpu_buffer_rsrc_t rp = make_rsrc(pts + 3 * p0, 12ull * L);
+    const uint32_t lane12 = 12u * (uint32_t)lane;
+    uint32_t acc = 0u;
+    for (uint32_t w0 = 0; w0 < L; w0 += kBatch * kWave) {
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+            const auto v = __builtin_amdgcn_raw_buffer_load_b96(rp, lane12, 12u * w0 + 768u * b, kAuxStream);
+            acc ^= v[0] ^ (v[1] << 1) ^ (v[2] << 2);
+        }
+    }
+    if (acc == kProbeMagic) sink[0] = acc;
+}
+
+// No-return int32 atomic adds C[idx[k]] += 1, k < n (indices >= n_words are skipped), four index
+// loads in flight per thread before their atomics.
+__global__ void __launch_bounds__(kBlock) k_probe_atomics(int32_t *__restrict__ C, int64_t n_words,
+                                                          const uint32_t *__restrict__ idx, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k0 < n; k0 += 4 * stride) {
+        uint32_t v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t k = k0 + j * stride;
+            v[j] = k < n ? idx[k] : 0xFFFFFFFFu;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if ((int64_t)v[j] < n_words) atomicAdd(C + v[j], 1);
+    }
+}
+
+// The counting kernel's per-point lookups without its per-streamline work: the point stream of
+// k_probe_stream, voxelisation, the coarse test in LDS, the (word, rank base) gather and, for
+// occupied voxels, the code gather, folded like the stream probe.  No de-duplication, no pair
+// updates: the stream-plus-lookup ceiling of the flat-stream kernel.
+template <int kBatch, bool kBrick>
+__global__ void __launch_bounds__(kBlock) k_probe_lookup(StreamSubject sub, int64_t P, int64_t nwaves,
+                                                         uint32_t *__restrict__ sink) {
+    extern __shared__ uint32_t s_coarse[];
+    const CompactVol &cv = sub.cv;
+    for (int k = threadIdx.x; k < cv.ncoarse_words; k += blockDim.x) s_coarse[k] = cv.coarse[k];
+    __syncthreads();
+    const int lane = lane_id();
+    const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    const int64_t per = (P + nwaves - 1) / nwaves;
+    const int64_t p0 = min(P, wave * per), p1 = min(P, p0 + per);
+    const uint32_t L = (uint32_t)(p1 - p0);
+    const __amdgpu_buffer_rsrc_t rp = make_rsrc(sub.pts + 3 * p0, 12ull * L);
+    const __amdgpu_buffer_rsrc_t rvol = make_rsrc(cv.mb, cv.span);
+    const uint32_t lane12 = 12u * (uint32_t)lane;
+    const uint32_t bX = fbits(sub.g.Xf), bY = fbits(sub.g.Yf), bZ = fbits(sub.g.Zf);
+    const uint32_t SBX = (uint32_t)cv.SBX, SBXY = (uint32_t)cv.SBXY;
+    const uint32_t csx = (uint32_t)cv.csx, csyz = (uint32_t)cv.csyz, CBX = (uint32_t)cv.CBX, CBXY = (uint32_t)cv.CBXY;
+    const int codes_off = uniform32((int)cv.codes_off);
+    constexpr uint32_t kOutOfRange = 0xFFFFFFF8u;
+    const uint32_t code_oob = kOutOfRange - (uint32_t)codes_off;
+    uint32_t acc = 0u;
+    for (uint32_t w0 = 0; w0 < L; w0 += kBatch * kWave) {
+        uint32_t addr[kBatch], bix[kBatch];
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+            const auto v = __builtin_amdgcn_raw_buffer_load_b96(rp, lane12, 12u * w0 + 768u * b, kAuxStream);
+            const float tx = __fadd_rn(__fmul_rn(__uint_as_float(v[0]), sub.scale), 0.5f);
+            const float ty = __fadd_rn(__fmul_rn(__uint_as_float(v[1]), sub.scale), 0.5f);
+            const float tz = __fadd_rn(__fmul_rn(__uint_as_float(v[2]), sub.scale), 0.5f);
+            const bool ok = (w0 + b * kWave + (uint32_t)lane < L) & (fbits(tx) < bX) & (fbits(ty) < bY) & (fbits(tz) < bZ);
+            const uint32_t ix = (uint32_t)(int)tx, iy = (uint32_t)(int)ty, iz = (uint32_t)(int)tz;
+            const uint32_t sb = __umul24(iz >> 3, SBXY) + __umul24(iy >> 3, SBX) + (ix >> 4);
+            const uint32_t cb = kBrick ? sb : __umul24(iz >> csyz, CBXY) + __umul24(iy >> csyz, CBX) + (ix >> csx);
+            const uint32_t cw = s_coarse[ok ? (cb >> 5) : 0u];
+            const bool hit = ok & (__builtin_amdgcn_ubfe(cw, cb, 1) != 0u);
+            addr[b] = hit ? (sb << 8) | ((iy << 2) & 0x18u) | ((iz << 5) & 0xE0u) : kOutOfRange;
+            bix[b] = (ix & 15u) | ((iy & 1u) << 4);
+        }
+        uint32_t mw[kBatch], base[kBatch];
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+            const auto e = __builtin_amdgcn_raw_buffer_load_b64(rvol, addr[b], 0, kAuxCached);
+            mw[b] = e[0];
+            base[b] = e[1];
+        }
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+            const bool flag = __builtin_amdgcn_ubfe(mw[b], bix[b], 1) != 0u;
+            const uint32_t at = base[b] + __popc(__builtin_amdgcn_ubfe(mw[b], 0, bix[b]));
+            const uint32_t off = flag ? (cv.packed ? at << 2 : at << 3) : code_oob;
+            acc ^= __builtin_amdgcn_raw_buffer_load_b32(rvol, off, codes_off, kAuxCached);
+        }
+    }
+    if (acc == kProbeMagic) sink[0] = acc;
+}
+
+hipError_t launch_probe_stream(const float *pts, int64_t P, int cus, uint32_t *sink, hipStream_t st) {
+    if (P <= 0) return hipSuccess;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&k_probe_stream<4>),
+                                                     kBlock, 0) != hipSuccess || per_cu < 1)
+        per_cu = 4;
+    const int64_t blocks = (int64_t)cus * per_cu;
+    k_probe_stream<4><<<(unsigned)blocks, kBlock, 0, st>>>(pts, P, blocks * kWavesPerBlock, sink);
+    return hipGetLastError();
+}
+
+hipError_t launch_probe_atomics(int32_t *C, int64_t n_words, const uint32_t *idx, int64_t n, int cus, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n + kBlock - 1) / kBlock, (int64_t)cus * 8);
+    k_probe_atomics<<<(unsigned)blocks, kBlock, 0, st>>>(C, n_words, idx, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_probe_lookup(const StreamSubject &sub, int64_t P, int cus, uint32_t *sink, hipStream_t st) {
+    if (P <= 0) return hipSuccess;
+    const size_t dyn = 4 * (size_t)sub.cv.ncoarse_words;
+    const bool brick = sub.cv.csx == 4 && sub.cv.csyz == 3;
+    const void *fn = brick ? reinterpret_cast<const void *>(&k_probe_lookup<4, true>)
+                           : reinterpret_cast<const void *>(&k_probe_lookup<4, false>);
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, dyn) != hipSuccess || per_cu < 1) per_cu = 4;
+    const int64_t blocks = (int64_t)cus * per_cu;
+    if (brick) k_probe_lookup<4, true><<<(unsigned)blocks, kBlock, dyn, st>>>(sub, P, blocks * kWavesPerBlock, sink);
+    else k_probe_lookup<4, false><<<(unsigned)blocks, kBlock, dyn, st>>>(sub, P, blocks * kWavesPerBlock, sink);
     return hipGetLastError();
 }
 

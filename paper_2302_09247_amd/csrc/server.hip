@@ -37,6 +37,8 @@ class HipExecutor final : public fcs::Executor {
         cfg_ = cfg;
         cus_ = cu_count(dev);
         blocks_ = cus_ * fc::count_batched_blocks_per_cu(4, kBatchedCoarseWords);
+        for (int k = 0; k < fc::kBatchedKinds; ++k)
+            kind_blocks_[k] = cus_ * fc::count_batched_blocks_per_cu(4, kBatchedCoarseWords, (fc::BatchedKind)k);
         items_full_ = (int64_t)blocks_ * fc::kWavesPerBlock * kItemsPerWave;
         hipError_t e = hipMalloc(&base_, cfg.budget);
         if (e != hipSuccess) {
@@ -95,7 +97,21 @@ class HipExecutor final : public fcs::Executor {
         return record(comp_, t);
     }
 
+    int after_stream(void *stream, fcs::Token *t) override {
+        TokenRec *rec = nullptr;
+        if (int rc = take(&rec, t)) return rc;
+        if (hip(hipEventRecord(rec->ev, static_cast<hipStream_t>(stream)), "hipEventRecord on the request's stream")) {
+            release(*t);
+            *t = 0;
+            return FASTCOD_EHIP;
+        }
+        return FASTCOD_OK;
+    }
+
     int begin_request(const fcs::Request &r, fcs::Token *t) override {
+        if (r.ready && (r.ready > toks_.size() ||
+                        hip(hipStreamWaitEvent(comp_, toks_[r.ready - 1].ev, 0), "hipStreamWaitEvent")))
+            return r.ready > toks_.size() ? err(FASTCOD_EINVAL, "unknown token") : FASTCOD_EHIP;
         if (hip(fc::launch_fill_i32(device_C(r), (int64_t)r.N * r.M, 0, cus_, comp_), "zero fill") ||
             hip(hipMemcpyAsync(base_ + r.off_offsets, r.offsets, 8 * (size_t)(r.S + 1), hipMemcpyHostToDevice, comp_),
                 "offsets upload"))
@@ -112,11 +128,22 @@ class HipExecutor final : public fcs::Executor {
         return record(copy_, t);
     }
 
-    int launch_tick(const std::vector<fcs::Chunk> &chunks, fcs::Token *t) override {
-        const int32_t n = (int32_t)chunks.size();
+    int launch_tick(const std::vector<fcs::Chunk> &chunks_in, fcs::Token *t) override {
+        const int32_t n = (int32_t)chunks_in.size();
         if (n < 1 || n > cfg_.max_active) return err(FASTCOD_EINVAL, "launch of an unexpected size");
         Slot &s = slots_[next_slot_++ % kTickSlots];
         if (hip(hipEventSynchronize(s.last), "descriptor slot")) return FASTCOD_EHIP;
+        // table entries grouped by kind of request (each kind has a launch of its own)
+        auto kind_of = [](const fcs::Chunk &c) { return (int)fc::batched_kind(c.req->mode, c.req->up); };
+        std::vector<fcs::Chunk> chunks(chunks_in);
+        std::stable_sort(chunks.begin(), chunks.end(),
+                         [&](const fcs::Chunk &a, const fcs::Chunk &b) { return kind_of(a) < kind_of(b); });
+        int32_t kind_lo[fc::kBatchedKinds + 1];
+        for (int k = 0; k <= fc::kBatchedKinds; ++k) {
+            kind_lo[k] = 0;
+            for (const fcs::Chunk &c : chunks) kind_lo[k] += kind_of(c) < k ? 1 : 0;
+        }
+        const int seed = (int)fc::BatchedKind::kSeedEnd, ends = (int)fc::BatchedKind::kEnds;
         // fallback scratch for the largest volume of this launch
         int32_t maxN = 1, maxM = 1;
         for (const fcs::Chunk &c : chunks) {
@@ -125,7 +152,7 @@ class HipExecutor final : public fcs::Executor {
         }
         if (int rc = ensure_fallback(maxN, maxM)) return rc;
         int64_t total = 0;
-        for (const fcs::Chunk &c : chunks) total += c.req->offsets[c.s1] - c.req->offsets[c.s0];
+        for (int32_t k = 0; k < kind_lo[seed]; ++k) total += chunks[k].req->offsets[chunks[k].s1] - chunks[k].req->offsets[chunks[k].s0];
         const int64_t want = std::max<int64_t>(1, std::min<int64_t>(items_full_, total / kMinItemPoints));
         s.h_base[0] = 0;
         for (int32_t k = 0; k < n; ++k) {
@@ -145,27 +172,49 @@ class HipExecutor final : public fcs::Executor {
             ss.si = (uint32_t)v.M;
             ss.sm = 1u;
             ss.ends = fc::EndLabels{0, nullptr, nullptr};
-            ss.up = 1;
-            const int64_t pts = r.offsets[c.s1] - r.offsets[c.s0];
-            int64_t ni = total > 0 ? (int64_t)((double)want * (double)pts / (double)total + 0.5) : 1;
-            ni = std::max<int64_t>(1, std::min<int64_t>(ni, c.s1 - c.s0));
+            if (r.mode == FASTCOD_MODE_END || r.mode == FASTCOD_MODE_BOTH_ENDS) {
+                int32_t *last = reinterpret_cast<int32_t *>(base_ + r.off_ends);
+                ss.ends = fc::EndLabels{r.mode, last, r.mode == FASTCOD_MODE_BOTH_ENDS ? last + r.S : nullptr};
+            }
+            ss.up = r.up;
+            int64_t ni = 0;
+            if (k < kind_lo[seed]) {   // the seed-to-end kind takes no work items
+                const int64_t pts = r.offsets[c.s1] - r.offsets[c.s0];
+                ni = total > 0 ? (int64_t)((double)want * (double)pts / (double)total + 0.5) : 1;
+                ni = std::max<int64_t>(1, std::min<int64_t>(ni, c.s1 - c.s0));
+            }
             s.h_base[k + 1] = s.h_base[k] + ni;
         }
         const int64_t nitems = s.h_base[n];
         if (nitems + 1 > (int64_t)(s.d_items.n / 8)) return err(FASTCOD_EINVAL, "work item table overflow");
         const auto *subs = static_cast<const fc::StreamSubject *>(s.d_subs.p);
+        const int2 *items = static_cast<const int2 *>(s.d_items.p);
         if (hip(hipMemcpyAsync(s.d_subs.p, s.h_subs, sizeof(fc::StreamSubject) * n, hipMemcpyHostToDevice, comp_),
                 "descriptor upload") ||
             hip(hipMemcpyAsync(s.d_base.p, s.h_base, 8 * (size_t)(n + 1), hipMemcpyHostToDevice, comp_),
                 "descriptor upload") ||
-            hip(fc::launch_fill_u64(ovf_.count, 2, cus_, comp_), "counter reset") ||
-            hip(fc::launch_partition_batched(subs, static_cast<const int64_t *>(s.d_base.p), n, nitems,
-                                             static_cast<int2 *>(s.d_items.p), cus_, comp_),
-                "partition") ||
-            hip(fc::launch_count_batched(subs, static_cast<const int2 *>(s.d_items.p), nitems, ovf_,
-                                         kBatchedCoarseWords, blocks_, 4, comp_),
-                "count") ||
-            hip(fc::launch_fallback_batched(subs, n, ovf_, fs_, comp_), "fallback") ||
+            hip(fc::launch_fill_u64(ovf_.count, 1 + fc::kBatchedKinds, cus_, comp_), "counter reset") ||
+            hip(fc::launch_end_labels_batched(subs, kind_lo[ends], kind_lo[ends + 1] - kind_lo[ends], cus_, comp_),
+                "end labels"))
+            return FASTCOD_EHIP;
+        if (nitems > 0) {
+            if (hip(fc::launch_partition_batched(subs, static_cast<const int64_t *>(s.d_base.p), n, nitems,
+                                                 static_cast<int2 *>(s.d_items.p), cus_, comp_),
+                    "partition"))
+                return FASTCOD_EHIP;
+            for (int k = 0; k < seed; ++k) {
+                const int64_t lo = s.h_base[kind_lo[k]], hi = s.h_base[kind_lo[k + 1]];
+                fc::Overflow o = ovf_;
+                o.work = ovf_.count + 1 + k;
+                if (hip(fc::launch_count_batched(subs, items + lo, hi - lo, o, kBatchedCoarseWords, kind_blocks_[k], 4,
+                                                 (fc::BatchedKind)k, comp_),
+                        "count"))
+                    return FASTCOD_EHIP;
+            }
+            if (hip(fc::launch_fallback_batched(subs, n, ovf_, fs_, comp_), "fallback")) return FASTCOD_EHIP;
+        }
+        if (hip(fc::launch_count_seed_end_batched(subs, kind_lo[seed], kind_lo[seed + 1] - kind_lo[seed], cus_, comp_),
+                "seed-to-end count") ||
             hip(hipEventRecord(s.last, comp_), "hipEventRecord"))
             return FASTCOD_EHIP;
         return record(comp_, t);
@@ -298,6 +347,7 @@ class HipExecutor final : public fcs::Executor {
     }
 
     int dev_ = 0, cus_ = 256, blocks_ = 256;
+    int kind_blocks_[fc::kBatchedKinds] = {};
     int64_t items_full_ = 0;
     fcs::Config cfg_;
     char *base_ = nullptr;

@@ -153,6 +153,8 @@ struct Request {
     const int64_t *offsets = nullptr;   // host
     int64_t S = 0, P = 0;
     float scale = 1.0f;
+    int32_t mode = FASTCOD_MODE_PASSTHROUGH;
+    int32_t up = 1;                     // upsampling factor
     int32_t *C_out = nullptr;
     int32_t N = 0, M = 0;
     State state = State::Pending;
@@ -160,8 +162,10 @@ struct Request {
     bool cancel = false;
     int64_t t_submit = 0, t_admit = 0, t_done = 0;
     int64_t off_C = -1, off_offsets = -1, off_points = -1;
+    int64_t off_ends = -1;                           // end labels (endpoint modes): last[S] (and first[S])
     int64_t issued_s = 0, ready_s = 0, next_s = 0;
     std::deque<std::pair<Token, int64_t>> uploads;   // (token, streamline end) in issue order
+    Token ready = 0;                                 // FASTCOD_REQ_AFTER_STREAM: the caller's stream at submission
     Token begin = 0, final = 0;
     uint64_t last_tick = 0;                          // sequence number of the latest tick using it
     int64_t chunks = 0, ticks = 0;
@@ -182,7 +186,15 @@ class Executor {
     // of the volume are already in v)
     virtual int volume_bytes(const Volume &v, uint64_t *bytes, uint64_t *tmp_bytes) = 0;
     virtual int build_volume(const Volume &v, Token *t) = 0;
-    // zero the request's C and upload its offsets (ordered before every tick that uses it)
+    // a marker of the work enqueued so far on a caller's stream (submission time); begin_request
+    // orders the request's device work after r.ready
+    virtual int after_stream(void *stream, Token *t) {
+        (void)stream;
+        *t = 0;
+        return FASTCOD_OK;
+    }
+    // zero the request's C and upload its offsets (ordered before every tick that uses it, and
+    // after r.ready)
     virtual int begin_request(const Request &r, Token *t) = 0;
     // host points of streamlines [s0, s1) to the request's device copy
     virtual int upload(const Request &r, int64_t s0, int64_t s1, Token *t) = 0;
@@ -244,11 +256,18 @@ class Core {
     }
     int32_t volume_count() const { return (int32_t)vols_.size(); }
 
+    // end labels a request keeps on the device (endpoint modes)
+    static uint64_t ends_bytes(int64_t S, int32_t mode) {
+        if (mode == FASTCOD_MODE_END) return 4 * (uint64_t)S;
+        if (mode == FASTCOD_MODE_BOTH_ENDS) return 8 * (uint64_t)S;
+        return 0;
+    }
     // Device bytes a request holds while admitted (volume excluded).
-    static uint64_t request_bytes(int64_t S, int64_t P, int32_t N, int32_t M, uint32_t flags) {
+    static uint64_t request_bytes(int64_t S, int64_t P, int32_t N, int32_t M, uint32_t flags, int32_t mode = 0) {
         uint64_t b = Arena::round(8 * (uint64_t)(S + 1));
         if (!(flags & FASTCOD_REQ_DEVICE_POINTS)) b += Arena::round(12 * (uint64_t)P);
         if (!(flags & FASTCOD_REQ_DEVICE_C)) b += Arena::round(4 * (uint64_t)N * (uint64_t)M);
+        if (ends_bytes(S, mode)) b += Arena::round(ends_bytes(S, mode));
         return b;
     }
 
@@ -261,10 +280,16 @@ class Core {
             return set_err(err, FASTCOD_EINVAL, "n_streamlines must be in [0, INT32_MAX]");
         if (!q.offsets) return set_err(err, FASTCOD_EINVAL, "offsets is NULL");
         if (!q.C_out) return set_err(err, FASTCOD_EINVAL, "C_out is NULL");
-        if (q.flags & ~(uint32_t)(FASTCOD_REQ_DEVICE_POINTS | FASTCOD_REQ_DEVICE_C))
+        if (q.flags & ~(uint32_t)(FASTCOD_REQ_DEVICE_POINTS | FASTCOD_REQ_DEVICE_C | FASTCOD_REQ_AFTER_STREAM))
             return set_err(err, FASTCOD_EINVAL, "unknown request flag");
         if (!(q.scale == q.scale) || q.scale <= 0.0f || q.scale > 3.4e38f)
             return set_err(err, FASTCOD_EINVAL, "scale must be finite and > 0");
+        if (q.mode < FASTCOD_MODE_PASSTHROUGH || q.mode > FASTCOD_MODE_SEED_END)
+            return set_err(err, FASTCOD_EINVAL, "unknown mode");
+        const int32_t up = q.upsample == 0 ? 1 : q.upsample;
+        if (up < 1 || up > 4) return set_err(err, FASTCOD_EINVAL, "upsample must be 0..4");
+        if (up > 1 && q.mode != FASTCOD_MODE_PASSTHROUGH)
+            return set_err(err, FASTCOD_EINVAL, "upsampling is available for the pass-through mode only");
         // offsets (host): start at 0, nondecreasing
         const int64_t S = q.n_streamlines;
         if (q.offsets[0] != 0) return set_err(err, FASTCOD_ERANGE, "offsets[0] must be 0");
@@ -273,7 +298,7 @@ class Core {
         const int64_t P = q.offsets[S];
         if (P > 0 && !q.points) return set_err(err, FASTCOD_EINVAL, "points is NULL");
         if (P >= (int64_t(1) << 47)) return set_err(err, FASTCOD_EINVAL, "too many points");
-        const uint64_t need = request_bytes(S, P, v->N, v->M, q.flags) + Arena::round(v->bytes) +
+        const uint64_t need = request_bytes(S, P, v->N, v->M, q.flags, q.mode) + Arena::round(v->bytes) +
                               Arena::round(v->tmp_bytes);
         if (need > arena_.size())
             return set_err(err, FASTCOD_ENOMEM, "request needs " + std::to_string(need) +
@@ -288,9 +313,15 @@ class Core {
         r->S = S;
         r->P = P;
         r->scale = q.scale;
+        r->mode = q.mode;
+        r->up = up;
         r->C_out = q.C_out;
         r->N = v->N;
         r->M = v->M;
+        if (q.flags & FASTCOD_REQ_AFTER_STREAM) {
+            const int rc = ex_->after_stream(q.stream, &r->ready);
+            if (rc) return set_err(err, rc, "could not record the request's stream: " + ex_->detail());
+        }
         r->t_submit = now_ns();
         pending_.push_back(r.get());
         *id = r->id;
@@ -390,7 +421,12 @@ class Core {
         arena_.release(r.off_C);
         arena_.release(r.off_offsets);
         arena_.release(r.off_points);
-        r.off_C = r.off_offsets = r.off_points = -1;
+        arena_.release(r.off_ends);
+        r.off_C = r.off_offsets = r.off_points = r.off_ends = -1;
+        if (r.ready) {
+            ex_->release(r.ready);
+            r.ready = 0;
+        }
         if (r.state == State::Active || r.state == State::Finalizing) {
             Volume &v = *vols_[r.vol];
             --v.users;
@@ -500,8 +536,10 @@ class Core {
         if (v.off < 0) need += Arena::round(v.bytes) + Arena::round(v.tmp_bytes);
         if (!(r.flags & FASTCOD_REQ_DEVICE_POINTS)) need += Arena::round(12 * (uint64_t)r.P);
         if (!(r.flags & FASTCOD_REQ_DEVICE_C)) need += Arena::round(4 * (uint64_t)r.N * (uint64_t)r.M);
+        const uint64_t eb = ends_bytes(r.S, r.mode);
+        if (eb) need += Arena::round(eb);
         for (;;) {
-            int64_t offs[5] = {-1, -1, -1, -1, -1};
+            int64_t offs[6] = {-1, -1, -1, -1, -1, -1};
             bool ok = true;
             auto take = [&](int k, uint64_t bytes) {
                 if (!ok) return;
@@ -515,6 +553,7 @@ class Core {
             take(2, 8 * (uint64_t)(r.S + 1));
             if (!(r.flags & FASTCOD_REQ_DEVICE_POINTS)) take(3, 12 * (uint64_t)r.P);
             if (!(r.flags & FASTCOD_REQ_DEVICE_C)) take(4, 4 * (uint64_t)r.N * (uint64_t)r.M);
+            if (eb) take(5, eb);
             if (ok) {
                 if (v.off < 0) {
                     v.off = offs[0];
@@ -530,6 +569,7 @@ class Core {
                 r.off_offsets = offs[2];
                 r.off_points = offs[3];
                 r.off_C = offs[4];
+                r.off_ends = offs[5];
                 return true;
             }
             for (int64_t o : offs) arena_.release(o);
@@ -556,6 +596,10 @@ class Core {
             if (rc) {
                 fail(rc, "request set-up could not be issued");
                 return true;
+            }
+            if (r.ready) {   // begin_request has ordered the request's device work after it
+                ex_->release(r.ready);
+                r.ready = 0;
             }
             if (r.flags & FASTCOD_REQ_DEVICE_POINTS) r.issued_s = r.ready_s = r.S;
             progress = true;
@@ -740,7 +784,7 @@ class Service {
                     info->t_admit_ns = r->t_admit;
                     info->t_done_ns = r->t_done;
                     info->chunks = r->chunks;
-                    info->device_bytes = (int64_t)Core::request_bytes(r->S, r->P, r->N, r->M, r->flags);
+                    info->device_bytes = (int64_t)Core::request_bytes(r->S, r->P, r->N, r->M, r->flags, r->mode);
                 }
                 const int st = r->status;
                 core_.forget(id);

@@ -31,8 +31,10 @@ EXPORTS = (
     "fastcod_server_cancel", "fastcod_server_get_stats", "fastcod_server_destroy",
     "fastcod_parcellate",
 )
+# every symbol include/fastcod_probe.h declares (ceiling probes, measurement only)
+PROBE_EXPORTS = ("fastcod_probe_stream", "fastcod_probe_atomics", "fastcod_probe_lookup")
 PLAN_TUNE = 1
-REQ_DEVICE_POINTS, REQ_DEVICE_C = 1, 2
+REQ_DEVICE_POINTS, REQ_DEVICE_C, REQ_AFTER_STREAM = 1, 2, 4
 
 
 class FastcodError(RuntimeError):
@@ -52,7 +54,8 @@ class Subject(ctypes.Structure):
     _fields_ = [("points", ctypes.c_void_p), ("offsets", ctypes.c_void_p), ("n_streamlines", ctypes.c_int64),
                 ("roi_index_vol", ctypes.c_void_p), ("target_label_vol", ctypes.c_void_p),
                 ("dims", ctypes.c_int32 * 3), ("N", ctypes.c_int32), ("M", ctypes.c_int32),
-                ("scale", ctypes.c_float), ("C_out", ctypes.c_void_p)]
+                ("scale", ctypes.c_float), ("C_out", ctypes.c_void_p), ("mode", ctypes.c_int32),
+                ("upsample", ctypes.c_int32)]
 
 
 class Schedule(ctypes.Structure):
@@ -68,7 +71,8 @@ class ServerConfig(ctypes.Structure):
 class Request(ctypes.Structure):
     _fields_ = [("volume_id", ctypes.c_int32), ("flags", ctypes.c_uint32), ("points", ctypes.c_void_p),
                 ("offsets", ctypes.c_void_p), ("n_streamlines", ctypes.c_int64), ("scale", ctypes.c_float),
-                ("C_out", ctypes.c_void_p)]
+                ("C_out", ctypes.c_void_p), ("mode", ctypes.c_int32), ("upsample", ctypes.c_int32),
+                ("stream", ctypes.c_void_p)]
 
 
 class RequestInfo(ctypes.Structure):
@@ -121,12 +125,15 @@ def load(path: str = LIB_PATH):
     lib.fastcod_server_get_stats.argtypes = [_vp, ctypes.POINTER(ServerStats)]
     lib.fastcod_server_destroy.argtypes = [_vp]
     lib.fastcod_parcellate.argtypes = [_vp, i32, i32, _vp, _vp, _vp, _vp]
+    lib.fastcod_probe_stream.argtypes = [_vp, i64, _vp, _vp]
+    lib.fastcod_probe_atomics.argtypes = [_vp, i64, _vp, i64, _vp]
+    lib.fastcod_probe_lookup.argtypes = [_vp, _vp, i64, ctypes.c_float, _vp, _vp]
     for name in ("fastcod_count", "fastcod_count_ex", "fastcod_volume_create", "fastcod_volume_count",
                  "fastcod_volume_destroy", "fastcod_validate", "fastcod_release", "fastcod_plan_create",
                  "fastcod_plan_launch", "fastcod_plan_get_schedule", "fastcod_plan_destroy",
                  "fastcod_count_batched", "fastcod_server_create", "fastcod_server_add_volume",
                  "fastcod_server_submit", "fastcod_server_wait", "fastcod_server_cancel",
-                 "fastcod_server_get_stats", "fastcod_server_destroy", "fastcod_parcellate"):
+                 "fastcod_server_get_stats", "fastcod_server_destroy", "fastcod_parcellate", *PROBE_EXPORTS):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -242,9 +249,11 @@ class Volume:
     def nbytes(self) -> int:
         return int(load().fastcod_volume_bytes(self._h))
 
-    def count(self, points: torch.Tensor, offsets: torch.Tensor, *, scale: float = 1.0, accumulate: bool = False,
-              out: Optional[torch.Tensor] = None, stream=None, events=None, mode: int = MODE_PASSTHROUGH,
-              pair_capacity: int = 0) -> torch.Tensor:
+    def count(self, points: torch.Tensor, offsets: torch.Tensor, *, scale: float = 1.0, upsample: int = 1,
+              accumulate: bool = False, out: Optional[torch.Tensor] = None, stream=None, events=None,
+              mode: int = MODE_PASSTHROUGH, pair_capacity: int = 0, batch: int = 0,
+              blocks_per_cu: int = 0) -> torch.Tensor:
+        """C of these streamlines against the resident volume (fastcod_volume_count)."""
         lib = load()
         _dev(points, torch.float32, "points", (3,))
         _dev(offsets, torch.int64, "offsets")
@@ -252,7 +261,10 @@ class Volume:
             out = (torch.empty if not accumulate else torch.zeros)((self.N, self.M), dtype=torch.int32,
                                                                   device=points.device)
         _dev(out, torch.int32, "out")
-        o = make_opts(scale, 1, accumulate, False, VARIANT_STREAM, events, mode=mode, pair_capacity=pair_capacity)
+        if tuple(out.shape) != (self.N, self.M):
+            raise ValueError(f"out must be [{self.N}, {self.M}]")
+        o = make_opts(scale, upsample, accumulate, False, VARIANT_STREAM, events, batch, blocks_per_cu, mode,
+                      pair_capacity)
         with torch.cuda.device(points.device):
             _check(lib.fastcod_volume_count(self._h, _points_ptr(points), offsets.data_ptr(),
                                             int(offsets.shape[0]) - 1, out.data_ptr(), ctypes.byref(o),
@@ -312,7 +324,7 @@ def release() -> None:
 
 
 def make_subject(points: torch.Tensor, offsets: torch.Tensor, roi: torch.Tensor, lab: torch.Tensor, N: int, M: int,
-                 C: torch.Tensor, scale: float = 1.0) -> Subject:
+                 C: torch.Tensor, scale: float = 1.0, mode: int = MODE_PASSTHROUGH, upsample: int = 1) -> Subject:
     """C-ABI descriptor of one subject of a batched plan (the tensors must outlive the plan)."""
     _dev(points, torch.float32, "points", (3,))
     _dev(offsets, torch.int64, "offsets")
@@ -331,20 +343,23 @@ def make_subject(points: torch.Tensor, offsets: torch.Tensor, roi: torch.Tensor,
     u.N, u.M = int(N), int(M)
     u.scale = float(scale)
     u.C_out = C.data_ptr()
+    u.mode = int(mode)
+    u.upsample = int(upsample)
     return u
 
 
 class Plan:
     """Batched counting plan (fastcod_plan_*): one captured graph counting every subject.
 
-    ``subjects``: sequence of dicts with points, offsets, roi, lab, N, M, C and optional scale
-    (CUDA tensors, kept alive by the plan object)."""
+    ``subjects``: sequence of dicts with points, offsets, roi, lab, N, M, C and optional scale, mode
+    and upsample (CUDA tensors, kept alive by the plan object)."""
 
     def __init__(self, subjects, tune: bool = False, tune_cache: Optional[str] = None, stream=None):
         lib = load()
         self._keep = list(subjects)
         arr = (Subject * len(subjects))(*[make_subject(d["points"], d["offsets"], d["roi"], d["lab"], d["N"], d["M"],
-                                                       d["C"], d.get("scale", 1.0)) for d in subjects])
+                                                       d["C"], d.get("scale", 1.0), d.get("mode", 0),
+                                                       d.get("upsample", 1)) for d in subjects])
         h = _vp()
         dev = subjects[0]["points"].device
         with torch.cuda.device(dev):
@@ -381,7 +396,8 @@ def count_batched(subjects, stream=None) -> None:
     """One-shot batched count (fastcod_count_batched): every subject's C is overwritten."""
     lib = load()
     arr = (Subject * len(subjects))(*[make_subject(d["points"], d["offsets"], d["roi"], d["lab"], d["N"], d["M"],
-                                                   d["C"], d.get("scale", 1.0)) for d in subjects])
+                                                   d["C"], d.get("scale", 1.0), d.get("mode", 0), d.get("upsample", 1))
+                                      for d in subjects])
     with torch.cuda.device(subjects[0]["points"].device):
         _check(lib.fastcod_count_batched(arr, len(subjects), _stream_ptr(stream)))
 
@@ -416,8 +432,12 @@ class Server:
         self._vols[vid.value] = (int(N), int(M))
         return vid.value
 
-    def submit(self, volume_id: int, points: torch.Tensor, offsets, out: torch.Tensor, scale: float = 1.0) -> int:
-        """Queues a request; ``out`` ([N, M] int32, host or device) receives C.  Returns its id."""
+    def submit(self, volume_id: int, points: torch.Tensor, offsets, out: torch.Tensor, scale: float = 1.0,
+               mode: int = MODE_PASSTHROUGH, upsample: int = 1, stream=None) -> int:
+        """Queues a request; ``out`` ([N, M] int32, host or device) receives C.  Returns its id.
+
+        When points or out are device tensors, the server orders its accesses to them after the
+        work enqueued so far on ``stream`` (default: the current torch stream)."""
         if not isinstance(points, torch.Tensor) or points.dtype != torch.float32 or not points.is_contiguous() \
                 or points.dim() != 2 or points.shape[1] != 3:
             raise TypeError("points must be a contiguous float32 [P, 3] tensor")
@@ -428,9 +448,13 @@ class Server:
         if N is not None and tuple(out.shape) != (N, M):
             raise ValueError(f"out must be [{N}, {M}]")
         flags = (REQ_DEVICE_POINTS if points.is_cuda else 0) | (REQ_DEVICE_C if out.is_cuda else 0)
+        st = None
+        if points.is_cuda or out.is_cuda:
+            flags |= REQ_AFTER_STREAM
+            st = _stream_ptr(stream)
         pts_ptr = _points_ptr(points) if points.is_cuda else (points.data_ptr() if points.numel() else None)
         r = Request(int(volume_id), flags, pts_ptr, offsets.data_ptr(), int(offsets.shape[0]) - 1, float(scale),
-                    out.data_ptr())
+                    out.data_ptr(), int(mode), int(upsample), st)
         rid = ctypes.c_uint64()
         _check(load().fastcod_server_submit(self._h, ctypes.byref(r), ctypes.byref(rid)))
         self._keep[rid.value] = (points, offsets, out)
@@ -481,3 +505,38 @@ def _host_i64(a, name):
     if t.is_cuda or t.dtype != torch.int64 or t.dim() != 1 or t.shape[0] < 1:
         raise TypeError(f"{name} must be a host int64 [S+1] array")
     return t.contiguous()
+
+
+# ---- ceiling probes (include/fastcod_probe.h): each enqueues one kernel on the stream ----
+
+def _sink(device):
+    d = _dummy.get(("sink", device))
+    if d is None:
+        d = _dummy[("sink", device)] = torch.zeros(1, dtype=torch.int32, device=device)
+    return d.data_ptr()
+
+
+def probe_stream(points: torch.Tensor, stream=None) -> None:
+    """Reads every point once (12 bytes each) with the counting kernel's access pattern."""
+    _dev(points, torch.float32, "points", (3,))
+    with torch.cuda.device(points.device):
+        _check(load().fastcod_probe_stream(_points_ptr(points), int(points.shape[0]), _sink(points.device),
+                                           _stream_ptr(stream)))
+
+
+def probe_atomics(target: torch.Tensor, idx: torch.Tensor, stream=None) -> None:
+    """target[idx[k]] += 1 with no-return device atomics (int32 target, int32/uint32 indices)."""
+    _dev(target, torch.int32, "target")
+    if not isinstance(idx, torch.Tensor) or not idx.is_cuda or idx.dtype != torch.int32 or not idx.is_contiguous():
+        raise TypeError("idx must be a contiguous int32 CUDA tensor (read as uint32)")
+    with torch.cuda.device(target.device):
+        _check(load().fastcod_probe_atomics(target.data_ptr(), int(target.numel()), idx.data_ptr(), int(idx.numel()),
+                                            _stream_ptr(stream)))
+
+
+def probe_lookup(vol: "Volume", points: torch.Tensor, scale: float = 1.0, stream=None) -> None:
+    """The point stream plus every point's lookups in the resident volume (no de-duplication, no C)."""
+    _dev(points, torch.float32, "points", (3,))
+    with torch.cuda.device(points.device):
+        _check(load().fastcod_probe_lookup(vol.handle, _points_ptr(points), int(points.shape[0]), float(scale),
+                                           _sink(points.device), _stream_ptr(stream)))

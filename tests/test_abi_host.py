@@ -12,8 +12,11 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "fastcod.h")
 
 
-def _declared():
-    text = open(HEADER).read()
+PROBE_HEADER = os.path.join(ROOT, "include", "fastcod_probe.h")
+
+
+def _declared(header=HEADER):
+    text = open(header).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(fastcod_[a-z_]+)\s*\(", text)))
 
@@ -137,3 +140,20 @@ def test_upsampling_needs_passthrough(lib):
     o = lib.fastcod_default_opts()
     o.upsample, o.mode = 2, 1
     assert _count(lib, pts=16, off=16, roi=16, lab=16, C=16, opts=o) == fastcod.EINVAL
+
+
+def test_probe_header_symbols_are_exported(lib):
+    names = _declared(PROBE_HEADER)
+    assert set(names) == set(fastcod.PROBE_EXPORTS)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_probes_reject_bad_arguments(lib):
+    assert lib.fastcod_probe_stream(None, 5, 16, None) == fastcod.EINVAL
+    assert lib.fastcod_probe_stream(16, -1, 16, None) == fastcod.EINVAL
+    assert lib.fastcod_probe_stream(16, 1, None, None) == fastcod.EINVAL
+    assert lib.fastcod_probe_atomics(16, -1, 16, 1, None) == fastcod.EINVAL
+    assert lib.fastcod_probe_atomics(16, 4, None, 1, None) == fastcod.EINVAL
+    assert lib.fastcod_probe_lookup(None, 16, 1, 1.0, 16, None) == fastcod.EINVAL
+    assert lib.fastcod_probe_lookup(16, 16, 1, 0.0, 16, None) == fastcod.EINVAL

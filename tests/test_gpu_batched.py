@@ -155,3 +155,58 @@ def test_subjects_sharing_one_C_receive_the_sum(fc):
         torch.cuda.synchronize()
         np.testing.assert_array_equal(shared.cpu().numpy(), exp_ab)
         np.testing.assert_array_equal(subs[2]["C"].cpu().numpy(), exp_c)
+
+
+def test_plan_with_per_subject_options(fc):
+    """Every kind of subject in one plan, each against the oracle with its own options: pass-through,
+    the end label (Alg. 2 as printed), both end labels, Alg. 1's seed-to-end count, and point
+    insertion with u = 2, 3, 4 (Section 3); the endpoint modes and upsampling also on the overflow
+    workload, whose streamlines go through the batched fallback."""
+    vols = [synth.volumes_batch_subject(k) for k in range(3)]
+    specs = [(0, 1), (1, 1), (2, 1), (3, 1), (0, 2), (0, 3), (0, 4), (1, 1), (3, 1), (0, 1)]
+    subs = []
+    for j, (mode, up) in enumerate(specs):
+        k = j % 3
+        w = synth.make_batch_subject(k, seed=60 + j, S=2500 + 700 * j, device="cuda", vols=vols[k])
+        d = _subject(w)
+        d.update(mode=mode, upsample=up)
+        subs.append(d)
+    sr = synth.make_sr(seed=71, S=3000, device="cuda")
+    for mode, up in ((0, 2), (2, 1)):
+        d = _subject(sr)
+        d.update(mode=mode, upsample=up)
+        subs.append(d)
+    for mode, up in ((1, 1), (2, 1), (0, 4)):
+        d = _subject(_overflow_workload())
+        d.update(mode=mode, upsample=up)
+        subs.append(d)
+    for d in subs:
+        w = d["w"]
+        d["expect"] = oracle.count(w.points, w.offsets, w.roi, w.lab, w.N, w.M, scale=w.scale, mode=d["mode"],
+                                   upsample=d["upsample"])
+        assert d["expect"].sum() > 0, (w.name, d["mode"], d["upsample"])
+    plan = fc.Plan(subs)
+    for rep in range(2):
+        for d in subs:
+            d["C"].fill_(-3)
+        plan.launch()
+        torch.cuda.synchronize()
+        for d in subs:
+            np.testing.assert_array_equal(d["C"].cpu().numpy(), d["expect"],
+                                          err_msg=f"{d['w'].name} mode={d['mode']} u={d['upsample']} rep={rep}")
+    plan.close()
+    for d in subs:   # the plain call with the same options agrees
+        plain = fc.count(d["points"], d["offsets"], d["roi"], d["lab"], d["N"], d["M"], scale=d["scale"],
+                         mode=d["mode"], upsample=d["upsample"])
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(plain.cpu().numpy(), d["expect"])
+
+
+def test_plan_rejects_bad_subject_options(fc):
+    w = synth.make_tiny64(seed=8, S=100, device="cuda")
+    for mode, up in ((4, 1), (1, 2), (0, 5), (-1, 1)):
+        d = _subject(w)
+        d.update(mode=mode, upsample=up)
+        with pytest.raises(fc.FastcodError) as e:
+            fc.Plan([d])
+        assert e.value.status == fc.EINVAL

@@ -214,3 +214,66 @@ def test_submission_errors(fc, cases):
     with pytest.raises(fc.FastcodError):
         srv.wait(rid)            # waited for already
     srv.close()
+
+
+def test_requests_with_modes_and_upsampling(fc, cases):
+    """Requests in the endpoint modes, Alg. 1's count and with point insertion, mixed in one server
+    with pass-through ones, each against the oracle with its own options."""
+    srv = fc.Server(memory_budget=1 << 30, tick_points=1 << 15, chunk_points=1 << 11)
+    vids = _register(srv, cases)
+    pend = []
+    opts = [(1, 1), (2, 1), (3, 1), (0, 2), (0, 3), (0, 4), (0, 1)]
+    for j, (mode, up) in enumerate(opts):
+        for c, v in zip(cases, vids):
+            w = c["w"]
+            exp = oracle.count(w.points, w.offsets, w.roi, w.lab, w.N, w.M, scale=c["scale"], mode=mode, upsample=up)
+            dp = (j % 2) == 1
+            pts = w.points.cuda() if dp else _pinned(w.points)
+            out = torch.full((w.N, w.M), -5, dtype=torch.int32, pin_memory=True)
+            rid = srv.submit(v, pts, w.offsets, out, scale=c["scale"], mode=mode, upsample=up)
+            pend.append((rid, out, exp, f"{c['name']} mode={mode} u={up}"))
+    for rid, out, exp, name in pend:
+        info = srv.wait(rid, timeout=60)
+        assert info["status"] == fc.OK, name
+        np.testing.assert_array_equal(out.numpy(), exp, err_msg=name)
+    assert sum(int(e.sum()) for _, _, e, _ in pend) > 0
+    srv.close()
+
+
+def test_request_options_are_checked(fc, cases):
+    srv = fc.Server(memory_budget=64 << 20)
+    c = cases[0]
+    v = srv.add_volume(c["w"].roi, c["w"].lab, c["w"].N, c["w"].M)
+    out = torch.zeros((c["w"].N, c["w"].M), dtype=torch.int32)
+    for mode, up in ((4, 1), (1, 2), (0, 5)):
+        with pytest.raises(fc.FastcodError) as e:
+            srv.submit(v, _pinned(c["w"].points), c["w"].offsets, out, mode=mode, upsample=up)
+        assert e.value.status == fc.EINVAL
+    srv.close()
+
+
+def test_device_inputs_ordered_after_the_callers_stream(fc, cases):
+    """Device points and C written by work still in flight on the caller's stream at submission: the
+    server's zero fill, counting and result must come after that work (regression: its streams used
+    to ignore the caller's)."""
+    c = cases[1]
+    w = c["w"]
+    srv = fc.Server(memory_budget=1 << 30, tick_points=1 << 15)
+    v = srv.add_volume(w.roi, w.lab, w.N, w.M)
+    src = w.points.cuda()
+    busy = torch.ones(1 << 26, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    for rep in range(3):
+        pts = torch.empty_like(src)
+        out = torch.empty((w.N, w.M), dtype=torch.int32, device="cuda")
+        with torch.cuda.stream(side):
+            for _ in range(40):              # a long queue of work ahead of the writes
+                busy.mul_(1.0000001)
+            pts.copy_(src)
+            out.fill_(-5)
+            rid = srv.submit(v, pts, w.offsets, out)     # ordered after `side` (the current stream)
+        info = srv.wait(rid, timeout=60)
+        assert info["status"] == fc.OK
+        np.testing.assert_array_equal(out.cpu().numpy(), c["expect"], err_msg=f"rep {rep}")
+    srv.close()
