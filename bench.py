@@ -644,11 +644,11 @@ def run_served(args, fastcod, synth, rates) -> dict:
                 info = srv.wait(rids[i])
                 recs[i] = (info, bool(np.array_equal(outs[i].numpy(), solo[(kinds[i], int(subj[i]))])))
 
+        for i in range(nreq):
+            outs[i].fill_(-1)          # a request that wrote nothing cannot match an earlier result
         th = threading.Thread(target=collect)
         th.start()
         start = time.monotonic_ns() + 2_000_000
-        for i in range(nreq):
-            outs[i].fill_(-1)          # a request that wrote nothing cannot match an earlier result
         for i in range(nreq):
             due = start + int(arrive[i] * 1e9)
             while True:

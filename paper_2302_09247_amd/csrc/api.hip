@@ -210,7 +210,7 @@ int make_count_plan(int64_t S, int32_t N, int32_t M, const fc::CompactVol *cv, c
     cp.zero_c = !(o.flags & FASTCOD_ACCUMULATE) && !cp.transposed;
     cp.fused_zero = cv != nullptr && S > 0;
     if (S == 0) return FASTCOD_OK;
-    cp.ovf_bytes = 256 + 8 * (size_t)S;
+    cp.ovf_bytes = fc::overflow_header_bytes(1) + 8 * (size_t)S;
     if (cp.transposed) cp.ct_bytes = 4 * (size_t)N * (size_t)M;
     if (o.mode == FASTCOD_MODE_END || o.mode == FASTCOD_MODE_BOTH_ENDS) {
         cp.nl = o.mode == FASTCOD_MODE_BOTH_ENDS ? 2 : 1;
@@ -305,12 +305,14 @@ int enqueue_count(const CountPlan &cp, const CountScratch &sc, int dev, const fl
         FC_HIP(fc::launch_end_labels(a, rv, cv, o.mode, last, first, cus, st));
     }
     a.ovf.count = static_cast<unsigned long long *>(sc.ovf);
-    a.ovf.list = reinterpret_cast<int64_t *>(static_cast<char *>(sc.ovf) + 256);
+    a.ovf.list = reinterpret_cast<int64_t *>(static_cast<char *>(sc.ovf) + fc::overflow_header_bytes(1));
     a.ovf.cap = S;
-    a.ovf.work = static_cast<unsigned long long *>(sc.ovf) + 1;
+    a.ovf.work = a.ovf.count + fc::kQueueWords;
     fc::FallbackScratch fs = cp.fs;
     fs.words = sc.fallback;
-    if (!cp.fused_zero) FC_HIP(fc::launch_fill_u64(a.ovf.count, 2, cus, st));   // overflow count and range counter
+    // overflow count and range queues
+    const int64_t header_words = (int64_t)(fc::overflow_header_bytes(1) / 8);
+    if (!cp.fused_zero) FC_HIP(fc::launch_fill_u64(a.ovf.count, header_words, cus, st));
     if (cv) {
         char *pb = sc.pairs;
         fc::PairOut po;
@@ -326,8 +328,8 @@ int enqueue_count(const CountPlan &cp, const CountScratch &sc, int dev, const fl
             z.w32[1] = reinterpret_cast<int32_t *>(pb + cp.off_hist);
             z.n32[1] = fc::pair_hist_cursor_words(cp.ntiles);
         }
-        z.w64 = a.ovf.count;   // overflow count and range counter
-        z.n64 = 2;
+        z.w64 = a.ovf.count;   // overflow count and range queues
+        z.n64 = header_words;
         // tapering ranges (largest first) end the launch evenly when ranges are long; short ones
         // would only add per-range work
         FC_HIP(fc::launch_partition(offsets, S, cp.nparts, sc.first, z, S >= kLongRangesFrom, cus, st));
@@ -500,7 +502,8 @@ int plan_items(fastcod_plan &pl, const PlanSched &ps, int cus, hipStream_t st) {
 int plan_enqueue(fastcod_plan &pl, int cus, hipStream_t st) {
     const auto *subs = static_cast<const fc::StreamSubject *>(pl.d_subs.p);
     FC_HIP(fc::launch_zero_subjects(subs, static_cast<const int64_t *>(pl.d_sizes.p), pl.n, cus, st));
-    FC_HIP(fc::launch_fill_u64(pl.ovf.count, 1 + fc::kBatchedKinds, cus, st));   // overflow count, work counters
+    // overflow count and every kind's work-item queues
+    FC_HIP(fc::launch_fill_u64(pl.ovf.count, (int64_t)(fc::overflow_header_bytes(fc::kBatchedKinds) / 8), cus, st));
     const int32_t *kl = pl.kind_lo;
     const int ends = (int)fc::BatchedKind::kEnds, seed = (int)fc::BatchedKind::kSeedEnd;
     FC_HIP(fc::launch_end_labels_batched(subs, kl[ends], kl[ends + 1] - kl[ends], cus, st));
@@ -510,7 +513,7 @@ int plan_enqueue(fastcod_plan &pl, int cus, hipStream_t st) {
         const int2 *items = static_cast<const int2 *>(pl.d_items.p);
         for (int k = 0; k < seed; ++k) {
             fc::Overflow o = pl.ovf;
-            o.work = pl.ovf.count + 1 + k;
+            o.work = pl.ovf.count + fc::kQueueWords * (1 + (size_t)k * fc::kRangeQueues);
             FC_HIP(fc::launch_count_batched(subs, items + pl.item_lo[k], pl.item_lo[k + 1] - pl.item_lo[k], o,
                                             kBatchedCoarseWords, pl.kind_blocks[k], pl.sched.batch,
                                             (fc::BatchedKind)k, st));
@@ -729,10 +732,11 @@ int plan_build(const fastcod_subject *subjects, int32_t n, uint32_t flags, const
     FC_HIP(pl->d_sizes.ensure(8 * (size_t)n, false));
     FC_HIP(hipMemcpyAsync(pl->d_subs.p, pl->subs.data(), sizeof(fc::StreamSubject) * (size_t)n, hipMemcpyHostToDevice, st));
     FC_HIP(hipMemcpyAsync(pl->d_sizes.p, pl->sizes.data(), 8 * (size_t)n, hipMemcpyHostToDevice, st));
-    FC_HIP(pl->d_ovf.ensure(256 + 8 * (size_t)std::max<int64_t>(total_s, 1), false));
+    const size_t header = fc::overflow_header_bytes(fc::kBatchedKinds);
+    FC_HIP(pl->d_ovf.ensure(header + 8 * (size_t)std::max<int64_t>(total_s, 1), false));
     pl->ovf.count = static_cast<unsigned long long *>(pl->d_ovf.p);
-    pl->ovf.work = pl->ovf.count + 1;
-    pl->ovf.list = reinterpret_cast<int64_t *>(static_cast<char *>(pl->d_ovf.p) + 256);
+    pl->ovf.work = pl->ovf.count + fc::kQueueWords;
+    pl->ovf.list = reinterpret_cast<int64_t *>(static_cast<char *>(pl->d_ovf.p) + header);
     pl->ovf.cap = std::max<int64_t>(total_s, 1);
     pl->fs.nwordsN = (int32_t)max_nw_n;
     pl->fs.nwordsM = (int32_t)max_nw_m;

@@ -72,8 +72,22 @@ struct Overflow {
     unsigned long long *count;
     int64_t *list;
     int64_t cap;
-    unsigned long long *work;   // next point range to hand out (flat-stream kernel); zeroed per launch
+    unsigned long long *work;   // the range (work item) queues' counters (flat-stream and batched
+                                // kernels), kQueueWords apart; zeroed per launch
 };
+
+// Point ranges (work items) are handed out by kRangeQueues counters, each in a 128-byte line of its
+// own: wavefront w takes the ranges c, c + Q, c + 2Q, ... of queue c = w mod Q (Q = kRangeQueues, or
+// fewer for a small grid), so that no counter is contended by more than a few dozen wavefronts
+// (a single counter serialises every wavefront's fetch).  Counter block: one 128-byte line for the
+// overflow count, then the queues.
+constexpr int kRangeQueues = 64;
+constexpr int kQueueWords = 16;                                   // 64-bit words per counter line
+constexpr size_t kQueueBlockBytes = 128 * (size_t)kRangeQueues;  // one launch's queues
+// bytes before the overflow list: count line + `launches` blocks of queues (256-aligned)
+inline size_t overflow_header_bytes(int launches) {
+    return (128 + kQueueBlockBytes * (size_t)launches + 255) & ~size_t(255);
+}
 
 // Per-workgroup scratch of the fallback kernel; bit maps are all-zero between launches.
 struct FallbackScratch {

@@ -967,6 +967,18 @@ __device__ __forceinline__ int64_t uniform64(int64_t v) {
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
+// Next point range (work item) of wavefront `wave`: queue c = wave mod Q holds ranges c, c + Q,
+// c + 2Q, ..., handed out in that order by its own counter (Q: kRangeQueues, or the largest power of
+// two not above the grid's wavefronts, so that every queue has wavefronts).
+__device__ __forceinline__ int64_t next_range(const Overflow &ovf, uint32_t wave) {
+    const uint32_t nw = gridDim.x * (uint32_t)kWavesPerBlock;
+    const uint32_t q = nw >= (uint32_t)kRangeQueues ? (uint32_t)kRangeQueues : (1u << (31 - __builtin_clz(nw)));
+    const uint32_t c = wave & (q - 1u);
+    unsigned long long t = 0;
+    if (lane_id() == 0) t = atomicAdd(ovf.work + (size_t)c * kQueueWords, 1ull);
+    return (int64_t)c + (int64_t)q * uniform64((int64_t)t);
+}
+
 constexpr int kRCap = 192, kLCap = 64, kTCap = 512;   // per-wave candidate lists and set
 constexpr int64_t kMaxRangePoints = int64_t(1) << 28;  // longest point range the flat-stream loop takes
 constexpr int kSetWords = kRCap + 2 * kLCap + kTCap;
@@ -1364,9 +1376,7 @@ __global__ void __launch_bounds__(kBlock) k_count_stream(StreamSubject sub, Over
     sink.init(s_pend + wv * kWave, sub.C, po, wave);
     for (;;) {
         // next point range: streamlines [first[part], first[part+1])
-        unsigned long long t = 0;
-        if (lane == 0) t = atomicAdd(ovf.work, 1ull);
-        const int64_t part = uniform64((int64_t)t);
+        const int64_t part = next_range(ovf, wave);
         if (part >= nparts) break;
         const int64_t s0 = uniform64(clamp64(first[part], 0, sub.S));
         const int64_t s1 = uniform64(clamp64(first[part + 1], s0, sub.S));
@@ -1394,9 +1404,7 @@ __global__ void __launch_bounds__(kBlock) k_count_stream_up(StreamSubject sub, O
     AppendSink sink;
     sink.init(s_pend + wv * kWave, sub.C, po, wave);
     for (;;) {
-        unsigned long long t = 0;
-        if (lane == 0) t = atomicAdd(ovf.work, 1ull);
-        const int64_t part = uniform64((int64_t)t);
+        const int64_t part = next_range(ovf, wave);
         if (part >= nparts) break;
         const int64_t s0 = uniform64(clamp64(first[part], 0, sub.S));
         const int64_t s1 = uniform64(clamp64(first[part + 1], s0, sub.S));
@@ -1427,10 +1435,9 @@ __global__ void __launch_bounds__(kBlock) k_count_batched(const StreamSubject *_
     BufferedSink sink;
     sink.init(s_pend + wv * kWave, nullptr);
     int loaded = -1;
+    const uint32_t wave = blockIdx.x * kWavesPerBlock + wv;
     for (;;) {
-        unsigned long long t = 0;
-        if (lane == 0) t = atomicAdd(ovf.work, 1ull);
-        const int64_t item = uniform64((int64_t)t);
+        const int64_t item = next_range(ovf, wave);
         if (item >= nitems) break;
         const int2 it = items[item];
         const int subject = uniform32(it.x);

@@ -59,10 +59,11 @@ class HipExecutor final : public fcs::Executor {
             FC_HIP(hipEventCreateWithFlags(&s.last, hipEventDisableTiming));
             FC_HIP(hipEventRecord(s.last, comp_));
         }
-        FC_HIP(d_ovf_.ensure(256 + 8 * (size_t)cfg.tick_streamlines, false));
+        const size_t header = fc::overflow_header_bytes(fc::kBatchedKinds);
+        FC_HIP(d_ovf_.ensure(header + 8 * (size_t)cfg.tick_streamlines, false));
         ovf_.count = static_cast<unsigned long long *>(d_ovf_.p);
-        ovf_.work = ovf_.count + 1;
-        ovf_.list = reinterpret_cast<int64_t *>(static_cast<char *>(d_ovf_.p) + 256);
+        ovf_.work = ovf_.count + fc::kQueueWords;
+        ovf_.list = reinterpret_cast<int64_t *>(static_cast<char *>(d_ovf_.p) + header);
         ovf_.cap = cfg.tick_streamlines;
         return FASTCOD_OK;
     }
@@ -193,7 +194,8 @@ class HipExecutor final : public fcs::Executor {
                 "descriptor upload") ||
             hip(hipMemcpyAsync(s.d_base.p, s.h_base, 8 * (size_t)(n + 1), hipMemcpyHostToDevice, comp_),
                 "descriptor upload") ||
-            hip(fc::launch_fill_u64(ovf_.count, 1 + fc::kBatchedKinds, cus_, comp_), "counter reset") ||
+            hip(fc::launch_fill_u64(ovf_.count, (int64_t)(fc::overflow_header_bytes(fc::kBatchedKinds) / 8), cus_, comp_),
+                "counter reset") ||
             hip(fc::launch_end_labels_batched(subs, kind_lo[ends], kind_lo[ends + 1] - kind_lo[ends], cus_, comp_),
                 "end labels"))
             return FASTCOD_EHIP;
@@ -205,7 +207,7 @@ class HipExecutor final : public fcs::Executor {
             for (int k = 0; k < seed; ++k) {
                 const int64_t lo = s.h_base[kind_lo[k]], hi = s.h_base[kind_lo[k + 1]];
                 fc::Overflow o = ovf_;
-                o.work = ovf_.count + 1 + k;
+                o.work = ovf_.count + fc::kQueueWords * (1 + (size_t)k * fc::kRangeQueues);
                 if (hip(fc::launch_count_batched(subs, items + lo, hi - lo, o, kBatchedCoarseWords, kind_blocks_[k], 4,
                                                  (fc::BatchedKind)k, comp_),
                         "count"))
