@@ -143,6 +143,24 @@ int fastcod_volume_count(const fastcod_volume *vol, const float *points, const i
 int fastcod_volume_destroy(fastcod_volume *vol);
 
 /*
+ * fastcod_volume_count without any device allocation, for callers that cannot allocate: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.  Arguments,
+ * result and asynchrony are those of fastcod_volume_count (the volume handle is created
+ * beforehand; C_out and the streamlines stay the caller's).  Instead of the per-stream workspace,
+ * every call on a device uses one fixed scratch area of 72 MiB that the library holds on that
+ * device until the process ends; nothing is allocated or freed by the call.  Limits: at most 2^21
+ * streamlines per call (EINVAL beyond), at most 2^21 appended C updates (the rest go to C as
+ * atomics, same result), a C of more than 2^26 entries takes atomics into C_out itself (no
+ * transposed copy), and N and M whose overflow bit maps exceed 4 MiB fail with ENOMEM -- every
+ * such check happens before anything is enqueued.  Calls on one device share the area: calls
+ * that overlap in time on one device (two streams, or two threads) race and give wrong counts,
+ * so serialise them (one stream).  The area keeps the last call's contents; each call clears what
+ * it needs zeroed with a kernel of its own (no memset node under capture).
+ */
+int fastcod_volume_count_noalloc(const fastcod_volume *vol, const float *points, const int64_t *offsets,
+                                 int64_t n_streamlines, int32_t *C_out, const fastcod_opts *opts, void *stream);
+
+/*
  * Batched form: many subjects (each its own streamlines, volumes, N, M, scale, mode, upsampling and
  * C) counted by persistent kernels that take (subject, point range) work items from a counter, the
  * whole sequence (zero every C, end labels, partition, count, overflow fallback, transposes) captured
@@ -339,7 +357,8 @@ const char *fastcod_strerror(int status);
 const char *fastcod_last_error(void);
 /* Frees every cached workspace that no call is using (synchronises the devices that own them
  * first).  FASTCOD_EBUSY: a call on another thread was enqueueing with one of them at that moment;
- * that workspace was kept (the others are freed) -- call again once that call has returned. */
+ * that workspace was kept (the others are freed) -- call again once that call has returned.  The
+ * fixed scratch area of fastcod_volume_count_noalloc is not a workspace and is never freed. */
 int fastcod_release(void);
 
 #ifdef __cplusplus

@@ -807,6 +807,37 @@ int plan_build(const fastcod_subject *subjects, int32_t n, uint32_t flags, const
 
 }  // namespace
 
+// ---- fixed scratch area of fastcod_volume_count_noalloc ----
+// One static device array (each device that loads the library holds its own copy until the process
+// ends).  In host code `scratch` is only a stand-in for the symbol: its device address comes from
+// hipGetSymbolAddress, once per device, and only that address is ever handed to kernels.
+constexpr size_t kNoAllocScratchBytes = size_t(72) << 20;
+constexpr int64_t kNoAllocMaxStreamlines = int64_t(1) << 21;
+constexpr int64_t kNoAllocMaxPairs = int64_t(1) << 21;          // appended updates (the rest go to C as atomics)
+constexpr int64_t kNoAllocFallbackBytes = int64_t(4) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, char *> g_scratch_ptr;
+
+// device address of `scratch` on dev (the current device)
+int noalloc_scratch(int dev, char **out) {
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it != g_scratch_ptr.end()) {
+        *out = it->second;
+        return FASTCOD_OK;
+    }
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[dev] = static_cast<char *>(p);
+    *out = static_cast<char *>(p);
+    return FASTCOD_OK;
+}
+}  // namespace
+
 struct fastcod_volume {
     int device;
     int32_t dims[3];
@@ -952,6 +983,55 @@ int fastcod_volume_count(const fastcod_volume *vol, const float *points, const i
     const fc::Grid g = make_grid(vol->dims);
     fc::CompactVol cv = compact_view(vol->buf, vol->L, vol->N, vol->M);
     return enqueue_count_ws(ws, dev, points, offsets, S, g, vol->N, vol->M, nullptr, &cv, C, o, st);
+}
+
+int fastcod_volume_count_noalloc(const fastcod_volume *vol, const float *points, const int64_t *offsets, int64_t S,
+                                 int32_t *C, const fastcod_opts *opts, void *stream) {
+    last_error().clear();
+    if (!vol) return fail(FASTCOD_EINVAL, "vol is NULL");
+    const fastcod_opts o = opts ? *opts : fastcod_default_opts();
+    int rc = check_stream_args(points, offsets, S, C, o);
+    if (rc) return rc;
+    if (o.variant == FASTCOD_VARIANT_WAVE) return fail(FASTCOD_EINVAL, "a resident volume has no raster form");
+    if (o.flags & FASTCOD_VALIDATE) return fail(FASTCOD_EINVAL, "validate the source volumes before creating the handle");
+    if (S > kNoAllocMaxStreamlines)
+        return fail(FASTCOD_EINVAL, "fastcod_volume_count_noalloc counts at most 2^21 streamlines per call");
+    int dev;
+    rc = current_device(&dev);
+    if (rc) return rc;
+    if (dev != vol->device) return fail(FASTCOD_EINVAL, "volume lives on another device");
+    char *base = nullptr;
+    rc = noalloc_scratch(dev, &base);
+    if (rc) return rc;
+    const fc::CompactVol cv = compact_view(vol->buf, vol->L, vol->N, vol->M);
+    CountPlan cp;
+    rc = make_count_plan(S, vol->N, vol->M, &cv, o, cu_count(dev), true, kNoAllocMaxPairs, kNoAllocFallbackBytes, cp);
+    if (rc) return rc;
+    // carve the regions out of the fixed area; reject before anything is enqueued if they do not fit
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char * {
+        if (!bytes) return nullptr;
+        char *p = base + off;
+        off = align256(off + bytes);
+        return p;
+    };
+    CountScratch sc;
+    sc.ovf = take(cp.ovf_bytes);
+    sc.ct = reinterpret_cast<int32_t *>(take(cp.ct_bytes));
+    sc.ends = reinterpret_cast<int32_t *>(take(cp.ends_bytes));
+    sc.fallback = reinterpret_cast<uint32_t *>(take(cp.fb_bytes));
+    sc.first = reinterpret_cast<int32_t *>(take(cp.first_bytes));
+    sc.pairs = take(cp.pairs_bytes);
+    if (off > kNoAllocScratchBytes)
+        return fail(FASTCOD_ENOMEM, "this call needs " + std::to_string(off) + " bytes of scratch; the fixed area holds " +
+                                        std::to_string(kNoAllocScratchBytes));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    FC_HIP(hipStreamWaitEvent(st, vol->ready, 0));
+    // the fallback's bit maps must start all-zero; an earlier call may have left other contents there
+    if (cp.fb_bytes) FC_HIP(fc::launch_fill_i32(reinterpret_cast<int32_t *>(sc.fallback), (int64_t)(cp.fb_bytes / 4), 0,
+                                                cu_count(dev), st));
+    const fc::Grid g = make_grid(vol->dims);
+    return enqueue_count(cp, sc, dev, points, offsets, S, g, vol->N, vol->M, nullptr, &cv, C, o, st);
 }
 
 int fastcod_probe_stream(const float *points, int64_t P, uint32_t *sink, void *stream) {

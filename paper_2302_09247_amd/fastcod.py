@@ -23,7 +23,8 @@ MODE_PASSTHROUGH, MODE_END, MODE_BOTH_ENDS, MODE_SEED_END = 0, 1, 2, 3
 # every symbol include/fastcod.h declares
 EXPORTS = (
     "fastcod_default_opts", "fastcod_count", "fastcod_count_ex", "fastcod_volume_create",
-    "fastcod_volume_bytes", "fastcod_volume_count", "fastcod_volume_destroy", "fastcod_validate",
+    "fastcod_volume_bytes", "fastcod_volume_count", "fastcod_volume_destroy", "fastcod_volume_count_noalloc",
+    "fastcod_validate",
     "fastcod_strerror", "fastcod_last_error", "fastcod_release",
     "fastcod_plan_create", "fastcod_plan_launch", "fastcod_plan_get_schedule", "fastcod_plan_destroy",
     "fastcod_count_batched",
@@ -108,6 +109,7 @@ def load(path: str = LIB_PATH):
     lib.fastcod_volume_bytes.restype = ctypes.c_size_t
     lib.fastcod_volume_count.argtypes = [_vp, _vp, _vp, i64, _vp, ctypes.POINTER(Opts), _vp]
     lib.fastcod_volume_destroy.argtypes = [_vp]
+    lib.fastcod_volume_count_noalloc.argtypes = [_vp, _vp, _vp, i64, _vp, ctypes.POINTER(Opts), _vp]
     lib.fastcod_validate.argtypes = [_vp, i64, _vp, _vp, _vp, i32, i32, _vp]
     lib.fastcod_strerror.argtypes = [ctypes.c_int]
     lib.fastcod_strerror.restype = ctypes.c_char_p
@@ -129,6 +131,7 @@ def load(path: str = LIB_PATH):
     lib.fastcod_probe_atomics.argtypes = [_vp, i64, _vp, i64, _vp]
     lib.fastcod_probe_lookup.argtypes = [_vp, _vp, i64, ctypes.c_float, _vp, _vp]
     for name in ("fastcod_count", "fastcod_count_ex", "fastcod_volume_create", "fastcod_volume_count",
+                 "fastcod_volume_count_noalloc",
                  "fastcod_volume_destroy", "fastcod_validate", "fastcod_release", "fastcod_plan_create",
                  "fastcod_plan_launch", "fastcod_plan_get_schedule", "fastcod_plan_destroy",
                  "fastcod_count_batched", "fastcod_server_create", "fastcod_server_add_volume",
@@ -251,13 +254,17 @@ class Volume:
 
     def count(self, points: torch.Tensor, offsets: torch.Tensor, *, scale: float = 1.0, upsample: int = 1,
               accumulate: bool = False, out: Optional[torch.Tensor] = None, stream=None, events=None,
-              mode: int = MODE_PASSTHROUGH, pair_capacity: int = 0, batch: int = 0,
-              blocks_per_cu: int = 0) -> torch.Tensor:
-        """C of these streamlines against the resident volume (fastcod_volume_count)."""
+              mode: int = MODE_PASSTHROUGH, pair_capacity: int = 0, batch: int = 0, blocks_per_cu: int = 0,
+              noalloc: bool = False) -> torch.Tensor:
+        """C of these streamlines against the resident volume (fastcod_volume_count, or with
+        ``noalloc`` fastcod_volume_count_noalloc: the library's fixed scratch area, no allocation;
+        then ``out`` must be given so that nothing is allocated here either)."""
         lib = load()
         _dev(points, torch.float32, "points", (3,))
         _dev(offsets, torch.int64, "offsets")
         if out is None:
+            if noalloc:
+                raise ValueError("noalloc counts need a preallocated out")
             out = (torch.empty if not accumulate else torch.zeros)((self.N, self.M), dtype=torch.int32,
                                                                   device=points.device)
         _dev(out, torch.int32, "out")
@@ -265,10 +272,10 @@ class Volume:
             raise ValueError(f"out must be [{self.N}, {self.M}]")
         o = make_opts(scale, upsample, accumulate, False, VARIANT_STREAM, events, batch, blocks_per_cu, mode,
                       pair_capacity)
+        fn = lib.fastcod_volume_count_noalloc if noalloc else lib.fastcod_volume_count
         with torch.cuda.device(points.device):
-            _check(lib.fastcod_volume_count(self._h, _points_ptr(points), offsets.data_ptr(),
-                                            int(offsets.shape[0]) - 1, out.data_ptr(), ctypes.byref(o),
-                                            _stream_ptr(stream)))
+            _check(fn(self._h, _points_ptr(points), offsets.data_ptr(), int(offsets.shape[0]) - 1, out.data_ptr(),
+                      ctypes.byref(o), _stream_ptr(stream)))
         return out
 
     def close(self):

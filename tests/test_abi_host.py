@@ -142,6 +142,23 @@ def test_upsampling_needs_passthrough(lib):
     assert _count(lib, pts=16, off=16, roi=16, lab=16, C=16, opts=o) == fastcod.EINVAL
 
 
+def test_noalloc_count_rejects_bad_arguments(lib):
+    """The no-alloc entry point checks its arguments (and its streamline limit) before any HIP
+    call; the handle is never touched by these failures."""
+    f = lib.fastcod_volume_count_noalloc
+    assert f(None, 16, 16, 1, 16, None, None) == fastcod.EINVAL
+    assert f(16, 16, None, 1, 16, None, None) == fastcod.EINVAL
+    assert f(16, 16, 16, 1, None, None, None) == fastcod.EINVAL
+    assert f(16, 16, 16, (1 << 21) + 1, 16, None, None) == fastcod.EINVAL
+    assert b"2^21" in lib.fastcod_last_error()
+    o = lib.fastcod_default_opts()
+    o.variant = fastcod.VARIANT_WAVE
+    assert f(16, 16, 16, 1, 16, ctypes.byref(o), None) == fastcod.EINVAL
+    o = lib.fastcod_default_opts()
+    o.flags = fastcod.VALIDATE
+    assert f(16, 16, 16, 1, 16, ctypes.byref(o), None) == fastcod.EINVAL
+
+
 def test_probe_header_symbols_are_exported(lib):
     names = _declared(PROBE_HEADER)
     assert set(names) == set(fastcod.PROBE_EXPORTS)
