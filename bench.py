@@ -21,7 +21,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0        # MI355X HBM3E peak
-KERNEL_NAME = "k_count_stream"
+KERNEL_NAME = "k_count_stream4"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "count_stream_07mm_traffic.json")
 
 
@@ -537,44 +537,55 @@ def bench_ceilings(args):
 
 
 def bench_sr(args):
-    """Super-resolution job (Section 3): 1.25 mm streamlines (S = 1M, 0.5-voxel steps) scaled by
-    fl32(1.25/0.7) onto the 0.7 mm volumes, counted as given (u = 1) and with one point inserted
-    between neighbours (u = 2, 0.45-voxel spacing on the fine grid).  HBM bytes per point are the
-    same 12 for both: the inserted points never leave registers."""
+    """Calls of one million streamlines: the 1.25 mm subject (u = 1), and the super-resolution job
+    (Section 3): 1.25 mm streamlines (0.5-voxel steps) scaled by fl32(1.25/0.7) onto the 0.7 mm
+    volumes, counted as given (u = 1) and with one point inserted between neighbours (u = 2,
+    0.45-voxel spacing on the fine grid).  HBM bytes per point are the same 12 for every row: the
+    inserted points never leave registers.  Bytes: 12 P + 8 (S+1) + 8 X Y Z + 4 N M."""
     import torch
     from paper_2302_09247_amd import fastcod, synth
-    w = synth.make_sr(S=1_000_000, device="cuda")
-    torch.cuda.synchronize()
     ev = HipEvents()
     stream = torch.cuda.current_stream()
-    C = torch.empty((w.N, w.M), dtype=torch.int32, device="cuda")
     rows = []
-    for u in (1, 2):
-        for _ in range(args.warmup):
-            fastcod.count(w.points, w.offsets, w.roi, w.lab, w.N, w.M, scale=w.scale, upsample=u, out=C, stream=stream)
-        ks = []
+    for name, make, ups in (("1.25mm", lambda: synth.make_125mm(S=1_000_000, device="cuda"), (1,)),
+                            ("sr", lambda: synth.make_sr(S=1_000_000, device="cuda"), (1, 2))):
+        w = make()
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            a, b = ev.create(), ev.create()
-            fastcod.count(w.points, w.offsets, w.roi, w.lab, w.N, w.M, scale=w.scale, upsample=u, out=C,
-                          stream=stream, events=(a, b))
-            ks.append((a, b))
-        torch.cuda.synchronize()
-        step = (time.perf_counter() - t0) / args.steps
-        kms = sum(ev.elapsed_ms(a, b) for a, b in ks) / len(ks)
-        pairs = int(C.sum(dtype=torch.int64).item())
-        alg = 12 * w.P + 8 * (w.S + 1) + 4 * pairs
-        rows.append({"upsample": u, "ms_per_step": step * 1e3, "kernel_ms": kms, "points_per_s": w.P / step,
-                     "counted_points_per_s": (w.P + (u - 1) * (w.P - w.S)) / step, "pairs": pairs,
-                     "kernel_GBps": alg / (kms * 1e-3) / 1e9})
-        log(f"u={u}: step {step * 1e3:.3f} ms, kernel {kms:.3f} ms, {rows[-1]['kernel_GBps']:.0f} GB/s, pairs {pairs}")
-    out = {"metric": "super-resolution job streamline points/s (1.25 mm streamlines on the 0.7 mm grid)",
-           "value": rows[-1]["points_per_s"], "unit": "points/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": rows[-1]["ms_per_step"], "higher_is_better": True,
+        X, Y, Z = w.dims
+        C = torch.empty((w.N, w.M), dtype=torch.int32, device="cuda")
+        for u in ups:
+            for _ in range(args.warmup):
+                fastcod.count(w.points, w.offsets, w.roi, w.lab, w.N, w.M, scale=w.scale, upsample=u, out=C,
+                              stream=stream)
+            ks = []
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                a, b = ev.create(), ev.create()
+                fastcod.count(w.points, w.offsets, w.roi, w.lab, w.N, w.M, scale=w.scale, upsample=u, out=C,
+                              stream=stream, events=(a, b))
+                ks.append((a, b))
+            torch.cuda.synchronize()
+            step = (time.perf_counter() - t0) / args.steps
+            kms = sum(ev.elapsed_ms(a, b) for a, b in ks) / len(ks)
+            pairs = int(C.sum(dtype=torch.int64).item())
+            alg = 12 * w.P + 8 * (w.S + 1) + 8 * X * Y * Z + 4 * w.N * w.M
+            rows.append({"workload": name, "upsample": u, "S": w.S, "P": w.P, "ms_per_step": step * 1e3,
+                         "kernel_ms": kms, "points_per_s": w.P / step,
+                         "counted_points_per_s": (w.P + (u - 1) * (w.P - w.S)) / step, "pairs": pairs,
+                         "algorithmic_bytes": alg, "kernel_GBps": alg / (kms * 1e-3) / 1e9,
+                         "kernel_frac": alg / (kms * 1e-3) / 1e9 / HBM_PEAK_GBPS})
+            log(f"{name} u={u}: step {step * 1e3:.3f} ms, kernel {kms:.3f} ms, {rows[-1]['kernel_GBps']:.0f} GB/s "
+                f"({rows[-1]['kernel_frac']:.3f} of peak), pairs {pairs}")
+        del w, C
+        torch.cuda.empty_cache()
+    out = {"metric": "streamline points/s of one-million-streamline calls (1.25 mm subject; SR job on the 0.7 mm grid)",
+           "value": rows[0]["points_per_s"], "unit": "points/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": rows[0]["ms_per_step"], "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": "SR job: S=1M 1.25 mm walks x fl32(1.25/0.7) on 260x311x260, N=45.8k, M=180",
-                      "S": w.S, "P": w.P}, "rows": rows}
+           "config": {"workload": "1.25mm subject S=1M (145x174x145, N=8058, M=70); SR job: S=1M 1.25 mm walks x "
+                                  "fl32(1.25/0.7) on 260x311x260, N=45.8k, M=180"},
+           "rows": rows}
     print(json.dumps(out), flush=True)
 
 

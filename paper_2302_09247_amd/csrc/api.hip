@@ -121,13 +121,11 @@ int check_stream_args(const float *points, const int64_t *offsets, int64_t S, in
 }
 
 constexpr int kBlocksPerCU = 8;            // resident 256-thread workgroups per CU (count kernels)
-// Flat-stream point ranges per wavefront (on average), handed out dynamically.  Each range start
-// costs a few dependent loads and a pipeline fill, so smaller calls take fewer, longer ranges; from
-// kLongRangesFrom streamlines the ranges are long anyway, and more of them (tapering, largest
-// first) let the wavefronts finish together.
-constexpr int kRangesPerWave = 4;
-constexpr int kRangesPerWaveShort = 2;
-constexpr int64_t kLongRangesFrom = int64_t(1) << 21;   // also the threshold for 4-window batches
+// Flat-stream point ranges per wavefront (on average), handed out largest first by the range
+// queues, their sizes falling linearly from 1.5x to 0.5x the mean, so that the wavefronts finish
+// together.  Each range start costs a few dependent loads and a pipeline fill.
+constexpr int kRangesPerWave = 6;
+constexpr int64_t kLongRangesFrom = int64_t(1) << 21;   // 4-window batches from this many streamlines
 
 // Fallback scratch layout for a C of N rows and M labels: per workgroup an N-bit map, an M-bit map
 // and an M-entry label list, as many workgroups (<= 64) as fit `max_bytes`; false if not even one.
@@ -232,7 +230,7 @@ int make_count_plan(int64_t S, int32_t N, int32_t M, const fc::CompactVol *cv, c
                                                 4 * (size_t)cv->ncoarse_words);
     if (o.blocks_per_cu > 0 && o.blocks_per_cu < per_cu) per_cu = o.blocks_per_cu;
     cp.blocks = (int64_t)cus * per_cu;
-    cp.nparts = cp.blocks * fc::kWavesPerBlock * (long_ranges ? kRangesPerWave : kRangesPerWaveShort);
+    cp.nparts = cp.blocks * fc::kWavesPerBlock * kRangesPerWave;
     cp.first_bytes = 4 * (size_t)(cp.nparts + 1);
     // pair slices: pair_capacity entries in all (default 8 per streamline, between 2^20 and
     // 2^28), split evenly between the wavefronts; a full slice sends the rest of its
@@ -330,9 +328,8 @@ int enqueue_count(const CountPlan &cp, const CountScratch &sc, int dev, const fl
         }
         z.w64 = a.ovf.count;   // overflow count and range queues
         z.n64 = header_words;
-        // tapering ranges (largest first) end the launch evenly when ranges are long; short ones
-        // would only add per-range work
-        FC_HIP(fc::launch_partition(offsets, S, cp.nparts, sc.first, z, S >= kLongRangesFrom, cus, st));
+        // tapering ranges (largest first) end the launch evenly
+        FC_HIP(fc::launch_partition(offsets, S, cp.nparts, sc.first, z, true, cus, st));
         if (o.event_begin) FC_HIP(hipEventRecord((hipEvent_t)o.event_begin, st));
         FC_HIP(fc::launch_count_stream(a, *cv, sc.first, cp.nparts, (int)cp.blocks, cp.batch, po, st));
         if (o.event_end) FC_HIP(hipEventRecord((hipEvent_t)o.event_end, st));

@@ -974,9 +974,11 @@ __device__ __forceinline__ int64_t next_range(const Overflow &ovf, uint32_t wave
     const uint32_t nw = gridDim.x * (uint32_t)kWavesPerBlock;
     const uint32_t q = nw >= (uint32_t)kRangeQueues ? (uint32_t)kRangeQueues : (1u << (31 - __builtin_clz(nw)));
     const uint32_t c = wave & (q - 1u);
+    // (the range index is formed in lane 0 and broadcast: forming it from the broadcast count
+    // costs the surrounding loop about 20 vector registers)
     unsigned long long t = 0;
-    if (lane_id() == 0) t = atomicAdd(ovf.work + (size_t)c * kQueueWords, 1ull);
-    return (int64_t)c + (int64_t)q * uniform64((int64_t)t);
+    if (lane_id() == 0) t = (unsigned long long)c + (unsigned long long)q * atomicAdd(ovf.work + (size_t)c * kQueueWords, 1ull);
+    return uniform64((int64_t)t);
 }
 
 constexpr int kRCap = 192, kLCap = 64, kTCap = 512;   // per-wave candidate lists and set
@@ -1360,13 +1362,15 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
     close_open(vb - 1 + k0);
 }
 
+// The flat-stream kernel's body: ranges from this wavefront's queue, pair updates through its
+// append sink.
 template <bool SCALED, bool PACKED, int kBatch, bool kEnds, bool kBrick>
-__global__ void __launch_bounds__(kBlock) k_count_stream(StreamSubject sub, Overflow ovf, const int32_t *__restrict__ first,
-                                                         int64_t nparts, PairOut po) {
+__device__ __forceinline__ void count_stream_body(const StreamSubject &sub, const Overflow &ovf,
+                                                  const int32_t *__restrict__ first, int64_t nparts, const PairOut &po) {
     __shared__ uint32_t s_set[kWavesPerBlock * kSetWords];
     __shared__ uint32_t s_pend[kWavesPerBlock * kWave];
     extern __shared__ uint32_t s_coarse[];   // coarse occupancy bit map, cv.ncoarse_words words
-    const int lane = lane_id(), wv = uniform32(threadIdx.x >> 6);
+    const int wv = uniform32(threadIdx.x >> 6);
     for (int k = threadIdx.x; k < sub.cv.ncoarse_words; k += blockDim.x) s_coarse[k] = sub.cv.coarse[k];
     __syncthreads();
     StreamSet set;
@@ -1384,6 +1388,21 @@ __global__ void __launch_bounds__(kBlock) k_count_stream(StreamSubject sub, Over
         stream_range<SCALED, PACKED ? 1 : 0, kBatch, kEnds, 1, kBrick>(sub, s_coarse, s0, s1, 0, ovf, set, sink);
     }
     sink.drain(po, wave);
+}
+
+// Two-window batches (the short-call schedule) need few vector registers; with at most 80 scalar
+// registers a SIMD holds 8 of these wavefronts.  (Each wavefront's scalar allocation is its count
+// rounded up to 16, plus 16 more: 800 / (96 + 16) = 7 wavefronts at 81..96 registers, 6 above that.)
+template <bool SCALED, bool PACKED, bool kEnds, bool kBrick>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_num_sgpr(80)))
+k_count_stream2(StreamSubject sub, Overflow ovf, const int32_t *__restrict__ first, int64_t nparts, PairOut po) {
+    count_stream_body<SCALED, PACKED, 2, kEnds, kBrick>(sub, ovf, first, nparts, po);
+}
+
+template <bool SCALED, bool PACKED, bool kEnds, bool kBrick>
+__global__ void __launch_bounds__(kBlock)
+k_count_stream4(StreamSubject sub, Overflow ovf, const int32_t *__restrict__ first, int64_t nparts, PairOut po) {
+    count_stream_body<SCALED, PACKED, 4, kEnds, kBrick>(sub, ovf, first, nparts, po);
 }
 
 // Upsampled pass-through (up = 2 .. kUp): the scale is always applied (multiplying by 1.0f is
@@ -1462,9 +1481,10 @@ __global__ void __launch_bounds__(kBlock) k_count_batched(const StreamSubject *_
 
 template <bool SCALED, bool PACKED, int B, bool E>
 static int blocks_per_cu_of(size_t dyn) {
+    const void *fn = B == 2 ? reinterpret_cast<const void *>(&k_count_stream2<SCALED, PACKED, E, true>)
+                            : reinterpret_cast<const void *>(&k_count_stream4<SCALED, PACKED, E, true>);
     int n = 0;
-    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &n, reinterpret_cast<const void *>(&k_count_stream<SCALED, PACKED, B, E, true>), kBlock, dyn);
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, kBlock, dyn);
     return (e == hipSuccess && n > 0) ? n : 4;
 }
 
@@ -1511,10 +1531,16 @@ static void launch_stream_bk(const CountArgs &a, const CompactVol &cv, const int
     const bool scaled = a.scale != 1.0f;
     const size_t dyn = 4 * (size_t)cv.ncoarse_words;
     const StreamSubject sub = stream_subject(a, cv);
-    if (scaled && cv.packed) k_count_stream<true, true, B, E, K><<<blocks, kBlock, dyn, st>>>(sub, a.ovf, first, nparts, po);
-    else if (scaled) k_count_stream<true, false, B, E, K><<<blocks, kBlock, dyn, st>>>(sub, a.ovf, first, nparts, po);
-    else if (cv.packed) k_count_stream<false, true, B, E, K><<<blocks, kBlock, dyn, st>>>(sub, a.ovf, first, nparts, po);
-    else k_count_stream<false, false, B, E, K><<<blocks, kBlock, dyn, st>>>(sub, a.ovf, first, nparts, po);
+#define FC_LAUNCH_STREAM(S_, P_)                                                                               \
+    do {                                                                                                       \
+        if (B == 2) k_count_stream2<S_, P_, E, K><<<blocks, kBlock, dyn, st>>>(sub, a.ovf, first, nparts, po); \
+        else k_count_stream4<S_, P_, E, K><<<blocks, kBlock, dyn, st>>>(sub, a.ovf, first, nparts, po);       \
+    } while (0)
+    if (scaled && cv.packed) FC_LAUNCH_STREAM(true, true);
+    else if (scaled) FC_LAUNCH_STREAM(true, false);
+    else if (cv.packed) FC_LAUNCH_STREAM(false, true);
+    else FC_LAUNCH_STREAM(false, false);
+#undef FC_LAUNCH_STREAM
 }
 
 // the super-brick coarse map (csx 4, csyz 3) has its own instantiations
