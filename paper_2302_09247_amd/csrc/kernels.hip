@@ -2429,7 +2429,9 @@ template <int kBatch>
 __global__ void __launch_bounds__(kBlock) k_probe_stream(const float *__restrict__ pts, int64_t P, int64_t nwaves,
                                                          uint32_t *__restrict__ sink) {
     const int lane = lane_id();
-    const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    // (the wave index through readfirstlane: a range derived from threadIdx would make the buffer
+    // resource divergent and put every load in a loop over lanes)
+    const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + uniform32((int)(threadIdx.x >> 6));
     const int64_t per = (P + nwaves - 1) / nwaves;
     const int64_t p0 = min(P, wave * per), p1 = min(P, p0 + per);
     const uint32_t L = (uint32_t)(p1 - p0);
@@ -2466,8 +2468,10 @@ __global__ void __launch_bounds__(kBlock) k_probe_atomics(int32_t *__restrict__ 
 
 // The counting kernel's per-point lookups without its per-streamline work: the point stream of
 // k_probe_stream, voxelisation, the coarse test in LDS, the (word, rank base) gather and, for
-// occupied voxels, the code gather, folded like the stream probe.  No de-duplication, no pair
-// updates: the stream-plus-lookup ceiling of the flat-stream kernel.
+// occupied voxels, the code gather, in the counting kernel's software pipeline (each iteration
+// issues batch k's code gathers, batch k+1's pair gathers and batch k+2's points, then decodes
+// batch k).  The decoded rows and labels are folded like the stream probe.  No de-duplication,
+// no pair updates: the stream-plus-lookup ceiling of the flat-stream kernel.
 template <int kBatch, bool kBrick>
 __global__ void __launch_bounds__(kBlock) k_probe_lookup(StreamSubject sub, int64_t P, int64_t nwaves,
                                                          uint32_t *__restrict__ sink) {
@@ -2476,50 +2480,99 @@ __global__ void __launch_bounds__(kBlock) k_probe_lookup(StreamSubject sub, int6
     for (int k = threadIdx.x; k < cv.ncoarse_words; k += blockDim.x) s_coarse[k] = cv.coarse[k];
     __syncthreads();
     const int lane = lane_id();
-    const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + uniform32((int)(threadIdx.x >> 6));
     const int64_t per = (P + nwaves - 1) / nwaves;
     const int64_t p0 = min(P, wave * per), p1 = min(P, p0 + per);
     const uint32_t L = (uint32_t)(p1 - p0);
     const __amdgpu_buffer_rsrc_t rp = make_rsrc(sub.pts + 3 * p0, 12ull * L);
     const __amdgpu_buffer_rsrc_t rvol = make_rsrc(cv.mb, cv.span);
     const uint32_t lane12 = 12u * (uint32_t)lane;
-    const uint32_t bX = fbits(sub.g.Xf), bY = fbits(sub.g.Yf), bZ = fbits(sub.g.Zf);
+    uint32_t bX = fbits(sub.g.Xf), bY = fbits(sub.g.Yf), bZ = fbits(sub.g.Zf);
+    asm volatile("" : "+v"(bX), "+v"(bY), "+v"(bZ));
     const uint32_t SBX = (uint32_t)cv.SBX, SBXY = (uint32_t)cv.SBXY;
     const uint32_t csx = (uint32_t)cv.csx, csyz = (uint32_t)cv.csyz, CBX = (uint32_t)cv.CBX, CBXY = (uint32_t)cv.CBXY;
     const int codes_off = uniform32((int)cv.codes_off);
     constexpr uint32_t kOutOfRange = 0xFFFFFFF8u;
     const uint32_t code_oob = kOutOfRange - (uint32_t)codes_off;
-    uint32_t acc = 0u;
-    for (uint32_t w0 = 0; w0 < L; w0 += kBatch * kWave) {
-        uint32_t addr[kBatch], bix[kBatch];
+    constexpr uint32_t BW = kWave * kBatch;
+    float ax[kBatch], ay[kBatch], az[kBatch];
+    auto load_batch = [&](uint32_t w) {
 #pragma unroll
         for (int b = 0; b < kBatch; ++b) {
-            const auto v = __builtin_amdgcn_raw_buffer_load_b96(rp, lane12, 12u * w0 + 768u * b, kAuxStream);
-            const float tx = __fadd_rn(__fmul_rn(__uint_as_float(v[0]), sub.scale), 0.5f);
-            const float ty = __fadd_rn(__fmul_rn(__uint_as_float(v[1]), sub.scale), 0.5f);
-            const float tz = __fadd_rn(__fmul_rn(__uint_as_float(v[2]), sub.scale), 0.5f);
-            const bool ok = (w0 + b * kWave + (uint32_t)lane < L) & (fbits(tx) < bX) & (fbits(ty) < bY) & (fbits(tz) < bZ);
+            const auto v = __builtin_amdgcn_raw_buffer_load_b96(rp, lane12, 12u * w + 768u * b, kAuxStream);
+            ax[b] = __uint_as_float(v[0]);
+            ay[b] = __uint_as_float(v[1]);
+            az[b] = __uint_as_float(v[2]);
+        }
+    };
+    auto lookup = [&](uint32_t w0, uint32_t (&addr)[kBatch], uint32_t (&bix)[kBatch]) {
+        const uint32_t left = w0 < L ? L - w0 : 0u;
+        const int rem = left > BW ? (int)BW : (int)left;
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+            const float tx = __fadd_rn(__fmul_rn(ax[b], sub.scale), 0.5f);
+            const float ty = __fadd_rn(__fmul_rn(ay[b], sub.scale), 0.5f);
+            const float tz = __fadd_rn(__fmul_rn(az[b], sub.scale), 0.5f);
+            const bool ok = (int)(lane + b * kWave < rem) & (int)(fbits(tx) < bX) & (int)(fbits(ty) < bY) &
+                            (int)(fbits(tz) < bZ);
             const uint32_t ix = (uint32_t)(int)tx, iy = (uint32_t)(int)ty, iz = (uint32_t)(int)tz;
-            const uint32_t sb = __umul24(iz >> 3, SBXY) + __umul24(iy >> 3, SBX) + (ix >> 4);
+            uint32_t sb = __umul24(iz >> 3, SBXY) + __umul24(iy >> 3, SBX) + (ix >> 4);
+            asm("" : "+v"(sb));
             const uint32_t cb = kBrick ? sb : __umul24(iz >> csyz, CBXY) + __umul24(iy >> csyz, CBX) + (ix >> csx);
             const uint32_t cw = s_coarse[ok ? (cb >> 5) : 0u];
-            const bool hit = ok & (__builtin_amdgcn_ubfe(cw, cb, 1) != 0u);
+            const bool hit = (int)ok & (int)(__builtin_amdgcn_ubfe(cw, cb, 1) != 0u);
             addr[b] = hit ? (sb << 8) | ((iy << 2) & 0x18u) | ((iz << 5) & 0xE0u) : kOutOfRange;
             bix[b] = (ix & 15u) | ((iy & 1u) << 4);
         }
-        uint32_t mw[kBatch], base[kBatch];
+    };
+    auto gather_pairs = [&](const uint32_t (&addr)[kBatch], uint32_t (&mw)[kBatch], uint32_t (&base)[kBatch]) {
 #pragma unroll
         for (int b = 0; b < kBatch; ++b) {
             const auto e = __builtin_amdgcn_raw_buffer_load_b64(rvol, addr[b], 0, kAuxCached);
             mw[b] = e[0];
             base[b] = e[1];
         }
+    };
+    uint32_t acc = 0u;
+    uint32_t bix[kBatch], mw[kBatch], base[kBatch];
+    {
+        uint32_t addr[kBatch];
+        load_batch(0u);
+        lookup(0u, addr, bix);
+        __builtin_amdgcn_sched_barrier(0);
+        gather_pairs(addr, mw, base);
+        __builtin_amdgcn_sched_barrier(0);
+        load_batch(BW);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    for (uint32_t w0 = 0; w0 < L; w0 += BW) {
+        bool flag[kBatch];
+        uint32_t c[kBatch];
 #pragma unroll
         for (int b = 0; b < kBatch; ++b) {
-            const bool flag = __builtin_amdgcn_ubfe(mw[b], bix[b], 1) != 0u;
+            flag[b] = __builtin_amdgcn_ubfe(mw[b], bix[b], 1) != 0u;
             const uint32_t at = base[b] + __popc(__builtin_amdgcn_ubfe(mw[b], 0, bix[b]));
-            const uint32_t off = flag ? (cv.packed ? at << 2 : at << 3) : code_oob;
-            acc ^= __builtin_amdgcn_raw_buffer_load_b32(rvol, off, codes_off, kAuxCached);
+            const uint32_t off = flag[b] ? (cv.packed ? at << 2 : at << 3) : code_oob;
+            c[b] = __builtin_amdgcn_raw_buffer_load_b32(rvol, off, codes_off, kAuxCached);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        uint32_t bix2[kBatch], mw2[kBatch], base2[kBatch];
+        {
+            uint32_t addr[kBatch];
+            lookup(w0 + BW, addr, bix2);
+            __builtin_amdgcn_sched_barrier(0);
+            gather_pairs(addr, mw2, base2);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        load_batch(w0 + 2 * BW);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+            const uint32_t rv = c[b] & cv.rmask, mv = c[b] >> cv.rbits;
+            acc += flag[b] ? (rv ^ (mv << 3)) : 0u;
+            bix[b] = bix2[b];
+            mw[b] = mw2[b];
+            base[b] = base2[b];
         }
     }
     if (acc == kProbeMagic) sink[0] = acc;
