@@ -84,7 +84,7 @@ typedef struct fastcod_opts {
     void *event_begin;  /* optional hipEvent_t, recorded on `stream` just before the counting kernel */
     void *event_end;    /* optional hipEvent_t, recorded on `stream` just after it                  */
     int32_t batch;      /* flat-stream schedule: 64-point windows per pipelined batch, 2 or 4; 0 = 4 for
-                           n_streamlines >= 2^21 (long ranges per wavefront), else 2                   */
+                           n_streamlines >= 2^21 (ranges long enough to fill the deeper pipeline), else 2 */
     int32_t blocks_per_cu; /* flat-stream schedule: resident workgroups per CU, 0 = occupancy limit */
     int32_t mode;       /* FASTCOD_MODE_*; the batched and served forms count FASTCOD_MODE_PASSTHROUGH */
     int64_t pair_capacity; /* flat-stream path: workspace entries (4 bytes each, held twice) for the   */

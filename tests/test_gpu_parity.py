@@ -311,7 +311,7 @@ def test_giant_streamline_range(fc):
 
 def test_many_short_streamlines(fc):
     # more than 2^21 streamlines, of 1 to 12 points or empty: the schedule of large calls (4-window
-    # batches, 4 tapering ranges per wavefront, largest first) over ranges of a few hundred points;
+    # batches; 6 tapering ranges per wavefront, largest first) over ranges of a few hundred points;
     # on a volume where short walks reach both ROI voxels and labels
     vols = synth.volumes_interleaved64()
     g = torch.Generator(device="cuda").manual_seed(31)
@@ -349,9 +349,9 @@ def test_many_short_streamlines(fc):
 
 
 def test_schedule_threshold(fc):
-    # exactly 2^21 streamlines (the smallest call on the large-call schedule: 4-window batches and
-    # 4 tapering ranges per wavefront) and the same input less its last streamline (2^21 - 1: the
-    # short-call schedule, 2-window batches and 2 even ranges per wavefront)
+    # exactly 2^21 streamlines (the smallest call counted with 4-window batches) and the same input
+    # less its last streamline (2^21 - 1: 2-window batches); both take 6 tapering ranges per
+    # wavefront
     vols = synth.volumes_interleaved64()
     g = torch.Generator(device="cuda").manual_seed(47)
     S = 1 << 21
