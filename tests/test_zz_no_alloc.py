@@ -87,3 +87,24 @@ def test_noalloc_rejects_too_many_streamlines(fc):
     C = torch.zeros((w.N, w.M), dtype=torch.int32, device="cuda")
     assert _noalloc(fc, vol, w.points, off, C) == fc.EINVAL
     vol.close()
+
+
+def test_noalloc_degenerate_inputs(fc):
+    # no streamlines, and only empty streamlines: C is zeroed (and left alone when accumulating)
+    w = synth.make_tiny64(seed=5, S=500, device="cuda")
+    vol = fc.Volume(w.roi, w.lab, w.N, w.M)
+    # (no points at all; the library takes a non-NULL point pointer whenever there are streamlines)
+    pts = torch.zeros((1, 3), dtype=torch.float32, device="cuda")
+    for n_off in (1, 9):
+        off = torch.zeros(n_off, dtype=torch.int64, device="cuda")
+        C = torch.full((w.N, w.M), -9, dtype=torch.int32, device="cuda")
+        torch.cuda.synchronize()
+        print(f"noalloc degenerate: S={n_off - 1}", flush=True)
+        assert _noalloc(fc, vol, pts, off, C) == fc.OK, fc.load().fastcod_last_error()
+        torch.cuda.synchronize()
+        assert not C.any()
+        C.fill_(3)
+        assert _noalloc(fc, vol, pts, off, C, fc.make_opts(accumulate=True)) == fc.OK, fc.load().fastcod_last_error()
+        torch.cuda.synchronize()
+        assert bool((C == 3).all())
+    vol.close()
