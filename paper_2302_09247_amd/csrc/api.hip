@@ -238,7 +238,7 @@ int make_count_plan(int64_t S, int32_t N, int32_t M, const fc::CompactVol *cv, c
     cp.nwaves = cp.blocks * fc::kWavesPerBlock;
     int64_t total = o.pair_capacity > 0 ? o.pair_capacity : std::min<int64_t>(std::max<int64_t>(8 * S, 1 << 20), 1 << 28);
     total = std::min<int64_t>(std::min<int64_t>(total, INT32_MAX), max_pairs);
-    cp.cap = cp.append ? total / cp.nwaves : 0;
+    cp.cap = cp.append ? (total / cp.nwaves) & ~int64_t(3) : 0;   // 16-byte aligned slices
     if (cp.append) {
         cp.off_hist = align256(4 * (size_t)cp.nwaves);
         cp.off_pairs = align256(cp.off_hist + 4 * (size_t)fc::pair_hist_words(cp.ntiles));

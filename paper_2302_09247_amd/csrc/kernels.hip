@@ -237,32 +237,38 @@ struct BufferedSink {
     }
 };
 
-// C updates appended, 64 at a time, to this wavefront's slice of a pair buffer (one coalesced
-// store), for a later histogram pass.  A cached store is acknowledged once the cache takes it,
-// whereas an atomic must first fetch its line of C, and on this architecture every later vector
-// memory wait also waits for it (a non-temporal store measured 1.5% slower for the same reason).
-// Once the slice is full, updates go to C as atomics.
+// C updates appended to this wavefront's slice of a pair buffer for a later histogram pass,
+// kSinkCap at a time: 16 bytes per lane, one store instruction per kSinkCap updates.  On this
+// architecture every later vector-memory wait also waits for older stores, so fewer stores stall
+// the stream less (a cached store is acknowledged once the cache takes it; an atomic must first
+// fetch its line of C).  Once the slice is full, updates go to C as atomics.
+constexpr int kSinkCap = 4 * kWave;
 struct AppendSink {
-    uint32_t *buf;   // [kWave] LDS
+    uint32_t *buf;   // [kSinkCap] LDS, 16-byte aligned
     int n;           // pending entries (wave-uniform)
-    uint32_t *out;   // next free entry of this wavefront's slice
+    uint32_t *out;   // next free entry of this wavefront's slice (16-byte aligned)
     uint32_t room;   // free entries left in the slice
     int32_t *C;
     __device__ void init(uint32_t *b, int32_t *c, const PairOut &po, uint32_t wave) {
         buf = b;
         n = 0;
         C = c;
-        out = po.pairs + (size_t)wave * po.cap;
+        out = po.pairs + (size_t)wave * po.cap;   // (po.cap is a multiple of 4)
         room = po.cap;
     }
-    __device__ void emit(int cnt) {   // the first cnt (<= 64) entries of buf
+    __device__ void emit(int cnt) {   // the first cnt (<= kSinkCap) entries of buf
         const int lane = lane_id();
-        if ((uint32_t)cnt <= room) {
-            if (lane < cnt) out[lane] = buf[lane];
+        if (cnt == kSinkCap && (uint32_t)cnt <= room) {
+            const uint4 v = reinterpret_cast<const uint4 *>(buf)[lane];
+            reinterpret_cast<uint4 *>(out)[lane] = v;
+            out += kSinkCap;
+            room -= (uint32_t)kSinkCap;
+        } else if ((uint32_t)cnt <= room) {
+            for (int k = lane; k < cnt; k += kWave) out[k] = buf[k];
             out += cnt;
             room -= (uint32_t)cnt;
-        } else if (lane < cnt) {
-            atomicAdd(C + buf[lane], 1);
+        } else {
+            for (int k = lane; k < cnt; k += kWave) atomicAdd(C + buf[k], 1);
         }
     }
     __device__ void push(bool valid, uint32_t idx) { push_lanes(__ballot(valid), idx); }
@@ -270,12 +276,12 @@ struct AppendSink {
         if (!vm) return;
         const bool valid = in_mask(vm);
         const int pos = n + mbcnt(vm);
-        if (valid && pos < kWave) buf[pos] = idx;
+        if (valid && pos < kSinkCap) buf[pos] = idx;
         const int cnt = __popcll(vm);
-        if (n + cnt >= kWave) {
-            emit(kWave);
-            if (valid && pos >= kWave) buf[pos - kWave] = idx;
-            n = n + cnt - kWave;
+        if (n + cnt >= kSinkCap) {
+            emit(kSinkCap);
+            if (valid && pos >= kSinkCap) buf[pos - kSinkCap] = idx;
+            n = n + cnt - kSinkCap;
         } else {
             n += cnt;
         }
@@ -1368,7 +1374,7 @@ template <bool SCALED, bool PACKED, int kBatch, bool kEnds, bool kBrick>
 __device__ __forceinline__ void count_stream_body(const StreamSubject &sub, const Overflow &ovf,
                                                   const int32_t *__restrict__ first, int64_t nparts, const PairOut &po) {
     __shared__ uint32_t s_set[kWavesPerBlock * kSetWords];
-    __shared__ uint32_t s_pend[kWavesPerBlock * kWave];
+    __shared__ __align__(16) uint32_t s_pend[kWavesPerBlock * kSinkCap];
     extern __shared__ uint32_t s_coarse[];   // coarse occupancy bit map, cv.ncoarse_words words
     const int wv = uniform32(threadIdx.x >> 6);
     for (int k = threadIdx.x; k < sub.cv.ncoarse_words; k += blockDim.x) s_coarse[k] = sub.cv.coarse[k];
@@ -1377,7 +1383,7 @@ __device__ __forceinline__ void count_stream_body(const StreamSubject &sub, cons
     set.init(s_set + wv * kSetWords);
     const uint32_t wave = blockIdx.x * kWavesPerBlock + wv;
     AppendSink sink;
-    sink.init(s_pend + wv * kWave, sub.C, po, wave);
+    sink.init(s_pend + wv * kSinkCap, sub.C, po, wave);
     for (;;) {
         // next point range: streamlines [first[part], first[part+1])
         const int64_t part = next_range(ovf, wave);
@@ -1412,7 +1418,7 @@ __global__ void __launch_bounds__(kBlock) k_count_stream_up(StreamSubject sub, O
                                                             const int32_t *__restrict__ first, int64_t nparts, PairOut po) {
     constexpr int kB = kUp == 2 ? 2 : 1;   // kB * kUp lookups per batch, as the plain kernel's 4
     __shared__ uint32_t s_set[kWavesPerBlock * kSetWords];
-    __shared__ uint32_t s_pend[kWavesPerBlock * kWave];
+    __shared__ __align__(16) uint32_t s_pend[kWavesPerBlock * kSinkCap];
     extern __shared__ uint32_t s_coarse[];
     const int lane = lane_id(), wv = uniform32(threadIdx.x >> 6);
     for (int k = threadIdx.x; k < sub.cv.ncoarse_words; k += blockDim.x) s_coarse[k] = sub.cv.coarse[k];
@@ -1421,7 +1427,7 @@ __global__ void __launch_bounds__(kBlock) k_count_stream_up(StreamSubject sub, O
     set.init(s_set + wv * kSetWords);
     const uint32_t wave = blockIdx.x * kWavesPerBlock + wv;
     AppendSink sink;
-    sink.init(s_pend + wv * kWave, sub.C, po, wave);
+    sink.init(s_pend + wv * kSinkCap, sub.C, po, wave);
     for (;;) {
         const int64_t part = next_range(ovf, wave);
         if (part >= nparts) break;
