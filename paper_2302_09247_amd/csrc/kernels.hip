@@ -238,12 +238,14 @@ struct BufferedSink {
 };
 
 // C updates appended to this wavefront's slice of a pair buffer for a later histogram pass,
-// kSinkCap at a time: 16 bytes per lane, one store instruction per kSinkCap updates.  On this
-// architecture every later vector-memory wait also waits for older stores, so fewer stores stall
-// the stream less (a cached store is acknowledged once the cache takes it; an atomic must first
-// fetch its line of C).  Once the slice is full, updates go to C as atomics.
-constexpr int kSinkCap = 4 * kWave;
+// kSinkCap at a time: 16 bytes per lane per store instruction, one store per 256 updates.  On this
+// architecture every later vector-memory wait also waits for older stores, so fewer, fuller
+// stores stall the stream less (a cached store is acknowledged once the cache takes it; an atomic
+// must first fetch its line of C).  Once the slice is full, updates go to C as atomics.
+// (kSinkCap: 256 or 512, a multiple of 256; the LDS it takes limits the workgroups per CU.)
+template <int kSinkCap>
 struct AppendSink {
+    static_assert(kSinkCap == 4 * kWave || kSinkCap == 8 * kWave, "one or two 16-byte stores per lane");
     uint32_t *buf;   // [kSinkCap] LDS, 16-byte aligned
     int n;           // pending entries (wave-uniform)
     uint32_t *out;   // next free entry of this wavefront's slice (16-byte aligned)
@@ -260,7 +262,13 @@ struct AppendSink {
         const int lane = lane_id();
         if (cnt == kSinkCap && (uint32_t)cnt <= room) {
             const uint4 v = reinterpret_cast<const uint4 *>(buf)[lane];
-            reinterpret_cast<uint4 *>(out)[lane] = v;
+            if constexpr (kSinkCap == 8 * kWave) {
+                const uint4 v2 = reinterpret_cast<const uint4 *>(buf)[lane + kWave];
+                reinterpret_cast<uint4 *>(out)[lane] = v;
+                reinterpret_cast<uint4 *>(out)[lane + kWave] = v2;
+            } else {
+                reinterpret_cast<uint4 *>(out)[lane] = v;
+            }
             out += kSinkCap;
             room -= (uint32_t)kSinkCap;
         } else if ((uint32_t)cnt <= room) {
@@ -1373,6 +1381,9 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
 template <bool SCALED, bool PACKED, int kBatch, bool kEnds, bool kBrick>
 __device__ __forceinline__ void count_stream_body(const StreamSubject &sub, const Overflow &ovf,
                                                   const int32_t *__restrict__ first, int64_t nparts, const PairOut &po) {
+    // 4-window batches run 6 wavefronts per SIMD (their scalar registers), so they can afford the
+    // LDS of 512 buffered updates; 2-window batches keep 8 per SIMD with 256
+    constexpr int kSinkCap = kBatch == 4 ? 8 * kWave : 4 * kWave;
     __shared__ uint32_t s_set[kWavesPerBlock * kSetWords];
     __shared__ __align__(16) uint32_t s_pend[kWavesPerBlock * kSinkCap];
     extern __shared__ uint32_t s_coarse[];   // coarse occupancy bit map, cv.ncoarse_words words
@@ -1382,7 +1393,7 @@ __device__ __forceinline__ void count_stream_body(const StreamSubject &sub, cons
     StreamSet set;
     set.init(s_set + wv * kSetWords);
     const uint32_t wave = blockIdx.x * kWavesPerBlock + wv;
-    AppendSink sink;
+    AppendSink<kSinkCap> sink;
     sink.init(s_pend + wv * kSinkCap, sub.C, po, wave);
     for (;;) {
         // next point range: streamlines [first[part], first[part+1])
@@ -1417,6 +1428,7 @@ template <int kUp>
 __global__ void __launch_bounds__(kBlock) k_count_stream_up(StreamSubject sub, Overflow ovf,
                                                             const int32_t *__restrict__ first, int64_t nparts, PairOut po) {
     constexpr int kB = kUp == 2 ? 2 : 1;   // kB * kUp lookups per batch, as the plain kernel's 4
+    constexpr int kSinkCap = 4 * kWave;
     __shared__ uint32_t s_set[kWavesPerBlock * kSetWords];
     __shared__ __align__(16) uint32_t s_pend[kWavesPerBlock * kSinkCap];
     extern __shared__ uint32_t s_coarse[];
@@ -1426,7 +1438,7 @@ __global__ void __launch_bounds__(kBlock) k_count_stream_up(StreamSubject sub, O
     StreamSet set;
     set.init(s_set + wv * kSetWords);
     const uint32_t wave = blockIdx.x * kWavesPerBlock + wv;
-    AppendSink sink;
+    AppendSink<kSinkCap> sink;
     sink.init(s_pend + wv * kSinkCap, sub.C, po, wave);
     for (;;) {
         const int64_t part = next_range(ovf, wave);
