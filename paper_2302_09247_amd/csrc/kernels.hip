@@ -981,6 +981,13 @@ __device__ __forceinline__ int64_t uniform64(int64_t v) {
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
+// A wave-uniform read of memory that no launch in flight writes (the end labels, filled by an
+// earlier launch), through the scalar data cache: a vector load would make the wavefront wait for
+// every gather and point load it has in flight, as vector-memory loads complete in issue order.
+__device__ __forceinline__ int32_t uniform_const_load(const int32_t *p, int64_t i) {
+    return ((const __attribute__((address_space(4))) int32_t *)p)[i];
+}
+
 // Next point range (work item) of wavefront `wave`: queue c = wave mod Q holds ranges c, c + Q,
 // c + 2Q, ..., handed out in that order by its own counter (Q: kRangeQueues, or the largest power of
 // two not above the grid's wavefronts, so that every queue has wavefronts).
@@ -1090,7 +1097,7 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
     auto close_open = [&](int64_t id) {
         if (endmode) {
             id = id < s0 ? s0 : (id >= s1 ? s1 - 1 : id);
-            set.add_end_labels(sub.ends.last[id], sub.ends.mode == 2 ? sub.ends.first[id] : -1);
+            set.add_end_labels(uniform_const_load(sub.ends.last, id), sub.ends.mode == 2 ? uniform_const_load(sub.ends.first, id) : -1);
         }
         set.close(sink, sub.si, sub.sm);
     };
