@@ -40,6 +40,18 @@ __device__ __forceinline__ int mbcnt(uint64_t m) {
 // this lane's bit of a wave-uniform mask, which the hardware takes directly as a lane predicate
 __device__ __forceinline__ bool in_mask(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
 
+// Global-memory views of pointers the compiler cannot place by itself (pointers read from a table
+// in memory rather than passed as kernel arguments).  It would access them with flat instructions,
+// which also count against the LDS wait counter: every LDS wait after one would wait for it too.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T *gview(const T *p) {
+    return (const __attribute__((address_space(1))) T *)p;
+}
+// C[k] += 1 as a device-scope atomic without return, in global memory
+__device__ __forceinline__ void add_one(int32_t *p) {
+    __hip_atomic_fetch_add((__attribute__((address_space(1))) int32_t *)p, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ uint64_t lanes_between(int lo, int hi) {  // bits [lo, hi)
     const uint64_t below_hi = hi >= 64 ? ~0ull : ((1ull << hi) - 1ull);
     return below_hi & ~((1ull << lo) - 1ull);
@@ -199,7 +211,7 @@ struct WaveSet {
 struct DirectSink {
     int32_t *C;
     __device__ void push_lanes(uint64_t vm, uint32_t idx) {   // the lanes in vm (wave-uniform)
-        if (in_mask(vm)) atomicAdd(C + idx, 1);
+        if (in_mask(vm)) add_one(C + idx);
     }
     __device__ void push(bool valid, uint32_t idx) { push_lanes(__ballot(valid), idx); }
 };
@@ -224,7 +236,7 @@ struct BufferedSink {
         if (valid && pos < kWave) buf[pos] = idx;
         const int cnt = __popcll(vm);
         if (n + cnt >= kWave) {
-            atomicAdd(C + buf[lane_id()], 1);
+            add_one(C + buf[lane_id()]);
             if (valid && pos >= kWave) buf[pos - kWave] = idx;
             n = n + cnt - kWave;
         } else {
@@ -232,7 +244,7 @@ struct BufferedSink {
         }
     }
     __device__ void drain() {
-        if (lane_id() < n) atomicAdd(C + buf[lane_id()], 1);
+        if (lane_id() < n) add_one(C + buf[lane_id()]);
         n = 0;
     }
 };
@@ -276,7 +288,7 @@ struct AppendSink {
             out += cnt;
             room -= (uint32_t)cnt;
         } else {
-            for (int k = lane; k < cnt; k += kWave) atomicAdd(C + buf[k], 1);
+            for (int k = lane; k < cnt; k += kWave) add_one(C + buf[k]);
         }
     }
     __device__ void push(bool valid, uint32_t idx) { push_lanes(__ballot(valid), idx); }
@@ -1017,7 +1029,8 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
     const int lane = lane_id();
     const CompactVol &cv = sub.cv;
     const int64_t S = sub.S;
-    const int64_t Ptot = uniform64(sub.offsets[S] > 0 ? sub.offsets[S] : 0);
+    const auto offs = gview(sub.offsets);
+    const int64_t Ptot = uniform64(offs[S] > 0 ? offs[S] : 0);
     // occupancy pairs and codes share one allocation and one resource (codes at cv.codes_off)
     const __amdgpu_buffer_rsrc_t rvol = make_rsrc(cv.mb, cv.span);
     const int codes_off = uniform32((int)cv.codes_off);
@@ -1028,15 +1041,15 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
     const uint32_t SBX = (uint32_t)cv.SBX, SBXY = (uint32_t)cv.SBXY;
     const uint32_t csx = (uint32_t)cv.csx, csyz = (uint32_t)cv.csyz, CBX = (uint32_t)cv.CBX, CBXY = (uint32_t)cv.CBXY;
     constexpr uint32_t kOutOfRange = 0xFFFFFFF8u;   // buffer offset past every resource: reads 0, no traffic
-    const int64_t P0 = uniform64(clamp64(sub.offsets[s0], 0, Ptot));
-    const int64_t P1 = uniform64(clamp64(sub.offsets[s1], P0, Ptot));
+    const int64_t P0 = uniform64(clamp64(offs[s0], 0, Ptot));
+    const int64_t P1 = uniform64(clamp64(offs[s1], P0, Ptot));
     if (P0 >= P1) return;
     if (P1 - P0 > kMaxRangePoints) {
         // positions below are 32-bit offsets from P0: a range this long (a few giant streamlines
         // make one) goes to the fallback kernel, one entry per non-empty streamline
         for (int64_t s = s0; s < s1; ++s) {
-            const int64_t b = uniform64(clamp64(sub.offsets[s], P0, P1));
-            const int64_t e = uniform64(clamp64(sub.offsets[s + 1], b, P1));
+            const int64_t b = uniform64(clamp64(offs[s], P0, P1));
+            const int64_t e = uniform64(clamp64(offs[s + 1], b, P1));
             if (e > b) push_overflow(ovf, b, subject);
         }
         return;
@@ -1057,7 +1070,7 @@ __device__ void stream_range(const StreamSubject &sub, const uint32_t *coarse, i
     uint32_t voff = 0, nxt = L;
     int k0 = 0;
     auto load_starts = [&]() {
-        voff = (vb + lane < s1) ? (uint32_t)(clamp64(sub.offsets[vb + lane], P0, P1) - P0) : L;
+        voff = (vb + lane < s1) ? (uint32_t)(clamp64(offs[vb + lane], P0, P1) - P0) : L;
         k0 = 0;
         nxt = (uint32_t)__builtin_amdgcn_readlane((int)voff, 0);
     };
@@ -1495,7 +1508,7 @@ __global__ void __launch_bounds__(kBlock) k_count_batched(const StreamSubject *_
         s1 = uniform64(clamp64(s1, s0, sub.S));
         if (s0 >= s1) continue;
         if (subject != loaded) {
-            for (int k = lane; k < sub.cv.ncoarse_words; k += kWave) coarse[k] = sub.cv.coarse[k];
+            for (int k = lane; k < sub.cv.ncoarse_words; k += kWave) coarse[k] = gview(sub.cv.coarse)[k];
             loaded = subject;
         }
         sink.C = sub.C;
