@@ -215,8 +215,8 @@ def main():
     ap.add_argument("--tune-cache", default=None)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the counting path runs on a single MI355X here "
-              "(a multi-GPU run would shard streamlines and all-reduce C; it is not part of this build).",
+        print("bench.py measures one GPU only: the counting path runs on a single MI355X "
+              "(a multi-GPU run would shard streamlines and all-reduce C; no multi-GPU path is implemented).",
               file=sys.stderr)
         sys.exit(2)
 
