@@ -62,10 +62,13 @@ struct PairOut {
 // Histogram of the appended updates into C, tile by tile in LDS.
 constexpr int kPairTileLog2 = 14;                   // 16K counters (64 KB of LDS) per tile of C
 constexpr int kMaxPairTiles = 4096;                 // up to 2^26 entries of C take this path
-// workgroups of the histogram and scatter passes: fewer for many tiles (each keeps ntiles offsets)
+// Workgroups (1024 threads) of the tile-count and scatter passes: 512, two per CU of a 256-CU
+// device, all resident at once.  Each keeps ntiles offsets; every tile cursor takes one atomic
+// per workgroup, so more workgroups mean a longer queue of atomics on each cursor (1024 measured
+// slower, 256 leave too few loads in flight).
 inline int pair_hist_blocks(int64_t ntiles) {
-    const int64_t b = (int64_t(1) << 22) / (ntiles > 0 ? ntiles : 1);
-    return (int)(b < 64 ? 64 : (b > 1024 ? 1024 : b));
+    (void)ntiles;
+    return 512;
 }
 
 struct Overflow {

@@ -1452,7 +1452,7 @@ __global__ void __launch_bounds__(kBlock) k_count_stream_up(StreamSubject sub, O
     __shared__ uint32_t s_set[kWavesPerBlock * kSetWords];
     __shared__ __align__(16) uint32_t s_pend[kWavesPerBlock * kSinkCap];
     extern __shared__ uint32_t s_coarse[];
-    const int lane = lane_id(), wv = uniform32(threadIdx.x >> 6);
+    const int wv = uniform32(threadIdx.x >> 6);
     for (int k = threadIdx.x; k < sub.cv.ncoarse_words; k += blockDim.x) s_coarse[k] = sub.cv.coarse[k];
     __syncthreads();
     StreamSet set;
@@ -2136,13 +2136,18 @@ __global__ void __launch_bounds__(256) k_transpose(const int32_t *__restrict__ C
     __shared__ int32_t tile[32][33];
     const int i0 = blockIdx.x * 32, m0 = blockIdx.y * 32;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
-    for (int k = ty; k < 32; k += 8) {
-        const int m = m0 + k, i = i0 + tx;
-        tile[k][tx] = (m < M && i < N) ? CT[(int64_t)m * N + i] : 0;
+    int32_t v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int m = m0 + ty + 8 * q, i = i0 + tx;
+        v[q] = (m < M && i < N) ? CT[(int64_t)m * N + i] : 0;
     }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) tile[ty + 8 * q][tx] = v[q];
     __syncthreads();
-    for (int k = ty; k < 32; k += 8) {
-        const int i = i0 + k, m = m0 + tx;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int k = ty + 8 * q, i = i0 + k, m = m0 + tx;
         if (i < N && m < M) {
             int32_t *dst = C + (int64_t)i * M + m;
             *dst = ACC ? *dst + tile[tx][k] : tile[tx][k];
@@ -2177,16 +2182,19 @@ __global__ void __launch_bounds__(256) k_transpose_many(const TransposeJob *__re
         const int64_t local = t - j.first_tile;
         const int64_t tn = (j.N + T - 1) / T;
         const int i0 = (int)(local % tn) * T, m0 = (int)(local / tn) * T;
+        int32_t v[T / R];   // (a fixed trip count, so that all the loads issue before the LDS stores)
 #pragma unroll
-        for (int k = ty; k < T; k += R) {
-            const int m = m0 + k, i = i0 + tx;
-            tile[k][tx] = (m < j.M && i < j.N) ? j.CT[(int64_t)m * j.N + i] : 0;
+        for (int q = 0; q < T / R; ++q) {
+            const int m = m0 + ty + q * R, i = i0 + tx;
+            v[q] = (m < j.M && i < j.N) ? j.CT[(int64_t)m * j.N + i] : 0;
         }
+#pragma unroll
+        for (int q = 0; q < T / R; ++q) tile[ty + q * R][tx] = v[q];
         __syncthreads();
 #pragma unroll
-        for (int k = ty; k < T; k += R) {
-            const int i = i0 + k, m = m0 + tx;
-            if (i < j.N && m < j.M) j.C[(int64_t)i * j.M + m] = tile[tx][k];
+        for (int q = 0; q < T / R; ++q) {
+            const int i = i0 + ty + q * R, m = m0 + tx;
+            if (i < j.N && m < j.M) j.C[(int64_t)i * j.M + m] = tile[tx][ty + q * R];
         }
         __syncthreads();   // the tile is rewritten by the next iteration
     }
