@@ -91,7 +91,9 @@ typedef struct fastcod_opts {
                         /* C updates it appends and later adds into C tile by tile; 0 = 8 per       */
                         /* streamline, clamped to [2^20, 2^28]; values above INT32_MAX are clamped.  */
                         /* Updates that find their wavefront's share full go to C as atomics: the   */
-                        /* result is the same, only slower.  Must be >= 0.                           */
+                        /* result is the same, only slower.  With 0, calls of fewer than 2^17       */
+                        /* streamlines on a C of at most 2^20 entries use no pair buffer and add    */
+                        /* every update to C as an atomic.  Must be >= 0.                            */
 } fastcod_opts;
 
 /* Default options: {1.0f, 1, 0, FASTCOD_VARIANT_AUTO, NULL, NULL, 0, 0, FASTCOD_MODE_PASSTHROUGH, 0}. */

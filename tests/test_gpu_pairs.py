@@ -4,7 +4,9 @@ The flat-stream kernel appends its C updates to per-wavefront slices of `pair_ca
 and adds their histogram into C tile by tile; a full slice sends the rest of its wavefront's
 updates to C as atomics.  Capacities from 1 entry (every wavefront overflows at once) to the
 default must give the same C, alone, with accumulate, in every mode and with upsampling; a C of
-more than 2^26 entries takes the transposed-atomics path instead.
+more than 2^26 entries takes the transposed-atomics path instead.  With the default capacity (0),
+calls of fewer than 2^17 streamlines on a C of at most 2^20 entries use no pair buffer at all (every
+update an atomic into C); an explicit capacity keeps it.
 """
 import sys
 
@@ -90,6 +92,17 @@ def test_125mm_small_slices(fc):
     for cap in (1 << 20, 0):
         np.testing.assert_array_equal(_run(fc, w, pair_capacity=cap), exp, err_msg=f"capacity {cap}")
     _say(f"[pairs] 1.25mm bit-exact ({int(exp.sum())} updates)")
+
+
+@pytest.mark.parametrize("S", [(1 << 17) - 1, 1 << 17])
+def test_direct_atomics_threshold(fc, S):
+    # either side of the streamline count below which a small C skips the pair buffer
+    w = synth.make_tiny64(seed=17, S=S)
+    exp = oracle.count(w.points, w.offsets, w.roi, w.lab, w.N, w.M)
+    g = w.to("cuda")
+    _say(f"[pairs] tiny64 S={S} P={w.P}")
+    for cap in (0, 4 * S):
+        np.testing.assert_array_equal(_run(fc, g, pair_capacity=cap), exp, err_msg=f"capacity {cap}")
 
 
 def test_large_C_takes_the_atomic_path(fc):
