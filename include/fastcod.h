@@ -237,7 +237,9 @@ int fastcod_count_batched(const fastcod_subject *subjects, int32_t n, void *stre
  * room, and rebuilt from the server's host copy when needed again.  A request that could never
  * fit is refused at submission with FASTCOD_ENOMEM.  Admitted requests are counted by one launch
  * at a time that takes the next streamline range of every active request (about tick_points
- * points in all), so a new request starts counting at the next launch.  Host points are uploaded
+ * points in all): about chunk_points points of each (an equal part of the launch when more are
+ * active than that allows) and the rest for the oldest requests first.  A new request thus starts
+ * counting at the next launch, and the oldest ones finish first.  Host points are uploaded
  * in pieces of about chunk_points points that overlap the counting.  A scheduler thread owned by
  * the server issues all device work on its own streams; the calls below only touch host state
  * and may come from any thread.

@@ -8,8 +8,10 @@
 //     recently used first to make room;
 //   - uploads of host points in pieces of about chunk_points points, a bounded number in flight;
 //   - continuous batching: every counting launch ("tick") takes the next ready streamline range of
-//     every active request (a fair share of tick_points each), so a new request joins the very
-//     next launch instead of waiting for the ones before it;
+//     every active request, so a new request joins the very next launch instead of waiting for the
+//     ones before it.  Each request gets at least chunk_points points of a tick (an equal part of it
+//     when that is less); the rest of tick_points goes to the oldest requests first, so that they
+//     finish, and their results leave over PCIe, while the others are still counting;
 //   - finalisation (C to its destination) once every streamline of a request has been counted,
 //     completion, cancellation and failure.
 // Each count of a streamline range adds exact integers into the request's C, so C does not
@@ -645,19 +647,24 @@ class Core {
 
     bool issue_tick() {
         if ((int32_t)ticks_.size() >= cfg_.ticks_in_flight) return false;
-        std::vector<Request *> ready;
-        for (size_t k = 0; k < active_.size(); ++k) {
-            Request *r = active_[(tick_rr_ + k) % std::max<size_t>(1, active_.size())];
+        std::vector<Request *> ready;   // in admission order: oldest first
+        for (Request *r : active_)
             if (!r->cancel && r->state == State::Active && r->next_s < r->ready_s) ready.push_back(r);
-        }
         if (ready.empty()) return false;
-        ++tick_rr_;
-        const int64_t share = std::max<int64_t>(cfg_.chunk_points, cfg_.tick_points / (int64_t)ready.size());
+        // a floor share for every ready request; the spare points of the tick to the oldest first
+        const int64_t n = (int64_t)ready.size();
+        const int64_t floor_pts = std::min<int64_t>(cfg_.chunk_points, std::max<int64_t>(1, cfg_.tick_points / n));
+        int64_t spare = cfg_.tick_points;
+        for (Request *r : ready) spare -= std::min<int64_t>(floor_pts, r->offsets[r->ready_s] - r->offsets[r->next_s]);
         int64_t pts = 0, sl = 0;
         std::vector<Chunk> chunks;
         for (Request *r : ready) {
             if (pts >= cfg_.tick_points || sl >= cfg_.tick_streamlines) break;
-            const int64_t want = std::min<int64_t>(share, cfg_.tick_points - pts);
+            const int64_t left = r->offsets[r->ready_s] - r->offsets[r->next_s];
+            const int64_t base = std::min<int64_t>(floor_pts, left);
+            const int64_t extra = std::min<int64_t>(std::max<int64_t>(spare, 0), left - base);
+            spare -= extra;
+            const int64_t want = std::min<int64_t>(base + extra, cfg_.tick_points - pts);
             const int64_t lim = std::min<int64_t>(r->ready_s, r->next_s + (cfg_.tick_streamlines - sl));
             const int64_t s1 = range_end(*r, r->next_s, want, lim);
             chunks.push_back(Chunk{r, vols_[r->vol].get(), r->next_s, s1});
@@ -708,7 +715,7 @@ class Core {
     uint64_t tick_seq_ = 0, done_tick_ = 0, next_id_ = 0, use_clock_ = 0;
     uint64_t builds_ = 0, evictions_ = 0, completed_ = 0;
     int32_t uploads_in_flight_ = 0;
-    size_t upload_rr_ = 0, tick_rr_ = 0;
+    size_t upload_rr_ = 0;
     int failed_ = 0;
     bool stopping_ = false;
     std::string fail_msg_;

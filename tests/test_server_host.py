@@ -1,8 +1,9 @@
 """Host tests of the request server's scheduling core (csrc/server_core.h), run through a simulated
 executor (tests/native/server_sim.cpp, built here with g++): admission against the memory budget,
 first-come-first-served order, LRU eviction of idle volumes, chunk coverage, continuous batching,
-fair shares, cancellation, failure, and the threaded wrapper's wait/timeout.  No GPU, no counting:
-the counting itself is covered by the GPU tests of the served form."""
+tick shares (a floor each, the rest oldest first), cancellation, failure, and the threaded
+wrapper's wait/timeout.  No GPU, no counting: the counting itself is covered by the GPU tests of the
+served form."""
 import ctypes
 import os
 import subprocess
@@ -257,7 +258,8 @@ def test_new_request_joins_next_launch(core):
     assert c.state(a)[:2] == (DONE, OK) and c.state(b)[:2] == (DONE, OK)
 
 
-def test_fair_share_between_active_requests(core):
+def test_tick_shares_floor_then_oldest_first(core):
+    # every ready request gets chunk_points of a tick; the rest of the tick goes to the oldest
     c = core(tick_points=1000, chunk_points=100, ticks_in_flight=1)
     _, v = c.add_volume()
     _, a = c.submit(v, [10] * 5000, flags=DEVICE_POINTS)
@@ -265,12 +267,35 @@ def test_fair_share_between_active_requests(core):
     for _ in range(12):
         c.step(complete=-1)
     ch = c.chunks()
-    for t in np.unique(ch[:, 0])[1:6]:
+    both = 0
+    for t in np.unique(ch[:, 0]):
         sel = ch[ch[:, 0] == t]
         if len(sel) == 2:
-            pts = (sel[:, 3] - sel[:, 2]) * 10
-            assert np.all(pts >= 500) and pts.sum() <= 1000 + 10
+            both += 1
+            pts = {int(r): int(s1 - s0) * 10 for _, r, s0, s1 in sel}
+            assert pts[a] == 900 and pts[b] == 100
+    assert both >= 3
     c.run()
+    ch = c.chunks()
+    last = {r: int(ch[ch[:, 1] == r][:, 0].max()) for r in (a, b)}
+    assert last[a] < last[b]   # the older request finished first
+    assert c.state(a)[:2] == (DONE, OK) and c.state(b)[:2] == (DONE, OK)
+
+
+def test_tick_shares_many_requests(core):
+    # more ready requests than tick_points / chunk_points: equal parts of the tick, nobody left out
+    c = core(tick_points=1000, chunk_points=100, ticks_in_flight=1)
+    _, v = c.add_volume()
+    ids = [c.submit(v, [1] * 3000, flags=DEVICE_POINTS)[1] for _ in range(20)]
+    for _ in range(6):
+        c.step(complete=-1)
+    ch = c.chunks()
+    t = int(ch[:, 0].max())
+    sel = ch[ch[:, 0] == t]
+    assert sorted(int(r) for r in sel[:, 1]) == sorted(ids)
+    assert np.all((sel[:, 3] - sel[:, 2]) == 50)
+    c.run()
+    assert all(c.state(r)[:2] == (DONE, OK) for r in ids)
 
 
 def test_tick_streamline_cap(core):
