@@ -250,7 +250,8 @@ typedef struct fastcod_server_config {
     uint64_t memory_budget;  /* device bytes for volumes and requests; 0 = 80% of the free memory     */
     int64_t tick_points;     /* points per counting launch over all active requests; 0 = 2^27         */
     int64_t chunk_points;    /* host upload piece and smallest per-request share of a launch; 0 = 2^20 */
-    int32_t max_active;      /* requests admitted at once, 1..1024; 0 = 64                             */
+    int32_t max_active;      /* admitted requests still counting, 1..1024; 0 = 64 (one whose result   */
+                             /* is being copied out no longer counts)                                 */
     int32_t reserved;        /* must be 0                                                              */
 } fastcod_server_config;
 

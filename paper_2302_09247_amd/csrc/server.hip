@@ -109,15 +109,18 @@ class HipExecutor final : public fcs::Executor {
         return FASTCOD_OK;
     }
 
+    // On the copy stream: the offsets (8 MB for a million streamlines) cross PCIe while the compute
+    // stream keeps counting the requests before this one; the core counts this request only once
+    // the token has completed.
     int begin_request(const fcs::Request &r, fcs::Token *t) override {
         if (r.ready && (r.ready > toks_.size() ||
-                        hip(hipStreamWaitEvent(comp_, toks_[r.ready - 1].ev, 0), "hipStreamWaitEvent")))
+                        hip(hipStreamWaitEvent(copy_, toks_[r.ready - 1].ev, 0), "hipStreamWaitEvent")))
             return r.ready > toks_.size() ? err(FASTCOD_EINVAL, "unknown token") : FASTCOD_EHIP;
-        if (hip(fc::launch_fill_i32(device_C(r), (int64_t)r.N * r.M, 0, cus_, comp_), "zero fill") ||
-            hip(hipMemcpyAsync(base_ + r.off_offsets, r.offsets, 8 * (size_t)(r.S + 1), hipMemcpyHostToDevice, comp_),
+        if (hip(fc::launch_fill_i32(device_C(r), (int64_t)r.N * r.M, 0, cus_, copy_), "zero fill") ||
+            hip(hipMemcpyAsync(base_ + r.off_offsets, r.offsets, 8 * (size_t)(r.S + 1), hipMemcpyHostToDevice, copy_),
                 "offsets upload"))
             return FASTCOD_EHIP;
-        return record(comp_, t);
+        return record(copy_, t);
     }
 
     int upload(const fcs::Request &r, int64_t s0, int64_t s1, fcs::Token *t) override {

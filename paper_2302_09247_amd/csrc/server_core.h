@@ -127,7 +127,7 @@ struct Config {
     int64_t tick_points = int64_t(1) << 27;
     int64_t tick_streamlines = 1 << 20;
     int64_t chunk_points = 1 << 20;   // points per host upload piece, and the smallest share of a tick
-    int32_t max_active = 64;          // requests admitted at once
+    int32_t max_active = 64;          // admitted requests still counting, at most
     int32_t upload_window = 8;        // upload pieces in flight
     int32_t ticks_in_flight = 2;      // counting launches queued on the device at once
 };
@@ -195,8 +195,8 @@ class Executor {
         *t = 0;
         return FASTCOD_OK;
     }
-    // zero the request's C and upload its offsets (ordered before every tick that uses it, and
-    // after r.ready)
+    // zero the request's C and upload its offsets (after r.ready); the request joins ticks only
+    // once the token has completed
     virtual int begin_request(const Request &r, Token *t) = 0;
     // host points of streamlines [s0, s1) to the request's device copy
     virtual int upload(const Request &r, int64_t s0, int64_t s1, Token *t) = 0;
@@ -581,9 +581,16 @@ class Core {
         }
     }
 
+    // admitted requests still counting: those whose result is on its way out make room for the next
+    int32_t counting() const {
+        int32_t n = 0;
+        for (const Request *r : active_) n += r->state == State::Active ? 1 : 0;
+        return n;
+    }
+
     bool admit() {
         bool progress = false;
-        while (!pending_.empty() && (int32_t)active_.size() < cfg_.max_active) {
+        while (!pending_.empty() && counting() < cfg_.max_active) {
             Request &r = *pending_.front();
             if (!try_admit(r)) break;
             if (failed_) return true;
@@ -648,8 +655,8 @@ class Core {
     bool issue_tick() {
         if ((int32_t)ticks_.size() >= cfg_.ticks_in_flight) return false;
         std::vector<Request *> ready;   // in admission order: oldest first
-        for (Request *r : active_)
-            if (!r->cancel && r->state == State::Active && r->next_s < r->ready_s) ready.push_back(r);
+        for (Request *r : active_)   // (set-up done: C zeroed, offsets on the device)
+            if (!r->cancel && r->state == State::Active && !r->begin && r->next_s < r->ready_s) ready.push_back(r);
         if (ready.empty()) return false;
         // a floor share for every ready request; the spare points of the tick to the oldest first
         const int64_t n = (int64_t)ready.size();
@@ -691,8 +698,8 @@ class Core {
 
     bool issue_finals() {
         bool progress = false;
-        for (Request *r : active_) {
-            if (r->cancel || r->state != State::Active || r->next_s < r->S) continue;
+        for (Request *r : active_) {   // (after the set-up: a request without streamlines has no tick)
+            if (r->cancel || r->state != State::Active || r->begin || r->next_s < r->S) continue;
             const int rc = ex_->finalize(*r, &r->final);
             if (rc) {
                 fail(rc, "result copy could not be issued");

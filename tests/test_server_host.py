@@ -298,6 +298,23 @@ def test_tick_shares_many_requests(core):
     assert all(c.state(r)[:2] == (DONE, OK) for r in ids)
 
 
+def test_finalizing_request_makes_room(core):
+    # max_active bounds the requests still counting: one whose result is being copied out lets the
+    # next one in
+    c = core(tick_points=1000, chunk_points=100, max_active=1)
+    _, v = c.add_volume()
+    _, a = c.submit(v, [10] * 20, flags=DEVICE_POINTS)
+    _, b = c.submit(v, [10] * 20, flags=DEVICE_POINTS)
+    for _ in range(8):   # every operation completes except the result copies
+        c.step()
+        for kind in (BUILD, BEGIN, UPLOAD, TICK):
+            c.lib.sim_complete(c.h, kind)
+    assert c.state(a)[0] == FINALIZING
+    assert c.state(b)[0] in (ACTIVE, FINALIZING)
+    c.run()
+    assert c.state(a)[:2] == (DONE, OK) and c.state(b)[:2] == (DONE, OK)
+
+
 def test_tick_streamline_cap(core):
     c = core(tick_points=1 << 30, tick_streamlines=64, chunk_points=1000)
     _, v = c.add_volume()
