@@ -508,14 +508,16 @@ int plan_items(fastcod_plan &pl, const PlanSched &ps, int cus, hipStream_t st) {
 int plan_enqueue(fastcod_plan &pl, int cus, hipStream_t st) {
     const auto *subs = static_cast<const fc::StreamSubject *>(pl.d_subs.p);
     FC_HIP(fc::launch_zero_subjects(subs, static_cast<const int64_t *>(pl.d_sizes.p), pl.n, cus, st));
-    // overflow count and every kind's work-item queues
-    FC_HIP(fc::launch_fill_u64(pl.ovf.count, (int64_t)(fc::overflow_header_bytes(fc::kBatchedKinds) / 8), cus, st));
+    // overflow count and every kind's work-item queues: zeroed by the partition launch (by a fill
+    // when no subject has work items)
+    const int64_t header_words = (int64_t)(fc::overflow_header_bytes(fc::kBatchedKinds) / 8);
+    if (pl.nitems == 0) FC_HIP(fc::launch_fill_u64(pl.ovf.count, header_words, cus, st));
     const int32_t *kl = pl.kind_lo;
     const int ends = (int)fc::BatchedKind::kEnds, seed = (int)fc::BatchedKind::kSeedEnd;
     FC_HIP(fc::launch_end_labels_batched(subs, kl[ends], kl[ends + 1] - kl[ends], cus, st));
     if (pl.nitems > 0) {
         FC_HIP(fc::launch_partition_batched(subs, static_cast<const int64_t *>(pl.d_item_base.p), pl.n, pl.nitems,
-                                            static_cast<int2 *>(pl.d_items.p), cus, st));
+                                            static_cast<int2 *>(pl.d_items.p), pl.ovf.count, header_words, cus, st));
         const int2 *items = static_cast<const int2 *>(pl.d_items.p);
         for (int k = 0; k < seed; ++k) {
             fc::Overflow o = pl.ovf;

@@ -214,8 +214,9 @@ hipError_t launch_transpose_many(const TransposeJob *jobs, int32_t njobs, int64_
 
 // batched form
 hipError_t launch_zero_subjects(const StreamSubject *subs, const int64_t *sizes, int32_t nsub, int cus, hipStream_t st);
+// (also zeroes zero[0 .. nzero): the counting launches' overflow count and range queues)
 hipError_t launch_partition_batched(const StreamSubject *subs, const int64_t *item_base, int32_t nsub, int64_t nitems,
-                                    int2 *items, int cus, hipStream_t st);
+                                    int2 *items, unsigned long long *zero, int64_t nzero, int cus, hipStream_t st);
 // Kinds of subject of the batched form, each counted by its own launch (subjects of one kind are
 // neighbours in the descriptor table): pass-through, endpoint modes 1/2 (end labels first),
 // upsampled pass-through (u = 2, or u = 3..4), Alg. 1's seed-to-end count (no work items).

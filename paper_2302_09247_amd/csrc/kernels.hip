@@ -1960,11 +1960,14 @@ hipError_t launch_parcellate(const int32_t *C, int32_t N, int32_t M, int32_t *la
 
 // items[i] = (subject, first streamline of [s_begin, S) at or after point P0 + floor(j * (P - P0) / n_s))
 // for the j-th of the subject's n_s items (P0 = offsets[s_begin], P = offsets[S]); item_base[s] ..
-// item_base[s+1] are subject s's items.
+// item_base[s+1] are subject s's items.  The same launch zeroes zero[0 .. nzero) (the counting
+// launches' overflow count and range queues), which saves a launch of its own.
 __global__ void k_partition_batched(const StreamSubject *__restrict__ subs, const int64_t *__restrict__ item_base,
-                                    int32_t nsub, int2 *__restrict__ items) {
+                                    int32_t nsub, int2 *__restrict__ items, unsigned long long *__restrict__ zero,
+                                    int64_t nzero) {
     const int64_t n = item_base[nsub];
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nzero; i += stride) zero[i] = 0ull;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         int lo = 0, hi = nsub;   // subject: last s with item_base[s] <= i
         while (hi - lo > 1) {
@@ -2003,8 +2006,9 @@ hipError_t launch_zero_subjects(const StreamSubject *subs, const int64_t *sizes,
 }
 
 hipError_t launch_partition_batched(const StreamSubject *subs, const int64_t *item_base, int32_t nsub, int64_t nitems,
-                                    int2 *items, int cus, hipStream_t st) {
-    k_partition_batched<<<fill_blocks(nitems, cus), kBlock, 0, st>>>(subs, item_base, nsub, items);
+                                    int2 *items, unsigned long long *zero, int64_t nzero, int cus, hipStream_t st) {
+    k_partition_batched<<<fill_blocks(std::max<int64_t>(nitems, nzero), cus), kBlock, 0, st>>>(subs, item_base, nsub,
+                                                                                             items, zero, nzero);
     return hipGetLastError();
 }
 

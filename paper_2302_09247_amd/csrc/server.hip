@@ -49,12 +49,14 @@ class HipExecutor final : public fcs::Executor {
         FC_HIP(hipStreamCreateWithFlags(&copy_, hipStreamNonBlocking));
         FC_HIP(hipStreamCreateWithFlags(&out_, hipStreamNonBlocking));
         const int64_t nsub = cfg.max_active;
+        // the subject table and the item bases in one block (host and device alike): one upload a launch
+        desc_base_off_ = (sizeof(fc::StreamSubject) * (size_t)nsub + 255) & ~size_t(255);
+        const size_t desc_bytes = desc_base_off_ + 8 * (size_t)(nsub + 1);
         for (Slot &s : slots_) {
-            FC_HIP(hipHostMalloc(reinterpret_cast<void **>(&s.h_subs), sizeof(fc::StreamSubject) * nsub,
-                                 hipHostMallocDefault));
-            FC_HIP(hipHostMalloc(reinterpret_cast<void **>(&s.h_base), 8 * (nsub + 1), hipHostMallocDefault));
-            FC_HIP(s.d_subs.ensure(sizeof(fc::StreamSubject) * nsub, false));
-            FC_HIP(s.d_base.ensure(8 * (nsub + 1), false));
+            FC_HIP(hipHostMalloc(reinterpret_cast<void **>(&s.h_desc), desc_bytes, hipHostMallocDefault));
+            s.h_subs = reinterpret_cast<fc::StreamSubject *>(s.h_desc);
+            s.h_base = reinterpret_cast<int64_t *>(s.h_desc + desc_base_off_);
+            FC_HIP(s.d_desc.ensure(desc_bytes, false));
             FC_HIP(s.d_items.ensure(8 * (size_t)(items_full_ + nsub + 1), false));
             FC_HIP(hipEventCreateWithFlags(&s.last, hipEventDisableTiming));
             FC_HIP(hipEventRecord(s.last, comp_));
@@ -191,20 +193,20 @@ class HipExecutor final : public fcs::Executor {
         }
         const int64_t nitems = s.h_base[n];
         if (nitems + 1 > (int64_t)(s.d_items.n / 8)) return err(FASTCOD_EINVAL, "work item table overflow");
-        const auto *subs = static_cast<const fc::StreamSubject *>(s.d_subs.p);
+        const auto *subs = static_cast<const fc::StreamSubject *>(s.d_desc.p);
+        const auto *d_base = reinterpret_cast<const int64_t *>(static_cast<const char *>(s.d_desc.p) + desc_base_off_);
         const int2 *items = static_cast<const int2 *>(s.d_items.p);
-        if (hip(hipMemcpyAsync(s.d_subs.p, s.h_subs, sizeof(fc::StreamSubject) * n, hipMemcpyHostToDevice, comp_),
+        // the counters and range queues are reset by the partition launch (by a fill without items)
+        const int64_t header_words = (int64_t)(fc::overflow_header_bytes(fc::kBatchedKinds) / 8);
+        if (hip(hipMemcpyAsync(s.d_desc.p, s.h_desc, desc_base_off_ + 8 * (size_t)(n + 1), hipMemcpyHostToDevice, comp_),
                 "descriptor upload") ||
-            hip(hipMemcpyAsync(s.d_base.p, s.h_base, 8 * (size_t)(n + 1), hipMemcpyHostToDevice, comp_),
-                "descriptor upload") ||
-            hip(fc::launch_fill_u64(ovf_.count, (int64_t)(fc::overflow_header_bytes(fc::kBatchedKinds) / 8), cus_, comp_),
-                "counter reset") ||
+            (nitems == 0 && hip(fc::launch_fill_u64(ovf_.count, header_words, cus_, comp_), "counter reset")) ||
             hip(fc::launch_end_labels_batched(subs, kind_lo[ends], kind_lo[ends + 1] - kind_lo[ends], cus_, comp_),
                 "end labels"))
             return FASTCOD_EHIP;
         if (nitems > 0) {
-            if (hip(fc::launch_partition_batched(subs, static_cast<const int64_t *>(s.d_base.p), n, nitems,
-                                                 static_cast<int2 *>(s.d_items.p), cus_, comp_),
+            if (hip(fc::launch_partition_batched(subs, d_base, n, nitems, static_cast<int2 *>(s.d_items.p), ovf_.count,
+                                                 header_words, cus_, comp_),
                     "partition"))
                 return FASTCOD_EHIP;
             for (int k = 0; k < seed; ++k) {
@@ -257,9 +259,10 @@ class HipExecutor final : public fcs::Executor {
         hipEvent_t ev = nullptr, link = nullptr;
     };
     struct Slot {
+        char *h_desc = nullptr;                 // pinned: subject table, then (at desc_base_off_) item bases
         fc::StreamSubject *h_subs = nullptr;
         int64_t *h_base = nullptr;
-        DevBuf d_subs, d_base, d_items;
+        DevBuf d_desc, d_items;                 // d_desc: the same layout as h_desc
         hipEvent_t last = nullptr;
     };
 
@@ -329,14 +332,13 @@ class HipExecutor final : public fcs::Executor {
         }
         toks_.clear();
         for (Slot &s : slots_) {
-            if (s.h_subs) (void)hipHostFree(s.h_subs);
-            if (s.h_base) (void)hipHostFree(s.h_base);
+            if (s.h_desc) (void)hipHostFree(s.h_desc);
             if (s.last) (void)hipEventDestroy(s.last);
+            s.h_desc = nullptr;
             s.h_subs = nullptr;
             s.h_base = nullptr;
             s.last = nullptr;
-            s.d_subs.release();
-            s.d_base.release();
+            s.d_desc.release();
             s.d_items.release();
         }
         d_ovf_.release();
@@ -358,6 +360,7 @@ class HipExecutor final : public fcs::Executor {
     char *base_ = nullptr;
     hipStream_t comp_ = nullptr, copy_ = nullptr, out_ = nullptr;
     Slot slots_[kTickSlots];
+    size_t desc_base_off_ = 0;   // offset of the item bases in a slot's descriptor block
     uint64_t next_slot_ = 0;
     std::vector<TokenRec> toks_;
     std::vector<fcs::Token> free_toks_;
