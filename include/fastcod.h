@@ -311,15 +311,19 @@ int fastcod_server_add_volume(fastcod_server *srv, const int32_t *roi_index_vol_
  * submission.  The server's device work runs on streams of its own: for device-resident points
  * or C_out written by work still in flight on some stream, set FASTCOD_REQ_AFTER_STREAM and name
  * that stream -- an event recorded on it here orders every device access of the request after
- * that work (without the flag the caller must have completed that work before submitting).  The
- * offsets are checked here: ERANGE if offsets[0] != 0 or they decrease.  Errors: EINVAL, ERANGE,
- * ENOMEM (can never fit the budget), EBUSY (server shutting down), EHIP (the event could not be
- * recorded on request.stream), or the status that failed the server. */
+ * that work (without the flag the caller must have completed that work before submitting).
+ * Offsets: ERANGE here if offsets[0] != 0 or offsets[n_streamlines] < 0; that none decreases is
+ * checked on the device when the request is set up (after admission, before it is counted), and a
+ * request whose offsets decrease finishes with FASTCOD_ERANGE from fastcod_server_wait, C_out
+ * untouched.  Errors: EINVAL, ERANGE, ENOMEM (can never fit the budget), EBUSY (server shutting
+ * down), EHIP (the event could not be recorded on request.stream), or the status that failed the
+ * server. */
 int fastcod_server_submit(fastcod_server *srv, const fastcod_request *req, uint64_t *request_id);
 /* Waits up to timeout_us microseconds (< 0: no limit) for a request to finish.  Returns its
  * status (FASTCOD_OK: C_out holds the result) and fills *info (may be NULL); the request's record
- * is then dropped, so each id is waited for once.  FASTCOD_ETIMEDOUT: still running (not an error
- * of the request); FASTCOD_EINVAL: unknown id. */
+ * is then dropped, so each id is waited for once.  FASTCOD_ERANGE: its offsets decrease (C_out
+ * untouched).  FASTCOD_ETIMEDOUT: still running (not an error of the request); FASTCOD_EINVAL:
+ * unknown id. */
 int fastcod_server_wait(fastcod_server *srv, uint64_t request_id, int64_t timeout_us,
                         fastcod_request_info *info);
 /* Cancels a request.  A pending one finishes at once; an admitted one takes no further launches

@@ -11,6 +11,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <memory>
 #include <thread>
 #include <vector>
@@ -61,6 +62,11 @@ class HipExecutor final : public fcs::Executor {
             FC_HIP(hipEventCreateWithFlags(&s.last, hipEventDisableTiming));
             FC_HIP(hipEventRecord(s.last, comp_));
         }
+        // offsets-check flags: one per request being set up, and at most max_active are
+        const int nflags = 2 * cfg.max_active;
+        FC_HIP(d_flags_.ensure(4 * (size_t)nflags, false));
+        FC_HIP(hipHostMalloc(reinterpret_cast<void **>(&h_flags_), 4 * (size_t)nflags, hipHostMallocDefault));
+        for (int k = nflags - 1; k >= 0; --k) free_flags_.push_back(k);
         const size_t header = fc::overflow_header_bytes(fc::kBatchedKinds);
         FC_HIP(d_ovf_.ensure(header + 8 * (size_t)cfg.tick_streamlines, false));
         ovf_.count = static_cast<unsigned long long *>(d_ovf_.p);
@@ -114,19 +120,39 @@ class HipExecutor final : public fcs::Executor {
     // On the copy stream: the offsets (8 MB for a million streamlines) cross PCIe while the compute
     // stream keeps counting the requests before this one; the core counts this request only once
     // the token has completed.
+    // The offsets are checked on the device copy (nondecreasing); the flag comes back to a pinned
+    // slot that setup_status reads once the token has completed.
     int begin_request(const fcs::Request &r, fcs::Token *t) override {
         if (r.ready && (r.ready > toks_.size() ||
                         hip(hipStreamWaitEvent(copy_, toks_[r.ready - 1].ev, 0), "hipStreamWaitEvent")))
             return r.ready > toks_.size() ? err(FASTCOD_EINVAL, "unknown token") : FASTCOD_EHIP;
+        if (free_flags_.empty()) return err(FASTCOD_EBUSY, "no free set-up flag");
+        const int slot = free_flags_.back();
+        const auto *d_off = reinterpret_cast<const int64_t *>(base_ + r.off_offsets);
+        int32_t *d_flag = static_cast<int32_t *>(d_flags_.p) + slot;
         if (hip(fc::launch_fill_i32(device_C(r), (int64_t)r.N * r.M, 0, cus_, copy_), "zero fill") ||
             hip(hipMemcpyAsync(base_ + r.off_offsets, r.offsets, 8 * (size_t)(r.S + 1), hipMemcpyHostToDevice, copy_),
-                "offsets upload"))
+                "offsets upload") ||
+            hip(fc::launch_validate(d_off, r.S, nullptr, nullptr, 0, 1, 1, d_flag, cus_, copy_), "offsets check") ||
+            hip(hipMemcpyAsync(h_flags_ + slot, d_flag, 4, hipMemcpyDeviceToHost, copy_), "offsets check"))
             return FASTCOD_EHIP;
+        free_flags_.pop_back();
+        flag_of_[r.id] = slot;
         return record(copy_, t);
+    }
+    int setup_status(const fcs::Request &r) override {
+        auto it = flag_of_.find(r.id);
+        if (it == flag_of_.end()) return FASTCOD_OK;
+        const int32_t f = h_flags_[it->second];
+        free_flags_.push_back(it->second);
+        flag_of_.erase(it);
+        return f ? FASTCOD_ERANGE : FASTCOD_OK;
     }
 
     int upload(const fcs::Request &r, int64_t s0, int64_t s1, fcs::Token *t) override {
-        const int64_t p0 = r.offsets[s0], p1 = r.offsets[s1];
+        // (clamped to [0, P]: the offsets may not have been checked yet)
+        const int64_t p0 = std::min<int64_t>(std::max<int64_t>(r.offsets[s0], 0), r.P);
+        const int64_t p1 = std::min<int64_t>(std::max<int64_t>(r.offsets[s1], p0), r.P);
         if (p1 > p0 && hip(hipMemcpyAsync(base_ + r.off_points + 12 * p0, r.points + 3 * p0, 12 * (size_t)(p1 - p0),
                                           hipMemcpyHostToDevice, copy_),
                            "points upload"))
@@ -343,6 +369,11 @@ class HipExecutor final : public fcs::Executor {
         }
         d_ovf_.release();
         d_fb_.release();
+        d_flags_.release();
+        if (h_flags_) (void)hipHostFree(h_flags_);
+        h_flags_ = nullptr;
+        free_flags_.clear();
+        flag_of_.clear();
         if (base_) (void)hipFree(base_);
         base_ = nullptr;
         for (hipStream_t *st : {&comp_, &copy_, &out_})
@@ -360,6 +391,10 @@ class HipExecutor final : public fcs::Executor {
     char *base_ = nullptr;
     hipStream_t comp_ = nullptr, copy_ = nullptr, out_ = nullptr;
     Slot slots_[kTickSlots];
+    DevBuf d_flags_;                      // offsets-check flags of requests being set up
+    int32_t *h_flags_ = nullptr;          // (pinned mirror)
+    std::vector<int> free_flags_;
+    std::map<uint64_t, int> flag_of_;     // request id -> flag slot
     size_t desc_base_off_ = 0;   // offset of the item bases in a slot's descriptor block
     uint64_t next_slot_ = 0;
     std::vector<TokenRec> toks_;

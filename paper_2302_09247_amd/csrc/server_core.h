@@ -162,6 +162,7 @@ struct Request {
     State state = State::Pending;
     int status = FASTCOD_OK;
     bool cancel = false;
+    int cancel_status = FASTCOD_ECANCELED;          // FASTCOD_ERANGE: offsets found decreasing at set-up
     int64_t t_submit = 0, t_admit = 0, t_done = 0;
     int64_t off_C = -1, off_offsets = -1, off_points = -1;
     int64_t off_ends = -1;                           // end labels (endpoint modes): last[S] (and first[S])
@@ -195,9 +196,14 @@ class Executor {
         *t = 0;
         return FASTCOD_OK;
     }
-    // zero the request's C and upload its offsets (after r.ready); the request joins ticks only
-    // once the token has completed
+    // zero the request's C, upload its offsets and check them (after r.ready); the request joins
+    // ticks only once the token has completed and setup_status has accepted it
     virtual int begin_request(const Request &r, Token *t) = 0;
+    // once the set-up token has completed: FASTCOD_OK, or FASTCOD_ERANGE if the offsets decrease
+    virtual int setup_status(const Request &r) {
+        (void)r;
+        return FASTCOD_OK;
+    }
     // host points of streamlines [s0, s1) to the request's device copy
     virtual int upload(const Request &r, int64_t s0, int64_t s1, Token *t) = 0;
     // count every chunk (ordered after begin_request and the volume build)
@@ -292,12 +298,13 @@ class Core {
         if (up < 1 || up > 4) return set_err(err, FASTCOD_EINVAL, "upsample must be 0..4");
         if (up > 1 && q.mode != FASTCOD_MODE_PASSTHROUGH)
             return set_err(err, FASTCOD_EINVAL, "upsampling is available for the pass-through mode only");
-        // offsets (host): start at 0, nondecreasing
+        // offsets (host): the first and the last are checked here; that none decreases is checked on
+        // the device during the set-up (reading a million of them here would take the submitting
+        // thread about a millisecond)
         const int64_t S = q.n_streamlines;
         if (q.offsets[0] != 0) return set_err(err, FASTCOD_ERANGE, "offsets[0] must be 0");
-        for (int64_t s = 0; s < S; ++s)
-            if (q.offsets[s + 1] < q.offsets[s]) return set_err(err, FASTCOD_ERANGE, "offsets decrease");
         const int64_t P = q.offsets[S];
+        if (P < 0) return set_err(err, FASTCOD_ERANGE, "offsets decrease");
         if (P > 0 && !q.points) return set_err(err, FASTCOD_EINVAL, "points is NULL");
         if (P >= (int64_t(1) << 47)) return set_err(err, FASTCOD_EINVAL, "too many points");
         const uint64_t need = request_bytes(S, P, v->N, v->M, q.flags, q.mode) + Arena::round(v->bytes) +
@@ -482,8 +489,16 @@ class Core {
         for (Request *rp : act) {
             Request &r = *rp;
             if (r.begin) {
-                check(r.begin, "request set-up");
+                const int q = check(r.begin, "request set-up");
                 if (failed_) return true;
+                if (q) {   // set up: its offsets checked on the device
+                    const int st = ex_->setup_status(r);
+                    if (st != FASTCOD_OK && !r.cancel) {
+                        r.cancel = true;   // ends like a cancelled request, once its uploads are done
+                        r.cancel_status = st;
+                    }
+                    progress = true;
+                }
             }
             while (!r.uploads.empty()) {
                 Token t = r.uploads.front().first;
@@ -503,7 +518,7 @@ class Core {
                     progress = true;
                 }
             } else if (r.cancel && !r.begin && r.uploads.empty() && r.last_tick <= done_tick_) {
-                finish(r, FASTCOD_ECANCELED);
+                finish(r, r.cancel_status);
                 progress = true;
             }
         }

@@ -51,6 +51,12 @@ class SimExecutor final : public fcs::Executor {
         ops.push_back({kBegin, (int64_t)r.id, r.off_C, r.off_offsets, r.off_points});
         return FASTCOD_OK;
     }
+    // the device check of the set-up, done on the host copy: no offset may decrease
+    int setup_status(const fcs::Request &r) override {
+        for (int64_t s = 0; s < r.S; ++s)
+            if (r.offsets[s + 1] < r.offsets[s]) return FASTCOD_ERANGE;
+        return FASTCOD_OK;
+    }
     int upload(const fcs::Request &r, int64_t s0, int64_t s1, fcs::Token *t) override {
         if (int rc = issue(kUpload, t)) return rc;
         ops.push_back({kUpload, (int64_t)r.id, s0, s1, 0});

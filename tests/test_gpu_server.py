@@ -196,10 +196,21 @@ def test_submission_errors(fc, cases):
     v = srv.add_volume(c["w"].roi, c["w"].lab, c["w"].N, c["w"].M)
     out = torch.zeros((c["w"].N, c["w"].M), dtype=torch.int32)
     bad = c["w"].offsets.clone()
-    bad[2] = bad[1] - 1
-    with pytest.raises(fc.FastcodError) as e:
-        srv.submit(v, c["w"].points, bad, out)
+    bad[1] = 3
+    with pytest.raises(fc.FastcodError) as e:   # offsets[0] != 0: refused at submission
+        srv.submit(v, c["w"].points, bad + 1, out)
     assert e.value.status == fc.ERANGE
+    # a decrease inside is found by the device check of the set-up: the request ends with ERANGE,
+    # C_out untouched, and the server goes on serving
+    bad = c["w"].offsets.clone()
+    bad[2] = bad[1] - 1
+    out.fill_(-7)
+    rid = srv.submit(v, _pinned(c["w"].points), bad, out, scale=c["scale"])
+    assert srv.wait(rid)["status"] == fc.ERANGE
+    assert bool((out == -7).all())
+    good = torch.zeros_like(out)
+    assert srv.wait(srv.submit(v, _pinned(c["w"].points), c["w"].offsets, good, scale=c["scale"]))["status"] == 0
+    np.testing.assert_array_equal(good.numpy().astype(np.int64), c["expect"])
     with pytest.raises(fc.FastcodError) as e:
         srv.submit(v + 7, c["w"].points, c["w"].offsets, out)
     assert e.value.status == fc.EINVAL

@@ -496,8 +496,17 @@ def test_submit_checks(core):
     _, v = c.add_volume()
     assert c.submit(v + 5, [1, 2])[0] == EINVAL
     assert c.submit(v, offsets=[1, 2, 3])[0] == ERANGE
-    assert c.submit(v, offsets=[0, 5, 3])[0] == ERANGE
+    assert c.submit(v, offsets=[0, 5, 3, 2, -1])[0] == ERANGE   # offsets[S] < 0
     assert c.submit(v, [1], flags=8)[0] == EINVAL
+    # a decrease inside is found by the set-up's check: the request ends with ERANGE, never counted,
+    # and its host points are uploaded only within [0, P)
+    rc, bad = c.submit(v, offsets=[0, 5, 3, 9])
+    assert rc == OK
+    c.run()
+    assert c.state(bad)[:2] == (DONE, ERANGE)
+    assert not any(o[0] == FINAL and o[1] == bad for o in c.ops())
+    ch = c.chunks()
+    assert len(ch) == 0 or bad not in ch[:, 1]
     rc, rid = c.submit(v, offsets=[0])
     assert rc == OK
     c.run()
