@@ -51,7 +51,7 @@ def test_capacities_random_small(fc, seed):
         np.testing.assert_array_equal(_run(fc, g, pair_capacity=cap), exp, err_msg=f"capacity {cap}")
 
 
-@pytest.mark.parametrize("cap", [1, 5000])
+@pytest.mark.parametrize("cap", [1, 5000, 0])   # (0: no pair buffer for this small call)
 def test_accumulate_with_small_slices(fc, cap):
     w = synth.make_tiny64(seed=12, S=8000)
     exp = oracle.count(w.points, w.offsets, w.roi, w.lab, w.N, w.M)
